@@ -1,0 +1,232 @@
+"""Gamma matrices, lattice geometry and the twisted-mass Wilson operator (FP64).
+
+Conventions (the paper names the twisted-mass operator, Section 2.1.1, but
+prints neither its form nor a gamma basis; these are the readings taken):
+
+* Fields are full-lattice numpy arrays.  Spinor: ``[..., T, Z, Y, X, 4, 3]``
+  (spin, colour); gauge: ``[T, Z, Y, X, 4, 3, 3]`` with ``mu = 0..3`` for
+  x, y, z, t.  Leading axes (``...``) are batch axes.
+* Euclidean chiral basis: ``gamma_k = [[0, -i sigma_k], [i sigma_k, 0]]``
+  (k = 1, 2, 3), ``gamma_4 = [[0, 1], [1, 0]]``, ``gamma_5 = g1 g2 g3 g4 =
+  diag(1, 1, -1, -1)``.
+* Hopping term ``(H psi)(x) = sum_mu (1 - gamma_mu) U_mu(x) psi(x + mu)
+  + (1 + gamma_mu) U_mu(x - mu)^dag psi(x - mu)``; periodic in space, a hop
+  that crosses the time boundary picks up ``bc_t`` (-1: antiperiodic).
+* kappa-normalised twisted-mass operator of the u flavour
+  ``M(mu) = 1 - kappa H + 2 i kappa mu gamma_5``; the d flavour is ``M(-mu)``.
+  In physical normalisation ``M / (2 kappa) = D_W + i mu gamma_5``.
+* Even-odd split by the parity ``(x + y + z + t) mod 2``; even-odd fields are
+  full arrays that vanish on the other parity.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# lattice axis of direction mu in a [..., T, Z, Y, X, 4, 3] spinor
+SPINOR_AXIS = {0: -3, 1: -4, 2: -5, 3: -6}
+
+
+def gamma_matrices():
+    """Return (gamma_1..gamma_4 as [4, 4, 4], gamma_5) in the chiral basis."""
+    s = [np.array([[0, 1], [1, 0]], dtype=complex),
+         np.array([[0, -1j], [1j, 0]], dtype=complex),
+         np.array([[1, 0], [0, -1]], dtype=complex)]
+    z = np.zeros((2, 2), dtype=complex)
+    one = np.eye(2, dtype=complex)
+    g = [np.block([[z, -1j * sk], [1j * sk, z]]) for sk in s]
+    g.append(np.block([[z, one], [one, z]]))
+    g = np.array(g)
+    g5 = g[0] @ g[1] @ g[2] @ g[3]
+    return g, g5
+
+
+GAMMA, GAMMA5 = gamma_matrices()
+
+
+def gamma_basis():
+    """The 16 insertions ``Gamma_n = g1^n0 g2^n1 g3^n2 g4^n3`` (n0 = lowest bit).
+
+    Section 2.2 only says any Gamma can be rebuilt from the 4x4 outer product;
+    this bit-indexed ordering of the Clifford basis is the reading used for the
+    output index.  ``Gamma_15 = gamma_5``.
+    """
+    out = np.zeros((16, 4, 4), dtype=complex)
+    for n in range(16):
+        m = np.eye(4, dtype=complex)
+        for k in range(4):
+            if (n >> k) & 1:
+                m = m @ GAMMA[k]
+        out[n] = m
+    return out
+
+
+GAMMA_BASIS = gamma_basis()
+
+
+def lattice_shape(dims):
+    X, Y, Z, T = dims
+    return (T, Z, Y, X)
+
+
+def parity(dims) -> np.ndarray:
+    """Site parity (x + y + z + t) mod 2 as an int array [T, Z, Y, X]."""
+    X, Y, Z, T = dims
+    t, z, y, x = np.meshgrid(np.arange(T), np.arange(Z), np.arange(Y), np.arange(X),
+                             indexing="ij")
+    return (x + y + z + t) % 2
+
+
+def shift_forward(f, mu, bc_t, lat_axis):
+    """f(x + mu): roll by one site, boundary factor on hops across t = T-1 -> 0."""
+    g = np.roll(f, -1, axis=lat_axis)
+    if mu == 3 and bc_t != 1:
+        idx = [slice(None)] * g.ndim
+        idx[lat_axis] = -1
+        g[tuple(idx)] *= bc_t
+    return g
+
+
+def shift_backward(f, mu, bc_t, lat_axis):
+    """f(x - mu): roll by one site, boundary factor on hops across t = 0 -> T-1."""
+    g = np.roll(f, 1, axis=lat_axis)
+    if mu == 3 and bc_t != 1:
+        idx = [slice(None)] * g.ndim
+        idx[lat_axis] = 0
+        g[tuple(idx)] *= bc_t
+    return g
+
+
+def color_mul(u, psi):
+    """(U psi)_a = sum_b U_ab psi_b per site and spin; u [..., 3, 3], psi [..., 4, 3]."""
+    return np.einsum("...ab,...sb->...sa", u, psi)
+
+
+def color_mul_dag(u, psi):
+    """(U^dag psi)_a = sum_b conj(U_ba) psi_b."""
+    return np.einsum("...ba,...sb->...sa", u.conj(), psi)
+
+
+def spin_mul(g, psi):
+    """(G psi)_s = sum_r G_sr psi_r for a 4x4 spin matrix."""
+    return np.einsum("sr,...rc->...sc", g, psi)
+
+
+def hop(U, psi, bc_t, dagger=False):
+    """Wilson hopping term H psi (or its adjoint H^dag psi).
+
+    The adjoint swaps the spin projectors: forward hops carry (1 + gamma_mu),
+    backward hops (1 - gamma_mu).
+    """
+    one = np.eye(4, dtype=complex)
+    out = np.zeros_like(psi, dtype=complex)
+    for mu in range(4):
+        ax = SPINOR_AXIS[mu]
+        pf = one + GAMMA[mu] if dagger else one - GAMMA[mu]
+        pb = one - GAMMA[mu] if dagger else one + GAMMA[mu]
+        fwd = color_mul(U[..., mu, :, :], shift_forward(psi, mu, bc_t, ax))
+        bwd = shift_backward(color_mul_dag(U[..., mu, :, :], psi), mu, bc_t, ax)
+        out += spin_mul(pf, fwd) + spin_mul(pb, bwd)
+    return out
+
+
+def twist_diag(kappa, mu):
+    """Per-spin diagonal of A = 1 + 2 i kappa mu gamma_5 (gamma_5 is diagonal here)."""
+    return 1.0 + 2j * kappa * mu * np.real(np.diag(GAMMA5))
+
+
+def apply_spin_diag(d, psi):
+    return psi * d[:, None]
+
+
+def apply_M(U, psi, kappa, mu, bc_t):
+    """M(mu) psi = psi - kappa H psi + 2 i kappa mu gamma_5 psi."""
+    return psi - kappa * hop(U, psi, bc_t) + 2j * kappa * mu * spin_mul(GAMMA5, psi)
+
+
+def apply_Mdag(U, psi, kappa, mu, bc_t):
+    """M(mu)^dag psi = psi - kappa H^dag psi - 2 i kappa mu gamma_5 psi."""
+    return psi - kappa * hop(U, psi, bc_t, dagger=True) - 2j * kappa * mu * spin_mul(GAMMA5, psi)
+
+
+def apply_M0(U, psi, kappa, bc_t):
+    """The mu-independent part M_0 = 1 - kappa H (= 2 kappa D_W)."""
+    return psi - kappa * hop(U, psi, bc_t)
+
+
+# ---------------------------------------------------------------------------
+# even-odd (Schur complement on odd sites)
+# ---------------------------------------------------------------------------
+
+def parity_mask(dims, p):
+    """[T, Z, Y, X, 1, 1] mask selecting parity p."""
+    return (parity(dims) == p).astype(float)[..., None, None]
+
+
+def project(psi, mask):
+    return psi * mask
+
+
+def Mhat(U, psi_o, kappa, mu, bc_t, dims):
+    """Schur complement on odd sites: 1 - kappa^2 A_o^-1 H_oe A_e^-1 H_eo.
+
+    With M = [[A_e, -kappa H_eo], [-kappa H_oe, A_o]] (even block first), the
+    odd-site equation after eliminating the even sites is
+    A_o^-1 (A_o - kappa^2 H_oe A_e^-1 H_eo) s_o = A_o^-1 (eta_o + kappa H_oe A_e^-1 eta_e).
+    """
+    me, mo = parity_mask(dims, 0), parity_mask(dims, 1)
+    ainv = 1.0 / twist_diag(kappa, mu)
+    u = apply_spin_diag(ainv, me * hop(U, mo * psi_o, bc_t))
+    w = apply_spin_diag(ainv, mo * hop(U, me * u, bc_t))
+    return mo * psi_o - kappa ** 2 * w
+
+
+def Mhat_dag(U, psi_o, kappa, mu, bc_t, dims):
+    """Adjoint of ``Mhat``: 1 - kappa^2 H_eo^dag A_e^-dag H_oe^dag A_o^-dag.
+
+    (H_eo)^dag = P_o H^dag P_e and (H_oe)^dag = P_e H^dag P_o, with P_p the
+    parity projectors; A^-dag = (1 - 2 i kappa mu gamma_5)^-1.
+    """
+    me, mo = parity_mask(dims, 0), parity_mask(dims, 1)
+    ainv_dag = 1.0 / np.conj(twist_diag(kappa, mu))
+    v = apply_spin_diag(ainv_dag, mo * psi_o)
+    u = apply_spin_diag(ainv_dag, me * hop(U, v, bc_t, dagger=True))
+    w = mo * hop(U, me * u, bc_t, dagger=True)
+    return mo * psi_o - kappa ** 2 * w
+
+
+def schur_rhs(U, eta, kappa, mu, bc_t, dims):
+    """bhat = A_o^-1 (eta_o + kappa H_oe A_e^-1 eta_e), an odd-site field."""
+    me, mo = parity_mask(dims, 0), parity_mask(dims, 1)
+    ainv = 1.0 / twist_diag(kappa, mu)
+    ue = apply_spin_diag(ainv, me * eta)
+    return apply_spin_diag(ainv, mo * eta + kappa * mo * hop(U, ue, bc_t))
+
+
+def reconstruct_even(U, eta, s_o, kappa, mu, bc_t, dims):
+    """Full solution from the odd half: s_e = A_e^-1 (eta_e + kappa H_eo s_o)."""
+    me, mo = parity_mask(dims, 0), parity_mask(dims, 1)
+    ainv = 1.0 / twist_diag(kappa, mu)
+    s_e = apply_spin_diag(ainv, me * eta + kappa * me * hop(U, mo * s_o, bc_t))
+    return s_e + mo * s_o
+
+
+# ---------------------------------------------------------------------------
+# dense matrices (tiny lattices only)
+# ---------------------------------------------------------------------------
+
+def dense(op, dims, batch=64):
+    """Dense matrix of a linear map on full-lattice spinors, index (site, spin, colour)."""
+    X, Y, Z, T = dims
+    n = X * Y * Z * T * 12
+    mat = np.empty((n, n), dtype=complex)
+    for c0 in range(0, n, batch):
+        nb = min(batch, n - c0)
+        e = np.zeros((nb, n), dtype=complex)
+        e[np.arange(nb), c0 + np.arange(nb)] = 1
+        cols = op(e.reshape((nb, T, Z, Y, X, 4, 3)))
+        mat[:, c0:c0 + nb] = cols.reshape(nb, n).T
+    return mat
+
+
+def dense_M(U, kappa, mu, bc_t, dims):
+    return dense(lambda p: apply_M(U, p, kappa, mu, bc_t), dims)

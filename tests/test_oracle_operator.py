@@ -1,0 +1,164 @@
+"""Pins of the oracle's gamma basis, operator and even-odd solver (CPU only)."""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import dirac, solver
+
+DIMS = (4, 4, 4, 4)
+
+
+def rel(a, b):
+    return np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300)
+
+
+def test_clifford_algebra_and_hermiticity():
+    g, g5 = dirac.GAMMA, dirac.GAMMA5
+    for m in range(4):
+        assert np.allclose(g[m], g[m].conj().T)
+        for n in range(4):
+            assert np.allclose(g[m] @ g[n] + g[n] @ g[m], 2 * np.eye(4) * (m == n))
+        assert np.allclose(g5 @ g[m] + g[m] @ g5, 0)
+    assert np.allclose(g5, np.diag([1, 1, -1, -1]))
+
+
+def test_gamma_basis_is_orthogonal_clifford_basis():
+    G = dirac.GAMMA_BASIS
+    gram = np.einsum("mab,nab->mn", G.conj(), G)      # tr(G_m^dag G_n)
+    assert np.allclose(gram, 4 * np.eye(16))
+    assert np.allclose(G[0], np.eye(4))
+    assert np.allclose(G[15], dirac.GAMMA5)
+    for n in range(16):                                # one unit-modulus entry per row
+        nz = np.abs(G[n]) > 1e-12
+        assert (nz.sum(axis=1) == 1).all()
+        assert np.allclose(np.abs(G[n][nz]), 1)
+
+
+@pytest.mark.parametrize("bc_t", [-1, 1])
+def test_free_field_plane_wave(bc_t):
+    """U = 1: M e^{ipx} u = e^{ipx} M(p) u with the closed-form momentum-space matrix."""
+    dims = (4, 6, 2, 8)
+    X, Y, Z, T = dims
+    kappa, mu = 0.13, 0.07
+    U = synth.unit_gauge(dims)
+    rng = np.random.default_rng(3)
+    u = rng.standard_normal((4, 3)) + 1j * rng.standard_normal((4, 3))
+    n = (1, 2, 1, 3)
+    shift = 0.5 if bc_t == -1 else 0.0
+    p = [2 * np.pi * n[0] / X, 2 * np.pi * n[1] / Y, 2 * np.pi * n[2] / Z,
+         2 * np.pi * (n[3] + shift) / T]
+    t, z, y, x = np.meshgrid(*[np.arange(L) for L in (T, Z, Y, X)], indexing="ij")
+    phase = np.exp(1j * (p[0] * x + p[1] * y + p[2] * z + p[3] * t))
+    psi = phase[..., None, None] * u
+    mp = ((1 - 2 * kappa * sum(np.cos(q) for q in p)) * np.eye(4)
+          + 2j * kappa * sum(dirac.GAMMA[m] * np.sin(p[m]) for m in range(4))
+          + 2j * kappa * mu * dirac.GAMMA5)
+    want = phase[..., None, None] * (mp @ u)
+    got = dirac.apply_M(U, psi, kappa, mu, bc_t)
+    assert rel(got, want) < 1e-13
+
+
+def test_hopping_adjoint_and_gamma5_hermiticity():
+    U = synth.random_gauge(DIMS, 11, 0.3)
+    a = synth.random_spinor(DIMS, 1)
+    b = synth.random_spinor(DIMS, 2)
+    k, mu = 0.16, 0.05
+    # <a, H b> = <H^dag a, b>
+    lhs = np.vdot(a, dirac.hop(U, b, -1))
+    rhs = np.vdot(dirac.hop(U, a, -1, dagger=True), b)
+    assert abs(lhs - rhs) < 1e-11 * abs(lhs)
+    # H^dag = gamma_5 H gamma_5
+    g5 = dirac.GAMMA5
+    h5 = dirac.spin_mul(g5, dirac.hop(U, dirac.spin_mul(g5, b), -1))
+    assert rel(dirac.hop(U, b, -1, dagger=True), h5) < 1e-14
+    # M(mu)^dag = gamma_5 M(-mu) gamma_5
+    m5 = dirac.spin_mul(g5, dirac.apply_M(U, dirac.spin_mul(g5, b), k, -mu, -1))
+    assert rel(dirac.apply_Mdag(U, b, k, mu, -1), m5) < 1e-14
+    assert abs(np.vdot(a, dirac.apply_M(U, b, k, mu, -1))
+               - np.vdot(dirac.apply_Mdag(U, a, k, mu, -1), b)) < 1e-11 * np.linalg.norm(a) ** 2
+
+
+def test_dense_gamma5_hermiticity_small():
+    dims = (2, 4, 2, 4)
+    U = synth.random_gauge(dims, 5, 0.4)
+    m = dirac.dense_M(U, 0.15, 0.03, -1, dims)
+    md = dirac.dense_M(U, 0.15, -0.03, -1, dims)
+    V = 2 * 4 * 2 * 4
+    g5 = np.kron(np.eye(V), np.kron(dirac.GAMMA5, np.eye(3)))
+    assert np.abs(m.conj().T - g5 @ md @ g5).max() < 1e-15
+
+
+def test_gauge_covariance():
+    """M[U^Omega] (Omega psi) = Omega M[U] psi, U^Omega_mu(x) = Omega(x) U_mu(x) Omega(x+mu)^dag."""
+    U = synth.random_gauge(DIMS, 21, 0.3)
+    om = synth.random_su3_field(DIMS, 22)
+    Ug = np.empty_like(U)
+    for mu in range(4):
+        om_fwd = np.roll(om, -1, axis=3 - mu)    # Omega(x + mu); om is [T, Z, Y, X, 3, 3]
+        Ug[..., mu, :, :] = om @ U[..., mu, :, :] @ np.swapaxes(om_fwd.conj(), -1, -2)
+    psi = synth.random_spinor(DIMS, 4)
+    opsi = dirac.color_mul(om, psi)
+    lhs = dirac.apply_M(Ug, opsi, 0.16, 0.05, -1)
+    rhs = dirac.color_mul(om, dirac.apply_M(U, psi, 0.16, 0.05, -1))
+    assert rel(lhs, rhs) < 1e-13
+
+
+def test_link_generator_is_special_unitary():
+    U = synth.random_gauge((4, 4, 4, 4), 1401, 0.3)
+    uu = U @ np.swapaxes(U.conj(), -1, -2)
+    assert np.abs(uu - np.eye(3)).max() < 1e-14
+    assert np.abs(np.linalg.det(U) - 1).max() < 1e-14
+    # loose check that the eigenphase spread matches eps = 0.3
+    ang = np.angle(np.linalg.eigvals(U)).ravel()
+    assert 0.1 < ang.std() < 0.5
+
+
+@pytest.mark.parametrize("mu", [0.05, -0.02])
+def test_schur_solve_matches_dense(mu):
+    dims = (4, 4, 2, 4)
+    U = synth.random_gauge(dims, 31, 0.3)
+    kappa = 0.16
+    eta = synth.random_spinor(dims, 9)
+    exact = solver.dense_solve(U, eta, kappa, mu, -1, dims)
+    s, info = solver.cgnr_eo(U, eta, kappa, mu, -1, dims, tol=1e-13)
+    assert info["converged"]
+    assert rel(s, exact) < 1e-11
+    assert solver.true_residual(U, eta, s, kappa, mu, -1) < 1e-11
+    # the Schur complement applied to the exact odd solution gives bhat
+    mo = dirac.parity_mask(dims, 1)
+    bhat = dirac.schur_rhs(U, eta, kappa, mu, -1, dims)
+    assert rel(dirac.Mhat(U, mo * exact, kappa, mu, -1, dims), bhat) < 1e-13
+    # the even half of the exact solution is what the reconstruction gives
+    assert rel(dirac.reconstruct_even(U, eta, mo * exact, kappa, mu, -1, dims), exact) < 1e-13
+
+
+def test_mhat_dag_is_adjoint():
+    U = synth.random_gauge(DIMS, 41, 0.3)
+    mo = dirac.parity_mask(DIMS, 1)
+    a = mo * synth.random_spinor(DIMS, 1)
+    b = mo * synth.random_spinor(DIMS, 2)
+    lhs = np.vdot(a, dirac.Mhat(U, b, 0.16, 0.01, -1, DIMS))
+    rhs = np.vdot(dirac.Mhat_dag(U, a, 0.16, 0.01, -1, DIMS), b)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_cg_residual_definition_and_stop():
+    """The stop rule is on the iterated normal-equation residual; check it independently."""
+    U = synth.random_gauge(DIMS, 51, 0.3)
+    eta = synth.random_spinor(DIMS, 7)
+    k, mu = 0.16, 0.01
+    for tol in (1e-2, 1e-8):
+        s, info = solver.cgnr_eo(U, eta, k, mu, -1, DIMS, tol=tol)
+        mo = dirac.parity_mask(DIMS, 1)
+        bhat = dirac.schur_rhs(U, eta, k, mu, -1, DIMS)
+        c = dirac.Mhat_dag(U, bhat, k, mu, -1, DIMS)
+        so = mo * s
+        true_normal = c - dirac.Mhat_dag(U, dirac.Mhat(U, so, k, mu, -1, DIMS), k, mu, -1, DIMS)
+        tr = np.linalg.norm(true_normal) / np.linalg.norm(c)
+        assert info["rel_resid"] <= tol
+        assert tr < 10 * tol                       # recursion residual tracks the true one
+        # one iteration fewer would not have met the target
+        _, info2 = solver.cgnr_eo(U, eta, k, mu, -1, DIMS, tol=tol, maxiter=info["iters"] - 1)
+        assert not info2["converged"]
