@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Benchmark of the truncated-solver-method fermion-loop pipeline on one MI355X.
+
+One step = the whole hot path on one synthetic gauge field: N_LP
+low-precision Z4 solves (bf16 storage, FP32 arithmetic, rho = 1e-2), N_HP
+high-precision solves (FP32 with FP64 reliable updates, rho = 1e-8), the
+low-precision solves of the same N_HP sources, one-end-trick contractions of
+all 160 local and one-derivative insertions accumulated in FP64 on the GPU,
+and the momentum projection (p^2 <= 4) with the TSM combination.  Inputs are
+resident on the GPU before timing starts; the loops stay in device memory.
+
+Prints one JSON line ("Measurement").
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "TSM LP solves/s + dslash HBM GB/s at rho=1e-2/1e-8 vs plain FP64 GPU path"
+HBM_PEAK_GBS = 8000.0
+COUNTERS = os.path.join(ROOT, "profiles", "dslash_bf16_24x24x24x48_counters.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1401_6750_amd", "csrc", f) for f in ("dslash.hip", "common.h")]
+
+WORKLOADS = {
+    # lattice name -> TSM sizes
+    "batched_24x24x24x48": dict(n_lp=1000, n_hp=50, p2max=4, noise="Z4"),
+    "tsm_16x16x16x32": dict(n_lp=200, n_hp=10, p2max=4, noise="Z2"),
+}
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="batched_24x24x24x48", choices=sorted(WORKLOADS))
+    ap.add_argument("--rhs-block", type=int, default=0)
+    ap.add_argument("--inflight-mb", type=float, default=65536.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-comparator", action="store_true")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="run only the profiled LP pass (for rocprofv3 counter runs)")
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; the per-GPU share of a multi-GPU run is the "
+              "N=1 workload (sources shard across GPUs with one final reduction, see DESIGN.md)",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1401_6750_amd as dl
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = synth.WORKLOADS[a.workload]
+    tw = WORKLOADS[a.workload]
+    dims, kappa, mu = w["dims"], w["kappa"], w["mu"]
+    X, Y, Z, T = dims
+    noise_kind = dl.DL_NOISE_Z4 if tw["noise"] == "Z4" else dl.DL_NOISE_Z2
+    n_lp, n_hp, p2 = tw["n_lp"], tw["n_hp"], tw["p2max"]
+
+    log(f"setup: {a.workload} gauge field")
+    U = synth.random_gauge(dims, w["gauge_seed"], w["eps"])
+    U_dev = torch.from_numpy(np.ascontiguousarray(U)).to("cuda")
+    stream = torch.cuda.current_stream()
+    ctx = dl.dl_create(0, stream.cuda_stream)
+    dl.dl_set_option(ctx, "inflight_mb", a.inflight_mb)
+    lat = dl.dl_lattice_create(ctx, dims, -1)
+    dl.dl_gauge_set(lat, U_dev, 1)
+    dl.dl_set_params(lat, kappa, mu)
+    acc = dl.dl_accum_create(lat, dl.DL_OPS_LOCAL | dl.DL_OPS_DERIV)
+    nmom = len(dl.dl_momenta(dims, p2))
+    out = torch.zeros((2, 5, 16, T, nmom), dtype=torch.complex128, device="cuda")
+    seed = w["source_seed"]
+
+    def jobs():
+        return [
+            dl.make_job(lat, noise=noise_kind, tier=dl.DL_TIER_LP_BF16, seed=seed, first_src=0, nsrc=n_lp,
+                        tol=1e-2, maxiter=500, rhs_block=a.rhs_block, accum=acc, accum_set=dl.DL_SET_LP),
+            dl.make_job(lat, noise=noise_kind, tier=dl.DL_TIER_HP_FP32, seed=seed, first_src=n_lp, nsrc=n_hp,
+                        tol=1e-8, maxiter=2000, rhs_block=a.rhs_block, accum=acc, accum_set=dl.DL_SET_HP),
+            dl.make_job(lat, noise=noise_kind, tier=dl.DL_TIER_LP_BF16, seed=seed, first_src=n_lp, nsrc=n_hp,
+                        tol=1e-2, maxiter=500, rhs_block=a.rhs_block, accum=acc, accum_set=dl.DL_SET_LPC),
+        ]
+
+    def step():
+        dl.dl_accum_reset(acc)
+        rc, st = dl.dl_solve_batch(ctx, jobs())
+        dl.dl_loops(ctx, acc, p2, out, 1)
+        return rc, st
+
+    if a.profile_only:
+        dl.dl_set_option(ctx, "profile", 1)
+        step()
+        torch.cuda.synchronize()
+        pr = dl.dl_profile_read(ctx, dl.DL_TIER_LP_BF16)
+        log(f"profile: {pr}")
+        return 0
+
+    for i in range(a.warmup):
+        log(f"warmup step {i}")
+        rc, st = step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        rc, st = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / a.steps
+    log(f"timed {a.steps} steps: {ms:.1f} ms/step")
+    assert rc == dl.DL_OK, f"solve status {rc}"
+    it_lp = [s.iters for s in st[:n_lp]]
+    it_hp = [s.iters for s in st[n_lp:n_lp + n_hp]]
+    ru_hp = [s.reliable_updates for s in st[n_lp:n_lp + n_hp]]
+
+    # ---- roofline of the hopping kernel, timed live with HIP events -----------
+    dl.dl_set_option(ctx, "profile", 1)
+    step()
+    torch.cuda.synchronize()
+    dl.dl_set_option(ctx, "profile", 0)
+    launches, kms, kbytes, krhs = dl.dl_profile_read(ctx, dl.DL_TIER_LP_BF16)
+    achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
+    traffic = None
+    if os.path.exists(COUNTERS):
+        c = json.load(open(COUNTERS))
+        if c.get("kernel_hash") == kernel_hash() and c.get("workload") == a.workload:
+            traffic = c.get("hbm_bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_dslash<bf16s, 0> (u_e = A^-1 H_eo p_o, LP tier)",
+                "launches": int(launches), "avg_launch_us": round(kms * 1e3 / max(launches, 1), 2),
+                "alg_bytes_per_launch": round(kbytes / max(launches, 1)),
+                "avg_active_rhs": round(krhs / max(launches, 1), 1)}
+
+    # ---- per-tier breakdown and the plain FP64 comparator (untimed in value) --
+    extra = {}
+    if not a.no_comparator:
+        def timed(job_list, reps=1):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(reps):
+                dl.dl_solve_batch(ctx, job_list)
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t) / reps
+
+        t_lp = timed([dl.make_job(lat, noise=noise_kind, tier=dl.DL_TIER_LP_BF16, seed=seed, nsrc=n_lp, tol=1e-2,
+                                  maxiter=500, rhs_block=a.rhs_block)])
+        t_hp = timed([dl.make_job(lat, noise=noise_kind, tier=dl.DL_TIER_HP_FP32, seed=seed, first_src=n_lp,
+                                  nsrc=n_hp, tol=1e-8, maxiter=2000, rhs_block=a.rhs_block)])
+        n_cmp = 4
+        dl.dl_set_option(ctx, "inflight_rhs", 1)
+        dl.dl_set_option(ctx, "use_graph", 0)
+        t_64 = timed([dl.make_job(lat, noise=noise_kind, tier=dl.DL_TIER_FP64, seed=seed, first_src=n_lp, nsrc=n_cmp,
+                                  tol=1e-8, maxiter=2000, rhs_block=1)])
+        dl.dl_set_option(ctx, "inflight_rhs", 1024)
+        dl.dl_set_option(ctx, "use_graph", 1)
+        extra = {
+            "lp_solves_per_s_solve_only": round(n_lp / t_lp, 2),
+            "hp_solves_per_s": round(n_hp / t_hp, 2),
+            "fp64_plain_single_rhs_solves_per_s_rho1e-8": round(n_cmp / t_64, 3),
+            "lp_vs_fp64_plain": round((n_lp / t_lp) / (n_cmp / t_64), 1),
+            "hp_vs_fp64_plain": round((n_hp / t_hp) / (n_cmp / t_64), 2),
+        }
+
+    # ---- CPU baseline: the FP64 oracle on a bounded sample ---------------------
+    cpu = None
+    if not a.no_cpu_baseline:
+        from oracle import dirac, noise as onoise
+        eta = onoise.source(dims, seed, 0, onoise.Z4 if noise_kind == dl.DL_NOISE_Z4 else onoise.Z2)
+        mo = dirac.parity_mask(dims, 1)
+        t = time.perf_counter()
+        dirac.Mhat(U, mo * eta, kappa, mu, -1, dims)
+        t_mhat = time.perf_counter() - t
+        mean_it = float(np.mean(it_lp))
+        n_ops = 2 * mean_it + 3          # Mhat and Mhat^dag per iteration, rhs setup and reconstruction
+        t_solve = t_mhat * n_ops
+        cpu = {"value": round(1.0 / t_solve, 6), "unit": "LP solves/s", "cores": 1, "kind": "oracle",
+               "sample": f"one oracle Schur-operator application on the {a.workload} lattice "
+                         f"({t_mhat:.1f} s, numpy FP64, 1 thread), scaled by {n_ops:.1f} operator "
+                         f"applications per LP solve (mean LP iterations {mean_it:.1f})"}
+
+    res = {
+        "metric": METRIC, "value": round(n_lp / (ms * 1e-3), 2), "unit": "LP solves/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": a.workload, "lattice": "x".join(map(str, dims)), "n_lp": n_lp, "n_hp": n_hp,
+                   "n_lpc": n_hp, "lp_storage": "bf16", "hp": "fp32+fp64 reliable updates",
+                   "noise": tw["noise"], "p2max": p2, "insertions": 160, "rhs_block": a.rhs_block or "auto"},
+        "iters_lp_mean": round(float(np.mean(it_lp)), 2), "iters_hp_mean": round(float(np.mean(it_hp)), 2),
+        "reliable_updates_hp_mean": round(float(np.mean(ru_hp)), 2),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    res.update(extra)
+    print(json.dumps(res), flush=True)
+    dl.dl_accum_destroy(acc)
+    dl.dl_lattice_destroy(lat)
+    dl.dl_destroy(ctx)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,237 @@
+/*
+ * discloop.h -- C ABI of the MI355X (gfx950) stochastic fermion-loop library.
+ *
+ * The library computes disconnected fermion loops of twisted-mass Wilson
+ * fermions the way the paper "A QUDA-branch to compute disconnected diagrams
+ * in GPUs" (LATTICE 2013) describes them:
+ *   - many stochastic inversions M s_r = eta_r (Section 2, eq. (1)) with
+ *     volume noise generated on the GPU (Section 2.3 draws it on the host;
+ *     Section 2.4 names that as a bottleneck and plans GPU generation);
+ *   - the truncated solver method (Section 2.1): many low-precision solves
+ *     plus a few high-precision corrections;
+ *   - one-end-trick contractions for all ultra-local and one-derivative
+ *     insertions, with and without tau_3 (Section 2.1.1, Section 2.2),
+ *     accumulated over sources on the GPU (the all-GPU scheme of Section 2.4,
+ *     Fig. 4) and projected to momenta with a p^2 cut (Section 2.3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Lattice dims are {X, Y, Z, T}, every extent even and >= 2.  The site index
+ * is lexicographic, x fastest: site = x + X (y + Y (z + Z t)).
+ * Operator (kappa normalised, u flavour):
+ *     M = 1 - kappa H + 2 i kappa mu gamma_5,
+ *     (H psi)(x) = sum_mu (1 - gamma_mu) U_mu(x) psi(x+mu)
+ *                       + (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu),
+ * chiral gamma basis (gamma_5 = diag(1, 1, -1, -1)), periodic in space, and
+ * a factor t_bc on every hop across the time boundary.  The d flavour is
+ * M(-mu).
+ * Host/device spinor fields at the boundary are complex128, laid out
+ * [site][spin 4][colour 3] (interleaved re, im).  Gauge fields are complex128
+ * [t][z][y][x][mu 4][3][3] (row-major 3x3, mu = 0..3 for x, y, z, t).
+ * Pointers documented "device" must be device memory of the context's GPU;
+ * the library never takes ownership of caller memory.
+ *
+ * Every call returns an int status: 0 OK; 1 DL_NOT_CONVERGED (results were
+ * written, per-source flags tell which ones); negative values are errors
+ * (see DL_E*).  dl_last_error() returns a thread-local message for the last
+ * failing call on the calling thread.  No C++ exception crosses this ABI.
+ * All GPU work is ordered on the context's stream; calls that return host
+ * results synchronise that stream before returning.
+ */
+#ifndef DISCLOOP_H
+#define DISCLOOP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define DL_OK 0
+#define DL_NOT_CONVERGED 1
+#define DL_EINVAL (-1)
+#define DL_ENOMEM (-2)
+#define DL_EHIP (-3)
+#define DL_ESTATE (-4)
+#define DL_EBREAKDOWN (-5)
+
+/* noise of the volume sources (Section 2): Z2 = real +-1, Z4 = {1, i, -1, -i};
+ * USER = caller-provided sources (dl_job.src_in). */
+#define DL_NOISE_Z2 0
+#define DL_NOISE_Z4 1
+#define DL_NOISE_USER 2
+
+/* solver tiers of the truncated solver method (Section 2.1).
+ *   FP64     plain method: fields, links and arithmetic in FP64.
+ *   LP_BF16  low precision: bf16-stored spinors and links, FP32 arithmetic,
+ *            FP64 dot products.
+ *   LP_FP16  as LP_BF16 with IEEE half storage.
+ *   HP_FP32  high precision: FP32 fields and arithmetic with FP64 reliable
+ *            updates (true residual and solution accumulated in FP64). */
+#define DL_TIER_FP64 0
+#define DL_TIER_LP_BF16 1
+#define DL_TIER_LP_FP16 2
+#define DL_TIER_HP_FP32 3
+
+/* accumulator sets of the TSM estimator
+ *   L = S_LP / N_LP + (S_HP - S_LPC) / N_HP
+ * LP: low-precision solves of the LP sources; HP: high-precision solves of
+ * the correction sources; LPC: low-precision solves of those same sources. */
+#define DL_SET_LP 0
+#define DL_SET_HP 1
+#define DL_SET_LPC 2
+
+/* insertion sets: LOCAL = 16 ultra-local Gamma; DERIV adds the 4 x 16
+ * one-derivative insertions (Section 2.1.1: 160 with both flavours). */
+#define DL_OPS_LOCAL 1
+#define DL_OPS_DERIV 2
+
+/* per-source status in dl_src_stats.status */
+#define DL_SRC_CONVERGED 0
+#define DL_SRC_MAXITER 1
+#define DL_SRC_BREAKDOWN 2
+
+typedef struct dl_ctx dl_ctx;
+typedef struct dl_lattice dl_lattice;
+typedef struct dl_accum dl_accum;
+
+/* One batch entry of dl_solve_batch: nsrc sources of one lattice and tier. */
+typedef struct dl_job {
+  dl_lattice* lat;       /* lattice (gauge field and kappa, mu set) */
+  int noise;             /* DL_NOISE_* */
+  int tier;              /* DL_TIER_* */
+  uint64_t seed;         /* noise seed (Z2 / Z4) */
+  int64_t first_src;     /* index r of the first source; source r is a pure
+                            function of (seed, r) */
+  int nsrc;              /* number of sources, >= 0 */
+  int maxiter;           /* CG iteration cap per source, > 0 */
+  double tol;            /* target relative residual rho (> 0) */
+  int rhs_block;         /* sources interleaved per slot; 0 = autotuned */
+  int report_true_resid; /* nonzero: also compute ||eta - M s|| / ||eta|| in FP64 */
+  const double* src_in;  /* DL_NOISE_USER: device complex128 [nsrc][V][12] */
+  double* sol_out;       /* optional device complex128 [nsrc][V][12]: s_r */
+  dl_accum* accum;       /* optional: add the loops of every source here */
+  int accum_set;         /* DL_SET_* */
+} dl_job;
+
+typedef struct dl_src_stats {
+  int iters;             /* CG iterations taken */
+  int status;            /* DL_SRC_* */
+  double rel_resid;      /* final iterated relative residual of the normal system */
+  double true_resid;     /* ||eta - M s|| / ||eta|| (FP64), or -1 if not requested */
+  int reliable_updates;  /* HP tier: number of FP64 reliable updates */
+  int pad;
+} dl_src_stats;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`.  `hip_stream` (a hipStream_t, may
+ * be NULL for the null stream) is borrowed: all work of this context is
+ * ordered on it and it must outlive the context. */
+int dl_create(dl_ctx** out, int device, void* hip_stream);
+int dl_destroy(dl_ctx* ctx);
+/* Message of the last failing call on this thread ("" if none). */
+const char* dl_last_error(void);
+/* Library version string. */
+const char* dl_version(void);
+
+/* ---- lattice and gauge field ------------------------------------------- */
+
+/* Create a lattice {X, Y, Z, T} (all even, >= 2) with time boundary factor
+ * t_bc (-1 antiperiodic, +1 periodic).  The library owns its device fields. */
+int dl_lattice_create(dl_ctx* ctx, const int dims[4], int t_bc, dl_lattice** out);
+int dl_lattice_destroy(dl_lattice* lat);
+
+/* Copy a gauge field in (layout above) and pack it into the FP64, FP32, bf16
+ * and fp16 even-odd layouts.  on_device: 0 host pointer, 1 device pointer.
+ * The caller keeps ownership of `links`. */
+int dl_gauge_set(dl_lattice* lat, const double* links, int on_device);
+
+/* Set kappa and mu of the operator (mu != 0, kappa > 0). */
+int dl_set_params(dl_lattice* lat, double kappa, double mu);
+
+/* ---- solves and loops -------------------------------------------------- */
+
+/* Solve every source of every job (Section 2, eq. (1)) by even-odd CGNR at
+ * the job's tier, then add the one-end-trick loops of each solution to the
+ * job's accumulator set.  Jobs of the same precision class run together in
+ * shared launches (different lattices and source blocks interleaved).
+ * stats: optional host array of sum(nsrc) entries, in job order.
+ * Returns DL_NOT_CONVERGED if any source missed its tolerance. */
+int dl_solve_batch(dl_ctx* ctx, const dl_job* jobs, int njobs, dl_src_stats* stats);
+
+/* Per-site FP64 loop accumulators of one lattice (three TSM sets). */
+int dl_accum_create(dl_lattice* lat, int ops, dl_accum** out);
+int dl_accum_reset(dl_accum* acc);
+int dl_accum_destroy(dl_accum* acc);
+/* Number of sources added to each set (counts[3] = {LP, HP, LPC}). */
+int dl_accum_counts(const dl_accum* acc, int64_t counts[3]);
+
+/* Integer momenta n with |n|^2 <= p2max, components in (-L/2, L/2] of the
+ * lattice's spatial extents, ordered by |n|^2 then (n_x, n_y, n_z).  Writes
+ * up to cap vectors to n_xyz (host int[cap][3], may be NULL) and returns the
+ * count in *np_out. */
+int dl_momenta(const int dims[4], int p2max, int* n_xyz, int cap, int* np_out);
+
+/* Project the accumulated loops (Section 2.3: Fourier transform over space
+ * per time slice, cut at p^2 <= p2max), rebuild the 16 Gamma insertions from
+ * the 4x4 outer products (Section 2.2), combine the TSM sets and apply the
+ * one-end-trick prefactors.  out: complex128 [2][nops][16][T][Np], flavour 0
+ * with tau_3, 1 without; op 0 local, 1..4 derivative along x, y, z, t
+ * (nops = 1 or 5 by the accumulator's ops); host (out_on_device = 0) or
+ * device pointer.  *np_out receives Np. */
+int dl_loops(dl_ctx* ctx, dl_accum* acc, int p2max, double* out, int out_on_device,
+             int* np_out);
+
+/* Gradients of loops built from caller sources (DL_NOISE_USER, FP64 or
+ * HP_FP32 tier) with respect to the sources and to mu: given
+ * grad_loops = dF/dL^* for the loops L = dl_loops(...) of those sources
+ * (complex128 [2][nops][16][T][Np], host), write dF/deta^* (device complex128
+ * [nsrc][V][12], optional) and dF/dmu (host double, optional), by adjoint
+ * solves with M^dag = gamma_5 M(-mu) gamma_5 (conjugate-Wirtinger
+ * convention, F real). */
+int dl_loops_backward(dl_ctx* ctx, const dl_job* job, int p2max, const double* grad_loops,
+                      double* grad_eta, double* grad_mu);
+
+/* ---- options and kernel timing ----------------------------------------- */
+
+/* Set a context option (name, numeric value):
+ *   "inflight_rhs"  max right-hand sides solved together per launch (>= 1)
+ *   "inflight_mb"   device memory budget of one batch of solves, MiB
+ *   "use_graph"     1: replay CG iterations from a HIP graph; 0: plain launches
+ *   "profile"       1: time every hopping-kernel launch of the CG (the
+ *                   u_e = A^-1 H_eo p_o step) with HIP events on the context
+ *                   stream and count its compulsory bytes; 0: off
+ * Returns DL_EINVAL for an unknown name or value. */
+int dl_set_option(dl_ctx* ctx, const char* name, double value);
+
+/* Read and reset the profile counters of the hopping kernel for one storage
+ * tier: out[0] launches, out[1] total kernel milliseconds, out[2] total
+ * compulsory HBM bytes (links once per lattice and launch, input and output
+ * spinor once per active right-hand side), out[3] total active rhs. */
+int dl_profile_read(dl_ctx* ctx, int tier, double out[4]);
+
+/* ---- single operators, for verification -------------------------------- */
+
+/* Operators of dl_apply_op. */
+#define DL_OP_M 0        /* M psi, full lattice */
+#define DL_OP_MDAG 1     /* M^dag psi */
+#define DL_OP_MHAT 2     /* even-odd Schur complement on odd sites */
+#define DL_OP_MHAT_DAG 3 /* its adjoint */
+#define DL_OP_HOP 4      /* the hopping term H psi */
+
+/* Apply one operator to nrhs fields through the library's kernels at
+ * precision `tier` (its storage type).  in/out: device complex128
+ * [nrhs][V][12]; for MHAT / MHAT_DAG only odd sites of `in` are read and the
+ * even sites of `out` are set to zero. */
+int dl_apply_op(dl_lattice* lat, int op, int tier, const double* in, double* out, int nrhs);
+
+/* Write source number `src` (Z2 / Z4) to out (device complex128 [V][12]). */
+int dl_fill_noise(dl_lattice* lat, int noise, uint64_t seed, int64_t src, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DISCLOOP_H */

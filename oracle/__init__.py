@@ -10,7 +10,7 @@ What it computes (paper: "A QUDA-branch to compute disconnected diagrams in
 GPUs", LATTICE 2013):
 
 * the stochastic inversions ``M s_r = eta_r`` of Section 2, eq. (1), for the
-  twisted-mass Wilson operator, with Z2 / Z4 volume noise (Section 2, 2.4);
+  twisted-mass Wilson operator, with Z2 / Z4 volume noise (Sections 2, 2.3, 2.4);
 * the truncated solver method of Section 2.1: many low-precision solves plus a
   few high-precision corrections;
 * the one-end-trick loops of Section 2.1.1 / 2.2: ultra-local and

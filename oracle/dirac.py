@@ -153,6 +153,38 @@ def apply_M0(U, psi, kappa, bc_t):
     return psi - kappa * hop(U, psi, bc_t)
 
 
+def hop_at_sites(U, psi, bc_t, sites):
+    """(H psi)(x) at a list of sites (t, z, y, x), one site at a time.
+
+    A second, site-by-site spelling of ``hop`` used to check outputs of very
+    large lattices where the whole-field version is too slow.
+    Returns [len(sites), 4, 3].
+    """
+    T, Z, Y, X = psi.shape[-6:-2]
+    ext = {0: X, 1: Y, 2: Z, 3: T}
+    one = np.eye(4, dtype=complex)
+    out = np.zeros((len(sites), 4, 3), dtype=complex)
+    for i, (t, z, y, x) in enumerate(sites):
+        acc = np.zeros((4, 3), dtype=complex)
+        for mu in range(4):
+            c = [x, y, z, t]
+            fw, bw = list(c), list(c)
+            fw[mu] += 1
+            bw[mu] -= 1
+            sf = bc_t if (mu == 3 and fw[3] == T) else 1.0
+            sb = bc_t if (mu == 3 and bw[3] < 0) else 1.0
+            fw[mu] %= ext[mu]
+            bw[mu] %= ext[mu]
+            pf = psi[fw[3], fw[2], fw[1], fw[0]]
+            pb = psi[bw[3], bw[2], bw[1], bw[0]]
+            uf = U[t, z, y, x, mu]
+            ub = U[bw[3], bw[2], bw[1], bw[0], mu]
+            acc += sf * (one - GAMMA[mu]) @ (pf @ uf.T)
+            acc += sb * (one + GAMMA[mu]) @ (pb @ ub.conj())
+        out[i] = acc
+    return out
+
+
 # ---------------------------------------------------------------------------
 # even-odd (Schur complement on odd sites)
 # ---------------------------------------------------------------------------

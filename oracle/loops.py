@@ -3,7 +3,7 @@
 Section 2.1.1 computes all ultra-local and one-derivative insertions, with and
 without tau_3 (160 in total), per time slice, at momenta up to a p^2 cut;
 Section 2.2 builds every ultra-local Gamma from the colour-traced 4x4 Dirac
-outer product of the two contracted vectors; Section 2.4 Fourier transforms
+outer product of the two contracted vectors; Section 2.3 Fourier transforms
 the per-site data and cuts in p^2.  The formulas are not printed, so the
 readings below are used.
 

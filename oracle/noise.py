@@ -1,5 +1,5 @@
-"""Volume noise sources eta_r (Section 2: random sources; Section 2.4: the
-paper draws them on the host with RANLUX and plans on-GPU generation).
+"""Volume noise sources eta_r (Section 2: random sources; Section 2.3: the
+paper draws them on the host with RANLUX; Section 2.4 plans GPU generation).
 
 Reading (the paper does not fix the noise or the generator):
 

@@ -1,0 +1,500 @@
+// The C ABI (include/discloop.h): argument checks, job planning and error
+// translation.  No C++ exception crosses this boundary.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "runtime.h"
+
+using namespace dl;
+
+static thread_local std::string g_last_error;
+
+template <class F>
+static int guarded(F&& f) {
+  try {
+    int rc = f();
+    if (rc >= 0) g_last_error.clear();
+    return rc;
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return DL_ENOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return DL_EHIP;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return DL_EHIP;
+  }
+}
+
+static void require(bool ok, const std::string& msg) {
+  if (!ok) throw Error(DL_EINVAL, msg);
+}
+
+extern "C" {
+
+const char* dl_last_error(void) { return g_last_error.c_str(); }
+
+const char* dl_version(void) { return "discloop-gfx950 0.1"; }
+
+int dl_create(dl_ctx** out, int device, void* hip_stream) {
+  return guarded([&] {
+    require(out != nullptr, "dl_create: out is NULL");
+    int n = 0;
+    HIPCHECK(hipGetDeviceCount(&n));
+    require(device >= 0 && device < n, "dl_create: no HIP device " + std::to_string(device));
+    HIPCHECK(hipSetDevice(device));
+    auto* c = new dl_ctx();
+    c->device = device;
+    c->user_stream = (hipStream_t)hip_stream;
+    try {
+      HIPCHECK(hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking));
+      HIPCHECK(hipEventCreateWithFlags(&c->ev, hipEventDisableTiming));
+      init_gamma_table();
+    } catch (...) {
+      if (c->st) (void)hipStreamDestroy(c->st);
+      if (c->ev) (void)hipEventDestroy(c->ev);
+      delete c;
+      throw;
+    }
+    *out = c;
+    return 0;
+  });
+}
+
+int dl_destroy(dl_ctx* ctx) {
+  return guarded([&] {
+    if (!ctx) return 0;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->st);
+    ctx->pool.clear();
+    (void)hipEventDestroy(ctx->ev);
+    (void)hipStreamDestroy(ctx->st);
+    delete ctx;
+    return 0;
+  });
+}
+
+int dl_lattice_create(dl_ctx* ctx, const int dims[4], int t_bc, dl_lattice** out) {
+  return guarded([&] {
+    require(ctx && dims && out, "dl_lattice_create: NULL argument");
+    for (int k = 0; k < 4; ++k)
+      require(dims[k] >= 2 && dims[k] % 2 == 0, "dl_lattice_create: every extent must be even and >= 2");
+    require(t_bc == 1 || t_bc == -1, "dl_lattice_create: t_bc must be +1 or -1");
+    const long long V = (long long)dims[0] * dims[1] * dims[2] * dims[3];
+    require(V / 2 < (1ll << 30), "dl_lattice_create: lattice too large");
+    HIPCHECK(hipSetDevice(ctx->device));
+    auto* L = new dl_lattice();
+    L->ctx = ctx;
+    std::memcpy(L->dims, dims, sizeof(L->dims));
+    L->bc = t_bc;
+    L->V = V;
+    L->Vh = V / 2;
+    try {
+      for (int p = 0; p < 4; ++p) {
+        const size_t bytes = (size_t)V * 4 * 9 * link_bytes(p);
+        if (hipMalloc(&L->gauge[p], bytes) != hipSuccess) {
+          (void)hipGetLastError();
+          throw Error(DL_ENOMEM, "dl_lattice_create: gauge allocation failed");
+        }
+      }
+    } catch (...) {
+      for (int p = 0; p < 4; ++p)
+        if (L->gauge[p]) (void)hipFree(L->gauge[p]);
+      delete L;
+      throw;
+    }
+    *out = L;
+    return 0;
+  });
+}
+
+int dl_lattice_destroy(dl_lattice* lat) {
+  return guarded([&] {
+    if (!lat) return 0;
+    (void)hipSetDevice(lat->ctx->device);
+    (void)hipStreamSynchronize(lat->ctx->st);
+    for (int p = 0; p < 4; ++p)
+      if (lat->gauge[p]) (void)hipFree(lat->gauge[p]);
+    delete lat;
+    return 0;
+  });
+}
+
+int dl_gauge_set(dl_lattice* lat, const double* links, int on_device) {
+  return guarded([&] {
+    require(lat && links, "dl_gauge_set: NULL argument");
+    dl_ctx* c = lat->ctx;
+    stream_enter(c);
+    const size_t bytes = (size_t)lat->V * 4 * 9 * 16;
+    DevBuf stage;
+    const double* src = links;
+    if (!on_device) {
+      stage = DevBuf(c, bytes);
+      HIPCHECK(hipMemcpyAsync(stage.p, links, bytes, hipMemcpyHostToDevice, c->st));
+      src = stage.as<double>();
+    }
+    launch_pack_gauge(src, lat->dims[0], lat->dims[1], lat->dims[2], lat->dims[3], lat->gauge[0], lat->gauge[1],
+                      lat->gauge[2], lat->gauge[3], c->st);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(c->st));
+    stream_exit(c);
+    lat->gauge_set = true;
+    return 0;
+  });
+}
+
+int dl_set_params(dl_lattice* lat, double kappa, double mu) {
+  return guarded([&] {
+    require(lat != nullptr, "dl_set_params: NULL lattice");
+    require(std::isfinite(kappa) && kappa > 0, "dl_set_params: kappa must be > 0");
+    require(std::isfinite(mu) && mu != 0, "dl_set_params: mu must be nonzero (one-end trick)");
+    lat->kappa = kappa;
+    lat->mu = mu;
+    lat->params_set = true;
+    return 0;
+  });
+}
+
+int dl_accum_create(dl_lattice* lat, int ops, dl_accum** out) {
+  return guarded([&] {
+    require(lat && out, "dl_accum_create: NULL argument");
+    require(ops == DL_OPS_LOCAL || ops == (DL_OPS_LOCAL | DL_OPS_DERIV), "dl_accum_create: ops must be LOCAL or LOCAL|DERIV");
+    HIPCHECK(hipSetDevice(lat->ctx->device));
+    auto* a = new dl_accum();
+    a->lat = lat;
+    a->ops = ops;
+    a->nq = acc_components(ops);
+    const size_t bytes = sizeof(double) * (size_t)a->nq * lat->V;
+    for (int s = 0; s < 3; ++s) {
+      if (hipMalloc((void**)&a->acc[s], bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        for (int k = 0; k < s; ++k) (void)hipFree(a->acc[k]);
+        delete a;
+        throw Error(DL_ENOMEM, "dl_accum_create: allocation failed");
+      }
+      HIPCHECK(hipMemset(a->acc[s], 0, bytes));
+    }
+    *out = a;
+    return 0;
+  });
+}
+
+int dl_accum_reset(dl_accum* a) {
+  return guarded([&] {
+    require(a != nullptr, "dl_accum_reset: NULL");
+    dl_ctx* c = a->lat->ctx;
+    stream_enter(c);
+    const size_t bytes = sizeof(double) * (size_t)a->nq * a->lat->V;
+    for (int s = 0; s < 3; ++s) {
+      HIPCHECK(hipMemsetAsync(a->acc[s], 0, bytes, c->st));
+      a->count[s] = 0;
+    }
+    stream_exit(c);
+    return 0;
+  });
+}
+
+int dl_accum_destroy(dl_accum* a) {
+  return guarded([&] {
+    if (!a) return 0;
+    (void)hipStreamSynchronize(a->lat->ctx->st);
+    for (int s = 0; s < 3; ++s)
+      if (a->acc[s]) (void)hipFree(a->acc[s]);
+    delete a;
+    return 0;
+  });
+}
+
+int dl_accum_counts(const dl_accum* a, int64_t counts[3]) {
+  return guarded([&] {
+    require(a && counts, "dl_accum_counts: NULL argument");
+    for (int s = 0; s < 3; ++s) counts[s] = a->count[s];
+    return 0;
+  });
+}
+
+static std::vector<std::array<int, 3>> momentum_list(const int dims[4], int p2max) {
+  std::vector<std::array<int, 3>> v;
+  int lo[3], hi[3];
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = -(dims[k] / 2) + 1;
+    hi[k] = dims[k] / 2;
+  }
+  for (int a = lo[0]; a <= hi[0]; ++a)
+    for (int b = lo[1]; b <= hi[1]; ++b)
+      for (int c = lo[2]; c <= hi[2]; ++c)
+        if (a * a + b * b + c * c <= p2max) v.push_back({a, b, c});
+  std::sort(v.begin(), v.end(), [](const std::array<int, 3>& x, const std::array<int, 3>& y) {
+    const int nx = x[0] * x[0] + x[1] * x[1] + x[2] * x[2], ny = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
+    if (nx != ny) return nx < ny;
+    return x < y;
+  });
+  return v;
+}
+
+int dl_momenta(const int dims[4], int p2max, int* n_xyz, int cap, int* np_out) {
+  return guarded([&] {
+    require(dims && np_out, "dl_momenta: NULL argument");
+    require(p2max >= 0, "dl_momenta: p2max must be >= 0");
+    auto v = momentum_list(dims, p2max);
+    *np_out = (int)v.size();
+    if (n_xyz)
+      for (int i = 0; i < (int)v.size() && i < cap; ++i)
+        for (int k = 0; k < 3; ++k) n_xyz[3 * i + k] = v[i][k];
+    return 0;
+  });
+}
+
+int dl_solve_batch(dl_ctx* ctx, const dl_job* jobs, int njobs, dl_src_stats* stats) {
+  return guarded([&] {
+    require(ctx != nullptr, "dl_solve_batch: NULL context");
+    require(njobs >= 0 && (njobs == 0 || jobs), "dl_solve_batch: bad job array");
+    std::vector<dl_job> J(jobs, jobs + njobs);
+    std::vector<long long> first_stat(njobs + 1, 0);
+    for (int j = 0; j < njobs; ++j) {
+      const dl_job& q = J[j];
+      require(q.lat != nullptr, "dl_solve_batch: job without lattice");
+      require(q.lat->ctx == ctx, "dl_solve_batch: lattice of another context");
+      require(q.lat->gauge_set, "dl_solve_batch: gauge field not set");
+      require(q.lat->params_set, "dl_solve_batch: kappa / mu not set");
+      require(q.nsrc >= 0, "dl_solve_batch: nsrc < 0");
+      require(q.maxiter > 0, "dl_solve_batch: maxiter must be > 0");
+      require(std::isfinite(q.tol) && q.tol > 0, "dl_solve_batch: tol must be > 0");
+      require(q.noise == DL_NOISE_Z2 || q.noise == DL_NOISE_Z4 || q.noise == DL_NOISE_USER,
+              "dl_solve_batch: unknown noise");
+      require(q.noise != DL_NOISE_USER || q.src_in, "dl_solve_batch: USER noise needs src_in");
+      require(q.first_src >= 0, "dl_solve_batch: first_src < 0");
+      (void)tier_prec(q.tier);
+      require(q.rhs_block >= 0, "dl_solve_batch: rhs_block < 0");
+      if (q.accum) {
+        require(q.accum->lat == q.lat, "dl_solve_batch: accumulator of another lattice");
+        require(q.accum_set >= 0 && q.accum_set < 3, "dl_solve_batch: bad accum_set");
+      }
+      first_stat[j + 1] = first_stat[j] + q.nsrc;
+    }
+    stream_enter(ctx);
+    bool all_ok = true;
+    const double budget = ctx->inflight_mb * 1048576.0;
+    const int max_rhs = ctx->inflight_rhs;
+    const int tiers[4] = {DL_TIER_FP64, DL_TIER_LP_BF16, DL_TIER_LP_FP16, DL_TIER_HP_FP32};
+    for (int tier : tiers) {
+      std::vector<SlotPlan> all;
+      for (int j = 0; j < njobs; ++j) {
+        const dl_job& q = J[j];
+        if (q.tier != tier || q.nsrc == 0) continue;
+        const int P = tier_prec(tier);
+        const int N = q.rhs_block > 0 ? q.rhs_block : autotune_block(ctx, q.lat, P, q.nsrc);
+        const long long V = q.lat->V;
+        for (int k = 0; k < q.nsrc; k += N) {
+          SlotPlan sp{};
+          sp.lat = q.lat;
+          sp.job = j;
+          sp.job_first = k;
+          sp.nrhs = std::min(N, q.nsrc - k);
+          sp.src0 = q.first_src + k;
+          sp.src_user = q.src_in ? q.src_in + (size_t)k * V * 24 : nullptr;
+          sp.sol_user = q.sol_out ? q.sol_out + (size_t)k * V * 24 : nullptr;
+          sp.acc = q.accum ? q.accum->acc[q.accum_set] : nullptr;
+          all.push_back(sp);
+        }
+      }
+      // waves bounded by device memory and rhs count
+      size_t i = 0;
+      while (i < all.size()) {
+        std::vector<SlotPlan> wave;
+        double bytes = 0;
+        int nrhs = 0;
+        while (i < all.size()) {
+          const SlotPlan& sp = all[i];
+          const int P = tier_prec(tier);
+          double per = (double)sp.lat->Vh * sp.nrhs * (7.0 * chunks_of(P) * 16);
+          if (tier == DL_TIER_HP_FP32) per += (double)sp.lat->Vh * sp.nrhs * 9.0 * 192;
+          if (J[sp.job].report_true_resid) per += (double)sp.lat->Vh * sp.nrhs * 6.0 * 192;
+          if (!wave.empty() && (bytes + per > budget || nrhs + sp.nrhs > max_rhs)) break;
+          wave.push_back(sp);
+          bytes += per;
+          nrhs += sp.nrhs;
+          ++i;
+        }
+        SolveReport rep;
+        run_batch(ctx, tier, wave, J, rep);
+        int g = 0;
+        for (const SlotPlan& sp : wave) {
+          for (int r = 0; r < sp.nrhs; ++r, ++g) {
+            if (rep.status[g] != 0) all_ok = false;
+            if (stats) {
+              dl_src_stats& s = stats[first_stat[sp.job] + sp.job_first + r];
+              s.iters = rep.iters[g];
+              s.status = rep.status[g];
+              s.rel_resid = rep.rel[g];
+              s.true_resid = rep.truer[g];
+              s.reliable_updates = rep.ru[g];
+              s.pad = 0;
+            }
+          }
+          const dl_job& q = J[sp.job];
+          if (q.accum) q.accum->count[q.accum_set] += sp.nrhs;
+        }
+      }
+    }
+    HIPCHECK(hipGetLastError());
+    stream_exit(ctx);
+    return all_ok ? 0 : DL_NOT_CONVERGED;
+  });
+}
+
+int dl_loops(dl_ctx* ctx, dl_accum* a, int p2max, double* out, int out_on_device, int* np_out) {
+  return guarded([&] {
+    require(ctx && a && out, "dl_loops: NULL argument");
+    require(p2max >= 0, "dl_loops: p2max must be >= 0");
+    dl_lattice* L = a->lat;
+    require(L->ctx == ctx, "dl_loops: accumulator of another context");
+    require(L->params_set, "dl_loops: kappa / mu not set");
+    require(a->count[DL_SET_LPC] == 0 || a->count[DL_SET_LPC] == a->count[DL_SET_HP],
+            "dl_loops: the LPC set must hold the same sources as the HP set");
+    auto moms = momentum_list(L->dims, p2max);
+    const int np = (int)moms.size();
+    if (np_out) *np_out = np;
+    const int X = L->dims[0], Y = L->dims[1], Z = L->dims[2], T = L->dims[3];
+    std::vector<double> ph[3];
+    const int ext[3] = {X, Y, Z};
+    for (int k = 0; k < 3; ++k) {
+      ph[k].resize((size_t)np * ext[k] * 2);
+      for (int p = 0; p < np; ++p)
+        for (int x = 0; x < ext[k]; ++x) {
+          const double ang = -2.0 * M_PI * (double)moms[p][k] * x / ext[k];
+          ph[k][2 * ((size_t)p * ext[k] + x)] = std::cos(ang);
+          ph[k][2 * ((size_t)p * ext[k] + x) + 1] = std::sin(ang);
+        }
+    }
+    stream_enter(ctx);
+    DevBuf dph[3];
+    for (int k = 0; k < 3; ++k) {
+      dph[k] = DevBuf(ctx, std::max<size_t>(ph[k].size() * sizeof(double), 16));
+      HIPCHECK(hipMemcpyAsync(dph[k].p, ph[k].data(), ph[k].size() * sizeof(double), hipMemcpyHostToDevice, ctx->st));
+    }
+    const size_t pbytes = std::max<size_t>(sizeof(double) * 2 * (size_t)a->nq * T * np, 16);
+    DevBuf proj[3];
+    for (int s = 0; s < 3; ++s) {
+      proj[s] = DevBuf(ctx, pbytes);
+      if (a->count[s] > 0) {
+        launch_project(a->acc[s], a->nq, X, Y, Z, T, np, dph[0].as<double>(), dph[1].as<double>(),
+                       dph[2].as<double>(), proj[s].as<double>(), ctx->st);
+      } else {
+        HIPCHECK(hipMemsetAsync(proj[s].p, 0, pbytes, ctx->st));
+      }
+    }
+    const int nops = (a->ops & DL_OPS_DERIV) ? 5 : 1;
+    const size_t obytes = sizeof(double) * 2 * 2 * nops * 16 * (size_t)T * np;
+    const double w_lp = a->count[DL_SET_LP] > 0 ? 1.0 / (double)a->count[DL_SET_LP] : 0.0;
+    const double w_hp = a->count[DL_SET_HP] > 0 ? 1.0 / (double)a->count[DL_SET_HP] : 0.0;
+    DevBuf dout;
+    double* target = out;
+    if (!out_on_device) {
+      dout = DevBuf(ctx, std::max<size_t>(obytes, 16));
+      target = dout.as<double>();
+    }
+    launch_loops_finalize(proj[0].as<double>(), proj[1].as<double>(), proj[2].as<double>(), w_lp, w_hp, nops, T, np,
+                          L->kappa, L->mu, target, ctx->st);
+    HIPCHECK(hipGetLastError());
+    if (!out_on_device) {
+      HIPCHECK(hipMemcpyAsync(out, target, obytes, hipMemcpyDeviceToHost, ctx->st));
+      HIPCHECK(hipStreamSynchronize(ctx->st));
+    }
+    stream_exit(ctx);
+    return 0;
+  });
+}
+
+int dl_set_option(dl_ctx* ctx, const char* name, double value) {
+  return guarded([&] {
+    require(ctx && name, "dl_set_option: NULL argument");
+    const std::string n(name);
+    if (n == "inflight_rhs") {
+      require(value >= 1 && value < 1e9, "dl_set_option: inflight_rhs must be >= 1");
+      ctx->inflight_rhs = (int)value;
+    } else if (n == "inflight_mb") {
+      require(value > 0, "dl_set_option: inflight_mb must be > 0");
+      ctx->inflight_mb = value;
+    } else if (n == "use_graph") {
+      require(value == 0 || value == 1, "dl_set_option: use_graph must be 0 or 1");
+      ctx->use_graph = value != 0;
+    } else if (n == "profile") {
+      require(value == 0 || value == 1, "dl_set_option: profile must be 0 or 1");
+      ctx->profile = value != 0;
+    } else {
+      throw Error(DL_EINVAL, "dl_set_option: unknown option '" + n + "'");
+    }
+    return 0;
+  });
+}
+
+int dl_profile_read(dl_ctx* ctx, int tier, double out[4]) {
+  return guarded([&] {
+    require(ctx && out, "dl_profile_read: NULL argument");
+    const int P = tier_prec(tier);
+    for (int k = 0; k < 4; ++k) {
+      out[k] = ctx->prof[P][k];
+      ctx->prof[P][k] = 0;
+    }
+    return 0;
+  });
+}
+
+int dl_apply_op(dl_lattice* lat, int op, int tier, const double* in, double* out, int nrhs) {
+  return guarded([&] {
+    require(lat && in && out, "dl_apply_op: NULL argument");
+    require(nrhs >= 1, "dl_apply_op: nrhs must be >= 1");
+    require(lat->gauge_set, "dl_apply_op: gauge field not set");
+    require(lat->params_set || op == DL_OP_HOP, "dl_apply_op: kappa / mu not set");
+    require(op >= DL_OP_M && op <= DL_OP_HOP, "dl_apply_op: unknown operator");
+    stream_enter(lat->ctx);
+    apply_op(lat, op, tier, in, out, nrhs);
+    HIPCHECK(hipGetLastError());
+    stream_exit(lat->ctx);
+    return 0;
+  });
+}
+
+int dl_fill_noise(dl_lattice* lat, int noise, uint64_t seed, int64_t src, double* out) {
+  return guarded([&] {
+    require(lat && out, "dl_fill_noise: NULL argument");
+    require(noise == DL_NOISE_Z2 || noise == DL_NOISE_Z4, "dl_fill_noise: noise must be Z2 or Z4");
+    require(src >= 0, "dl_fill_noise: src < 0");
+    dl_ctx* c = lat->ctx;
+    stream_enter(c);
+    std::vector<dl_job> J(1);
+    std::memset(&J[0], 0, sizeof(dl_job));
+    J[0].lat = lat;
+    J[0].noise = noise;
+    J[0].seed = seed;
+    std::vector<SlotPlan> plan(1);
+    plan[0] = SlotPlan{};
+    plan[0].lat = lat;
+    plan[0].job = 0;
+    plan[0].nrhs = 1;
+    plan[0].src0 = src;
+    plan[0].sol_user = out;
+    fill_noise_fields(c, plan, J);
+    stream_exit(c);
+    return 0;
+  });
+}
+
+int dl_loops_backward(dl_ctx* ctx, const dl_job* job, int p2max, const double* grad_loops, double* grad_eta,
+                      double* grad_mu) {
+  return guarded([&] {
+    require(ctx && job && grad_loops, "dl_loops_backward: NULL argument");
+    loops_backward(ctx, *job, p2max, grad_loops, grad_eta, grad_mu);
+    return 0;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,315 @@
+// Internal definitions shared by the HIP kernels and the host runtime.
+//
+// Device data layout (one lattice, one right-hand side):
+//   spinor half field, parity p:  [chunk][site]   16-byte chunks, site = even-odd
+//                                                index within the parity
+//       FP64: 12 chunks of 1 complex, FP32: 6 chunks of 2 complex,
+//       bf16 / fp16: 3 chunks of 4 complex.  Component k = 3 * spin + colour.
+//   gauge field:                  [mu][parity][entry 9][site]  one complex
+//                                                element per (mu, parity, entry, site)
+//   loop accumulators (FP64):     [component q][full e/o site = parity * Vh + site]
+//
+// A "batch" interleaves several lattices and right-hand sides: rhs r of slot i
+// starts at site offset fo_i + r * Vh_i of every batch field.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dl {
+
+enum Prec : int { P64 = 0, P32 = 1, PB16 = 2, PH16 = 3 };
+
+// Tag types of the two 16-bit storage formats.
+struct bf16s {};
+struct f16s {};
+
+template <class S> struct Traits;
+template <> struct Traits<double> { using R = double; static constexpr int NC = 12; static constexpr int prec = P64; };
+template <> struct Traits<float> { using R = float; static constexpr int NC = 6; static constexpr int prec = P32; };
+template <> struct Traits<bf16s> { using R = float; static constexpr int NC = 3; static constexpr int prec = PB16; };
+template <> struct Traits<f16s> { using R = float; static constexpr int NC = 3; static constexpr int prec = PH16; };
+
+inline int chunks_of(int prec) { return prec == P64 ? 12 : (prec == P32 ? 6 : 3); }
+inline int link_bytes(int prec) { return prec == P64 ? 16 : (prec == P32 ? 8 : 4); }
+
+constexpr int TILE = 64;        // sites per unit (one wavefront)
+
+// ---------------------------------------------------------------------------
+// complex numbers in the compute precision
+// ---------------------------------------------------------------------------
+template <class R> struct cx { R re, im; };
+
+template <class R> __host__ __device__ inline cx<R> mk(R a, R b) { return cx<R>{a, b}; }
+template <class R> __device__ inline cx<R> operator+(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <class R> __device__ inline cx<R> operator-(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <class R> __device__ inline cx<R> operator*(cx<R> a, cx<R> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <class R> __device__ inline cx<R> operator*(R s, cx<R> a) { return {s * a.re, s * a.im}; }
+template <class R> __device__ inline cx<R> conj(cx<R> a) { return {a.re, -a.im}; }
+template <class R> __device__ inline cx<R> times_i(cx<R> a) { return {-a.im, a.re}; }
+template <class R> __device__ inline cx<R> times_mi(cx<R> a) { return {a.im, -a.re}; }
+// a += conj(b) * c
+template <class R> __device__ inline void cjmac(cx<R>& a, cx<R> b, cx<R> c) {
+  a.re += b.re * c.re + b.im * c.im;
+  a.im += b.re * c.im - b.im * c.re;
+}
+// a += b * c
+template <class R> __device__ inline void cmac(cx<R>& a, cx<R> b, cx<R> c) {
+  a.re += b.re * c.re - b.im * c.im;
+  a.im += b.re * c.im + b.im * c.re;
+}
+
+// ---------------------------------------------------------------------------
+// 16-bit conversions (round to nearest even)
+// ---------------------------------------------------------------------------
+__device__ inline float bf16_to_f(uint32_t h) { return __uint_as_float(h << 16); }
+__device__ inline uint32_t f_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x7fffffu)) return 0x7fc0u;  // NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+__device__ inline float f16_to_f(uint32_t h) {
+  _Float16 v = __builtin_bit_cast(_Float16, (uint16_t)h);
+  return (float)v;
+}
+__device__ inline uint32_t f_to_f16(float f) {
+  _Float16 v = (_Float16)f;
+  return (uint32_t)__builtin_bit_cast(uint16_t, v);
+}
+
+template <class S> __device__ inline cx<float> unpack2(uint32_t w);
+template <> __device__ inline cx<float> unpack2<bf16s>(uint32_t w) { return {bf16_to_f(w & 0xffffu), bf16_to_f(w >> 16)}; }
+template <> __device__ inline cx<float> unpack2<f16s>(uint32_t w) { return {f16_to_f(w & 0xffffu), f16_to_f(w >> 16)}; }
+template <class S> __device__ inline uint32_t pack2(cx<float> v);
+template <> __device__ inline uint32_t pack2<bf16s>(cx<float> v) { return f_to_bf16(v.re) | (f_to_bf16(v.im) << 16); }
+template <> __device__ inline uint32_t pack2<f16s>(cx<float> v) { return f_to_f16(v.re) | (f_to_f16(v.im) << 16); }
+
+// ---------------------------------------------------------------------------
+// spinor loads / stores: base points at chunk 0 of one (rhs, parity) half
+// field; stride is Vh (chunks between consecutive chunk rows).
+// ---------------------------------------------------------------------------
+template <class S> struct Spinor {
+  using R = typename Traits<S>::R;
+  cx<R> c[12];
+};
+
+template <class S>
+__device__ inline void load_spinor(const void* base, long stride, long s, cx<typename Traits<S>::R> (&v)[12]);
+
+template <>
+__device__ inline void load_spinor<double>(const void* base, long stride, long s, cx<double> (&v)[12]) {
+  const double2* p = (const double2*)base;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    double2 w = p[k * stride + s];
+    v[k] = {w.x, w.y};
+  }
+}
+template <>
+__device__ inline void load_spinor<float>(const void* base, long stride, long s, cx<float> (&v)[12]) {
+  const float4* p = (const float4*)base;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    float4 w = p[k * stride + s];
+    v[2 * k] = {w.x, w.y};
+    v[2 * k + 1] = {w.z, w.w};
+  }
+}
+template <class S16>
+__device__ inline void load_spinor16(const void* base, long stride, long s, cx<float> (&v)[12]) {
+  const uint4* p = (const uint4*)base;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    uint4 w = p[k * stride + s];
+    v[4 * k + 0] = unpack2<S16>(w.x);
+    v[4 * k + 1] = unpack2<S16>(w.y);
+    v[4 * k + 2] = unpack2<S16>(w.z);
+    v[4 * k + 3] = unpack2<S16>(w.w);
+  }
+}
+template <>
+__device__ inline void load_spinor<bf16s>(const void* base, long stride, long s, cx<float> (&v)[12]) {
+  load_spinor16<bf16s>(base, stride, s, v);
+}
+template <>
+__device__ inline void load_spinor<f16s>(const void* base, long stride, long s, cx<float> (&v)[12]) {
+  load_spinor16<f16s>(base, stride, s, v);
+}
+
+template <class S>
+__device__ inline void store_spinor(void* base, long stride, long s, const cx<typename Traits<S>::R> (&v)[12]);
+
+template <>
+__device__ inline void store_spinor<double>(void* base, long stride, long s, const cx<double> (&v)[12]) {
+  double2* p = (double2*)base;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) p[k * stride + s] = make_double2(v[k].re, v[k].im);
+}
+template <>
+__device__ inline void store_spinor<float>(void* base, long stride, long s, const cx<float> (&v)[12]) {
+  float4* p = (float4*)base;
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+    p[k * stride + s] = make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im);
+}
+template <class S16>
+__device__ inline void store_spinor16(void* base, long stride, long s, const cx<float> (&v)[12]) {
+  uint4* p = (uint4*)base;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    uint4 w;
+    w.x = pack2<S16>(v[4 * k + 0]);
+    w.y = pack2<S16>(v[4 * k + 1]);
+    w.z = pack2<S16>(v[4 * k + 2]);
+    w.w = pack2<S16>(v[4 * k + 3]);
+    p[k * stride + s] = w;
+  }
+}
+template <>
+__device__ inline void store_spinor<bf16s>(void* base, long stride, long s, const cx<float> (&v)[12]) {
+  store_spinor16<bf16s>(base, stride, s, v);
+}
+template <>
+__device__ inline void store_spinor<f16s>(void* base, long stride, long s, const cx<float> (&v)[12]) {
+  store_spinor16<f16s>(base, stride, s, v);
+}
+
+// Round a spinor held in the compute precision to the storage precision.
+template <class S> __device__ inline void quantize(cx<typename Traits<S>::R> (&)[12]) {}
+template <class S16> __device__ inline void quantize16(cx<float> (&v)[12]) {
+#pragma unroll
+  for (int k = 0; k < 12; ++k) v[k] = unpack2<S16>(pack2<S16>(v[k]));
+}
+template <> __device__ inline void quantize<bf16s>(cx<float> (&v)[12]) { quantize16<bf16s>(v); }
+template <> __device__ inline void quantize<f16s>(cx<float> (&v)[12]) { quantize16<f16s>(v); }
+
+// |v|^2 summed in FP64
+template <class R> __device__ inline double norm2(const cx<R> (&v)[12]) {
+  double n = 0.0;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) n += (double)v[k].re * (double)v[k].re + (double)v[k].im * (double)v[k].im;
+  return n;
+}
+
+// Address of (rhs field) chunk row 0 for site offset `off` (in sites) of a
+// batch field with NC chunks per site.
+template <class S> __device__ inline const void* field_at(const void* base, long long off) {
+  return (const char*)base + off * (long long)Traits<S>::NC * 16;
+}
+template <class S> __device__ inline void* field_at(void* base, long long off) {
+  return (char*)base + off * (long long)Traits<S>::NC * 16;
+}
+
+// ---------------------------------------------------------------------------
+// gauge links: 9 complex entries, row-major
+// ---------------------------------------------------------------------------
+template <class S>
+__device__ inline void load_link(const void* g, long vh, int mu, int par, long s, cx<typename Traits<S>::R> (&u)[9]);
+
+template <>
+__device__ inline void load_link<double>(const void* g, long vh, int mu, int par, long s, cx<double> (&u)[9]) {
+  const double2* p = (const double2*)g + (long)(mu * 2 + par) * 9 * vh;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    double2 w = p[e * vh + s];
+    u[e] = {w.x, w.y};
+  }
+}
+template <>
+__device__ inline void load_link<float>(const void* g, long vh, int mu, int par, long s, cx<float> (&u)[9]) {
+  const float2* p = (const float2*)g + (long)(mu * 2 + par) * 9 * vh;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    float2 w = p[e * vh + s];
+    u[e] = {w.x, w.y};
+  }
+}
+template <class S16>
+__device__ inline void load_link16(const void* g, long vh, int mu, int par, long s, cx<float> (&u)[9]) {
+  const uint32_t* p = (const uint32_t*)g + (long)(mu * 2 + par) * 9 * vh;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) u[e] = unpack2<S16>(p[e * vh + s]);
+}
+template <>
+__device__ inline void load_link<bf16s>(const void* g, long vh, int mu, int par, long s, cx<float> (&u)[9]) {
+  load_link16<bf16s>(g, vh, mu, par, s, u);
+}
+template <>
+__device__ inline void load_link<f16s>(const void* g, long vh, int mu, int par, long s, cx<float> (&u)[9]) {
+  load_link16<f16s>(g, vh, mu, par, s, u);
+}
+
+// ---------------------------------------------------------------------------
+// batch slots
+// ---------------------------------------------------------------------------
+enum UnitKind : int { UK_RHS = 0, UK_SITE = 1, UK_DERIV = 2 };
+
+struct SlotDesc {
+  int X, Y, Z, T;
+  int Xh, Vh, ntile, nrhs;
+  int ubeg[3];             // first unit of this slot per UnitKind
+  int rhs_begin;           // global index of this slot's rhs 0
+  long long fo;            // site offset of rhs 0 in every batch field
+  double bc;               // time-boundary factor
+  const void* gauge[4];    // gauge field per precision
+  double* acc;             // accumulator set of this slot (contractions), or null
+  uint64_t seed;           // noise
+  long long src0;          // source index of rhs 0
+  int noise;               // DL_NOISE_*
+  int acc_ops;             // DL_OPS_* of the accumulator
+  const double* src_user;  // caller sources of rhs 0 (complex128 [V][12] per rhs), or null
+  double* sol_user;        // caller solution array of rhs 0, or null
+};
+
+// Per-slot site-diagonal spin coefficients of one dslash-type launch:
+//   out = e (.) H(d (.) in) + f (.) y     (per-spin complex factors)
+struct Coef {
+  double d[4][2], e[4][2], f[4][2];
+};
+
+// Hardware dispatches workgroup b to XCD (b mod 8); renumber so that each XCD
+// runs one contiguous range of logical workgroups (neighbouring tiles and the
+// right-hand sides of one tile then share that XCD's L2).
+__device__ inline int xcd_logical_block() {
+  int nb = gridDim.x, b = blockIdx.x;
+  int q = nb >> 3, rem = nb & 7, x = b & 7, k = b >> 3;
+  return x * q + (x < rem ? x : rem) + k;
+}
+
+__device__ inline int find_slot(const SlotDesc* slots, int nslots, int kind, int u) {
+  int lo = 0, hi = nslots - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (slots[mid].ubeg[kind] <= u) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Site coordinates of even-odd index s in parity p.
+struct Coords { int x, y, z, t; };
+__device__ inline Coords eo_coords(const SlotDesc& sd, int s, int p) {
+  Coords c;
+  int xh = s % sd.Xh;
+  int rest = s / sd.Xh;
+  c.y = rest % sd.Y;
+  rest /= sd.Y;
+  c.z = rest % sd.Z;
+  c.t = rest / sd.Z;
+  c.x = 2 * xh + ((p + c.y + c.z + c.t) & 1);
+  return c;
+}
+__device__ inline int eo_index(const SlotDesc& sd, int x, int y, int z, int t) {
+  return (x + sd.X * (y + sd.Y * (z + sd.Z * t))) >> 1;
+}
+
+// wave64 sum, fixed butterfly order (deterministic)
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+}  // namespace dl

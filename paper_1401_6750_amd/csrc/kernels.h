@@ -1,0 +1,111 @@
+// Host-side launchers of the HIP kernels (implemented in the *.hip files).
+#pragma once
+
+#include "common.h"
+
+namespace dl {
+
+// dslash epilogue / prologue flags
+enum DslashFlags : int {
+  F_D = 1,      // multiply the input by the per-spin factor d on load
+  F_Y = 2,      // add f (.) y
+  F_NORM = 4,   // per-unit partial of ||result||^2 (or ||r||^2 with F_XR)
+  F_XR = 8,     // CG update: x += alpha p, r -= alpha result (result not stored)
+  F_OUT2 = 16,  // also store the result to a second field
+};
+
+struct DslashArgs {
+  const SlotDesc* slots;
+  int nslots;
+  int total_units;
+  const Coef* coef;
+  int p_out;
+  const void* in;
+  void* out;
+  const void* y;
+  double* partial;
+  const int* active;
+  void* x;
+  void* r;
+  const void* p;
+  const double* alpha;
+  void* out2;
+};
+
+void launch_dslash(int prec, int flags, const DslashArgs& a, hipStream_t st);
+
+// finalize kinds
+enum FinKind : int { FK_INIT = 0, FK_ALPHA = 1, FK_BETA = 2, FK_STORE = 3 };
+
+struct CgScalars {
+  double* rr;      // current <r, r>
+  double* cc;      // <c, c> of the normal-equation right-hand side
+  double* alpha;
+  double* beta;
+  double* tol2;    // tol^2
+  double* out;     // FK_STORE destination
+  int* active;
+  int* iters;
+  int* maxiter;
+  int* status;
+};
+
+void launch_finalize(int kind, const SlotDesc* slots, int nslots, int nrhs_total,
+                     const double* partial, const CgScalars& cs, hipStream_t st);
+
+// p = r + beta p for active right-hand sides
+void launch_update_p(int prec, const SlotDesc* slots, int nslots, int total_units, void* p,
+                     const void* r, const double* beta, const int* active, hipStream_t st);
+
+// set a batch field to zero on parity-free half fields
+void launch_zero(int prec, const SlotDesc* slots, int nslots, int total_units, void* f,
+                 const int* active, hipStream_t st);
+
+// eta (parity p) of every rhs: Z2 / Z4 from the counter generator, or packed
+// from the caller's complex128 sources
+void launch_sources(int prec, const SlotDesc* slots, int nslots, int total_units, int parity,
+                    void* eta, hipStream_t st);
+
+// unpack even and odd half fields to the caller's complex128 solution arrays
+void launch_unpack(int prec, const SlotDesc* slots, int nslots, int total_units, int parity,
+                   const void* f, hipStream_t st);
+
+// out = (S_out) in, for active rhs (or all when active is null); add != 0: out += in
+void launch_convert(int prec_in, int prec_out, const SlotDesc* slots, int nslots, int total_units,
+                    const void* in, void* out, int add, const int* active, hipStream_t st);
+
+// r64 = c64 - ap64, r32 = (float) r64, partial ||r64||^2, for rhs with flag set
+void launch_residual_replace(const SlotDesc* slots, int nslots, int total_units, const void* c64,
+                             const void* ap64, void* r64, void* r32, double* partial,
+                             const int* flag, hipStream_t st);
+
+// partial ||a - b||^2 and ||b||^2 (FP64 fields) for the true residual report
+void launch_diff_norms(const SlotDesc* slots, int nslots, int total_units, const void* a,
+                       const void* b, double* partial_diff, double* partial_b, hipStream_t st);
+
+// gauge packing: FP64 [t][z][y][x][mu][3][3] (device) -> four even-odd layouts
+void launch_pack_gauge(const double* src, int X, int Y, int Z, int T, void* g64, void* g32,
+                       void* gb16, void* gh16, hipStream_t st);
+
+// loop contractions of a block of solutions into FP64 accumulators
+void launch_contract_local(int prec, const SlotDesc* slots, int nslots, int total_units,
+                           const void* s_e, const void* s_o, const void* xi_e, const void* xi_o,
+                           hipStream_t st);
+void launch_contract_deriv(int prec, const SlotDesc* slots, int nslots, int total_units,
+                           const void* s_e, const void* s_o, const void* xi_e, const void* xi_o,
+                           hipStream_t st);
+
+// momentum projection of accumulator components: acc [nq][V] -> proj [nq][T][Np] complex
+void launch_project(const double* acc, int nq, int X, int Y, int Z, int T, int np,
+                    const double* phase_x, const double* phase_y, const double* phase_z,
+                    double* proj, hipStream_t st);
+
+// Gamma rebuild, TSM combination and prefactors -> out [2][nops][16][T][Np] complex
+void launch_loops_finalize(const double* proj_lp, const double* proj_hp, const double* proj_lpc,
+                           double w_lp, double w_hp, int nops, int T, int np, double kappa,
+                           double mu, double* out, hipStream_t st);
+
+// Number of FP64 accumulator components per site for an ops mask.
+int acc_components(int ops);
+
+}  // namespace dl

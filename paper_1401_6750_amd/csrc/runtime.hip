@@ -1,0 +1,819 @@
+// Host runtime: batched even-odd CGNR solves (the stochastic inversions of
+// the paper's eq. (1)), source generation, contractions and loop assembly.
+//
+// A batch is a list of slots (lattice, block of consecutive sources) of one
+// precision class.  Every kernel launch covers the whole batch, so lattices of
+// different sizes and any number of right-hand sides advance together; each
+// right-hand side carries its own CG scalars and retires on its own
+// convergence, after which its units exit at once.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+
+#include "runtime.h"
+
+namespace dl {
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw Error(DL_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void* Pool::get(size_t bytes) {
+  auto it = free_.find(bytes);
+  if (it != free_.end()) {
+    void* p = it->second;
+    free_.erase(it);
+    cached_bytes -= bytes;
+    return p;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    clear();
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(DL_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+  }
+  return p;
+}
+
+void Pool::put(void* p, size_t bytes) {
+  free_.emplace(bytes, p);
+  cached_bytes += bytes;
+}
+
+void Pool::clear() {
+  for (auto& kv : free_) (void)hipFree(kv.second);
+  free_.clear();
+  cached_bytes = 0;
+}
+
+void stream_enter(dl_ctx* c) {
+  HIPCHECK(hipSetDevice(c->device));
+  HIPCHECK(hipEventRecord(c->ev, c->user_stream));
+  HIPCHECK(hipStreamWaitEvent(c->st, c->ev, 0));
+}
+
+void stream_exit(dl_ctx* c) {
+  HIPCHECK(hipEventRecord(c->ev, c->st));
+  HIPCHECK(hipStreamWaitEvent(c->user_stream, c->ev, 0));
+}
+
+int tier_prec(int tier) {
+  switch (tier) {
+    case DL_TIER_FP64: return P64;
+    case DL_TIER_LP_BF16: return PB16;
+    case DL_TIER_LP_FP16: return PH16;
+    case DL_TIER_HP_FP32: return P32;
+  }
+  throw Error(DL_EINVAL, "unknown tier " + std::to_string(tier));
+}
+
+// ---------------------------------------------------------------------------
+// gamma insertions: Gamma_n = g1^n0 g2^n1 g3^n2 g4^n3, chiral basis
+// ---------------------------------------------------------------------------
+void init_gamma_table() {
+  using C = std::complex<double>;
+  const C I(0, 1);
+  C g[4][4][4] = {};
+  // gamma_k = [[0, -i sigma_k], [i sigma_k, 0]], gamma_4 = [[0, 1], [1, 0]]
+  const C sig[3][2][2] = {{{0, 1}, {1, 0}}, {{0, -I}, {I, 0}}, {{1, 0}, {0, -1}}};
+  for (int k = 0; k < 3; ++k)
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) {
+        g[k][a][2 + b] = -I * sig[k][a][b];
+        g[k][2 + a][b] = I * sig[k][a][b];
+      }
+  for (int a = 0; a < 2; ++a) g[3][a][2 + a] = g[3][2 + a][a] = 1;
+  int col[16][4];
+  double ph[16][4][2];
+  for (int n = 0; n < 16; ++n) {
+    C m[4][4] = {};
+    for (int a = 0; a < 4; ++a) m[a][a] = 1;
+    for (int k = 0; k < 4; ++k) {
+      if (!((n >> k) & 1)) continue;
+      C t[4][4] = {};
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b)
+          for (int c = 0; c < 4; ++c) t[a][b] += m[a][c] * g[k][c][b];
+      std::memcpy(m, t, sizeof(m));
+    }
+    for (int a = 0; a < 4; ++a) {
+      int found = -1;
+      for (int b = 0; b < 4; ++b)
+        if (std::abs(m[a][b]) > 0.5) found = b;
+      col[n][a] = found;
+      ph[n][a][0] = m[a][found].real();
+      ph[n][a][1] = m[a][found].imag();
+    }
+  }
+  set_gamma_table(col, ph);
+}
+
+// ---------------------------------------------------------------------------
+// per-slot spin coefficients of the dslash-type launches
+// ---------------------------------------------------------------------------
+enum CoefKind : int {
+  CK_MHAT1 = 0,   // u_e = A^-1(mu) H_eo p_o
+  CK_MHAT2,       // t_o = p_o - kappa^2 A^-1(mu) H_oe u_e
+  CK_MDAG1,       // u_e = A^-1(-mu) H_eo gamma5 A^-1(-mu) w_o
+  CK_MDAG2,       // out_o = w_o - kappa^2 gamma5 H_oe u_e
+  CK_PREP,        // bhat_o = A^-1(eta_o + kappa H_oe A^-1 eta_e)
+  CK_RECON,       // s_e = A^-1(eta_e + kappa H_eo s_o)
+  CK_XI,          // xi_p = s_p - kappa H s
+  CK_MFULL,       // (M psi)_p = A psi_p - kappa H psi
+  CK_MDAGFULL,    // (M^dag psi)_p = A(-mu) psi_p - kappa gamma5 H gamma5 psi
+  CK_HOP,         // H psi
+  CK_COUNT
+};
+
+using Cd = std::complex<double>;
+
+static void put(double (&dst)[4][2], const Cd (&v)[4]) {
+  for (int s = 0; s < 4; ++s) {
+    dst[s][0] = v[s].real();
+    dst[s][1] = v[s].imag();
+  }
+}
+
+static Coef make_coef(int kind, double kappa, double mu) {
+  const double g5[4] = {1, 1, -1, -1};
+  Cd one[4], zero[4], A[4], Am[4], Ai[4], Ami[4], G5[4];
+  for (int s = 0; s < 4; ++s) {
+    one[s] = 1.0;
+    zero[s] = 0.0;
+    A[s] = Cd(1.0, 2.0 * kappa * mu * g5[s]);
+    Am[s] = Cd(1.0, -2.0 * kappa * mu * g5[s]);
+    Ai[s] = 1.0 / A[s];
+    Ami[s] = 1.0 / Am[s];
+    G5[s] = g5[s];
+  }
+  Cd d[4], e[4], f[4];
+  for (int s = 0; s < 4; ++s) {
+    d[s] = one[s];
+    e[s] = one[s];
+    f[s] = zero[s];
+  }
+  const double k2 = kappa * kappa;
+  for (int s = 0; s < 4; ++s) {
+    switch (kind) {
+      case CK_MHAT1: e[s] = Ai[s]; break;
+      case CK_MHAT2: e[s] = -k2 * Ai[s]; f[s] = 1.0; break;
+      case CK_MDAG1: d[s] = G5[s] * Ami[s]; e[s] = Ami[s]; break;
+      case CK_MDAG2: e[s] = -k2 * G5[s]; f[s] = 1.0; break;
+      case CK_PREP: d[s] = Ai[s]; e[s] = kappa * Ai[s]; f[s] = Ai[s]; break;
+      case CK_RECON: e[s] = kappa * Ai[s]; f[s] = Ai[s]; break;
+      case CK_XI: e[s] = -kappa; f[s] = 1.0; break;
+      case CK_MFULL: e[s] = -kappa; f[s] = A[s]; break;
+      case CK_MDAGFULL: d[s] = G5[s]; e[s] = -kappa * G5[s]; f[s] = Am[s]; break;
+      case CK_HOP: break;
+    }
+  }
+  Coef c;
+  put(c.d, d);
+  put(c.e, e);
+  put(c.f, f);
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// batch state
+// ---------------------------------------------------------------------------
+struct Batch {
+  dl_ctx* ctx;
+  int prec;
+  std::vector<SlotDesc> hs;
+  std::vector<Coef> coefs;     // host copies stay alive while their uploads are in flight
+  DevBuf dslots, dcoef;
+  int nslots = 0, nrhs = 0, u_rhs = 0, u_site = 0, u_deriv = 0;
+  long long sites = 0;
+  DevBuf partial, partial2, scal;
+  CgScalars cs{};
+  int* h_int = nullptr;        // pinned: active / status / iters mirrors
+  double* h_dbl = nullptr;     // pinned: rr / cc / out mirrors
+
+  Batch(dl_ctx* c, int prec_, const std::vector<SlotPlan>& plan, const std::vector<dl_job>* jobs)
+      : ctx(c), prec(prec_) {
+    int ur = 0, us = 0, ud = 0, rb = 0;
+    long long fo = 0;
+    for (const SlotPlan& sp : plan) {
+      const dl_lattice* L = sp.lat;
+      SlotDesc d{};
+      d.X = L->dims[0]; d.Y = L->dims[1]; d.Z = L->dims[2]; d.T = L->dims[3];
+      d.Xh = d.X / 2;
+      d.Vh = (int)L->Vh;
+      d.ntile = (d.Vh + TILE - 1) / TILE;
+      d.nrhs = sp.nrhs;
+      d.ubeg[UK_RHS] = ur; d.ubeg[UK_SITE] = us; d.ubeg[UK_DERIV] = ud;
+      d.rhs_begin = rb;
+      d.fo = fo;
+      d.bc = (double)L->bc;
+      for (int p = 0; p < 4; ++p) d.gauge[p] = L->gauge[p];
+      d.acc = sp.acc;
+      d.acc_ops = 0;
+      if (jobs && sp.acc) d.acc_ops = (*jobs)[sp.job].accum->ops;
+      if (jobs) {
+        const dl_job& j = (*jobs)[sp.job];
+        d.seed = j.seed;
+        d.noise = j.noise;
+      } else {
+        d.noise = DL_NOISE_USER;
+      }
+      d.src0 = sp.src0;
+      d.src_user = sp.src_user;
+      d.sol_user = sp.sol_user;
+      ur += d.ntile * d.nrhs;
+      us += 2 * d.ntile;
+      ud += 16 * d.ntile;
+      rb += d.nrhs;
+      fo += (long long)d.nrhs * d.Vh;
+      hs.push_back(d);
+    }
+    nslots = (int)hs.size();
+    nrhs = rb;
+    u_rhs = ur; u_site = us; u_deriv = ud;
+    sites = fo;
+    dslots = DevBuf(ctx, sizeof(SlotDesc) * nslots);
+    HIPCHECK(hipMemcpyAsync(dslots.p, hs.data(), sizeof(SlotDesc) * nslots, hipMemcpyHostToDevice, ctx->st));
+    coefs.resize((size_t)CK_COUNT * nslots);
+    for (int k = 0; k < CK_COUNT; ++k)
+      for (int i = 0; i < nslots; ++i) {
+        const dl_lattice* L = plan[i].lat;
+        coefs[(size_t)k * nslots + i] = make_coef(k, L->kappa, L->mu);
+      }
+    dcoef = DevBuf(ctx, sizeof(Coef) * coefs.size());
+    HIPCHECK(hipMemcpyAsync(dcoef.p, coefs.data(), sizeof(Coef) * coefs.size(), hipMemcpyHostToDevice, ctx->st));
+    partial = DevBuf(ctx, sizeof(double) * std::max(u_rhs, 1));
+    partial2 = DevBuf(ctx, sizeof(double) * std::max(u_rhs, 1));
+    // scalars: 6 double arrays + 4 int arrays
+    const size_t nd = 6 * (size_t)nrhs, ni = 4 * (size_t)nrhs;
+    scal = DevBuf(ctx, sizeof(double) * nd + sizeof(int) * ni + 16);
+    double* db = scal.as<double>();
+    cs.rr = db; cs.cc = db + nrhs; cs.alpha = db + 2 * nrhs; cs.beta = db + 3 * nrhs;
+    cs.tol2 = db + 4 * nrhs; cs.out = db + 5 * nrhs;
+    int* ib = (int*)(db + nd);
+    cs.active = ib; cs.iters = ib + nrhs; cs.maxiter = ib + 2 * nrhs; cs.status = ib + 3 * nrhs;
+    HIPCHECK(hipHostMalloc((void**)&h_int, sizeof(int) * 4 * std::max(nrhs, 1), hipHostMallocDefault));
+    HIPCHECK(hipHostMalloc((void**)&h_dbl, sizeof(double) * 6 * std::max(nrhs, 1), hipHostMallocDefault));
+  }
+  ~Batch() {
+    if (h_int) (void)hipHostFree(h_int);
+    if (h_dbl) (void)hipHostFree(h_dbl);
+  }
+  const SlotDesc* slots() const { return dslots.as<SlotDesc>(); }
+  const Coef* coef(int kind) const { return dcoef.as<Coef>() + (size_t)kind * nslots; }
+  size_t field_bytes(int p) const { return (size_t)sites * chunks_of(p) * 16; }
+  DevBuf field(int p) { return DevBuf(ctx, std::max<size_t>(field_bytes(p), 16)); }
+
+  void dslash(int p, int flags, int ck, int p_out, const void* in, void* out, const void* y,
+              const int* gate, void* x = nullptr, void* r = nullptr, const void* pp = nullptr,
+              void* out2 = nullptr, double* part = nullptr) {
+    DslashArgs a{};
+    a.slots = slots(); a.nslots = nslots; a.total_units = u_rhs; a.coef = coef(ck); a.p_out = p_out;
+    a.in = in; a.out = out; a.y = y; a.partial = part ? part : partial.as<double>(); a.active = gate;
+    a.x = x; a.r = r; a.p = pp; a.alpha = cs.alpha; a.out2 = out2;
+    launch_dslash(p, flags, a, ctx->st);
+  }
+  void finalize(int kind, const double* part = nullptr) {
+    launch_finalize(kind, slots(), nslots, nrhs, part ? part : partial.as<double>(), cs, ctx->st);
+  }
+  void finalize_store(double* dst, const int* gate, const double* part) {
+    CgScalars c = cs;
+    c.out = dst;
+    c.active = const_cast<int*>(gate);
+    launch_finalize(FK_STORE, slots(), nslots, nrhs, part, c, ctx->st);
+  }
+  void to_host_int(const int* dev, int* host) {
+    HIPCHECK(hipMemcpyAsync(host, dev, sizeof(int) * nrhs, hipMemcpyDeviceToHost, ctx->st));
+  }
+  void to_host_dbl(const double* dev, double* host) {
+    HIPCHECK(hipMemcpyAsync(host, dev, sizeof(double) * nrhs, hipMemcpyDeviceToHost, ctx->st));
+  }
+  void sync() { HIPCHECK(hipStreamSynchronize(ctx->st)); }
+};
+
+// All-ones gate (every rhs selected) for FK_STORE of reports.
+static DevBuf ones_gate(Batch& b) {
+  DevBuf g(b.ctx, sizeof(int) * std::max(b.nrhs, 1));
+  std::vector<int> h(std::max(b.nrhs, 1), 1);
+  HIPCHECK(hipMemcpyAsync(g.p, h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice, b.ctx->st));
+  HIPCHECK(hipStreamSynchronize(b.ctx->st));
+  return g;
+}
+
+// ---------------------------------------------------------------------------
+// CG on Mhat^dag Mhat: one iteration (7 launches), gated by the active mask
+// ---------------------------------------------------------------------------
+struct CgFields {
+  void *x, *r, *p, *t, *u;
+};
+
+static void cg_iteration(Batch& b, int P, const CgFields& f, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr) {
+  const int* act = b.cs.active;
+  if (t0) HIPCHECK(hipEventRecord(t0, b.ctx->st));
+  b.dslash(P, 0, CK_MHAT1, 0, f.p, f.u, nullptr, act);
+  if (t1) HIPCHECK(hipEventRecord(t1, b.ctx->st));
+  b.dslash(P, F_Y | F_NORM, CK_MHAT2, 1, f.u, f.t, f.p, act);
+  b.finalize(FK_ALPHA);
+  b.dslash(P, F_D, CK_MDAG1, 0, f.t, f.u, nullptr, act);
+  b.dslash(P, F_Y | F_XR | F_NORM, CK_MDAG2, 1, f.u, nullptr, f.t, act, f.x, f.r, f.p);
+  b.finalize(FK_BETA);
+  launch_update_p(P, b.slots(), b.nslots, b.u_rhs, f.p, f.r, b.cs.beta, act, b.ctx->st);
+}
+
+// c = Mhat^dag bhat with bhat from eta; r = p = c, x = 0, scalars initialised.
+static void cg_start(Batch& b, int P, const void* eta_e, const void* eta_o, const CgFields& f) {
+  b.dslash(P, F_D | F_Y, CK_PREP, 1, eta_e, f.t, eta_o, nullptr);
+  b.dslash(P, F_D, CK_MDAG1, 0, f.t, f.u, nullptr, nullptr);
+  b.dslash(P, F_Y | F_NORM | F_OUT2, CK_MDAG2, 1, f.u, f.r, f.t, nullptr, nullptr, nullptr, nullptr, f.p);
+  b.finalize(FK_INIT);
+  launch_zero(P, b.slots(), b.nslots, b.u_rhs, f.x, nullptr, b.ctx->st);
+}
+
+// Contractions add into per-site accumulators with plain read-modify-writes,
+// so no two units of one launch may own the same accumulator.  Consecutive
+// slots of one lattice that feed one accumulator are contiguous in every batch
+// field and merge into one contraction slot (its right-hand sides are summed in
+// registers, in order); accumulators that still appear in several merged slots
+// are handled in successive launches.
+static void contract_passes(Batch& b, int P, const void* s_e, const void* s_o, const void* xi_e, const void* xi_o) {
+  std::vector<SlotDesc> merged;
+  for (const SlotDesc& d : b.hs) {
+    if (!d.acc) continue;
+    if (!merged.empty()) {
+      SlotDesc& m = merged.back();
+      if (m.acc == d.acc && m.gauge[0] == d.gauge[0] && m.fo + (long long)m.nrhs * m.Vh == d.fo) {
+        m.nrhs += d.nrhs;
+        continue;
+      }
+    }
+    merged.push_back(d);
+  }
+  std::vector<std::vector<SlotDesc>> passes;
+  std::map<double*, int> seen;
+  for (const SlotDesc& d : merged) {
+    const int k = seen[d.acc]++;
+    if ((int)passes.size() <= k) passes.emplace_back();
+    passes[k].push_back(d);
+  }
+  for (auto& pass : passes) {
+    int us = 0, ud = 0;
+    for (SlotDesc& d : pass) {
+      d.ubeg[UK_SITE] = us;
+      d.ubeg[UK_DERIV] = ud;
+      us += 2 * d.ntile;
+      ud += 16 * d.ntile;
+    }
+    DevBuf ds(b.ctx, sizeof(SlotDesc) * pass.size());
+    HIPCHECK(hipMemcpyAsync(ds.p, pass.data(), sizeof(SlotDesc) * pass.size(), hipMemcpyHostToDevice, b.ctx->st));
+    const SlotDesc* dptr = ds.as<SlotDesc>();
+    launch_contract_local(P, dptr, (int)pass.size(), us, s_e, s_o, xi_e, xi_o, b.ctx->st);
+    launch_contract_deriv(P, dptr, (int)pass.size(), ud, s_e, s_o, xi_e, xi_o, b.ctx->st);
+    // the descriptor buffer returns to the pool only after the stream passed it
+    HIPCHECK(hipStreamSynchronize(b.ctx->st));
+  }
+}
+
+static int count_active(Batch& b) {
+  b.to_host_int(b.cs.active, b.h_int);
+  b.sync();
+  int n = 0;
+  for (int i = 0; i < b.nrhs; ++i) n += b.h_int[i] != 0;
+  return n;
+}
+
+// Plain CG (FP64 and low-precision tiers): iterations replayed from a HIP
+// graph, convergence polled on the host between bursts.
+// Compulsory HBM bytes of one hopping launch (u_e = A^-1 H_eo p_o) for the
+// given active mask: every lattice's links once (8 links of 18 reals per
+// output site) plus input and output spinor (24 reals each) per active rhs.
+static double hop_launch_bytes(const Batch& b, int P, const int* active) {
+  const double breal = P == P64 ? 8.0 : (P == P32 ? 4.0 : 2.0);
+  double bytes = 0.0;
+  std::vector<const void*> seen;
+  for (const SlotDesc& d : b.hs) {
+    int na = 0;
+    for (int r = 0; r < d.nrhs; ++r) na += active[d.rhs_begin + r] != 0;
+    if (!na) continue;
+    bytes += na * 48.0 * breal * d.Vh;
+    if (std::find(seen.begin(), seen.end(), d.gauge[0]) == seen.end()) {
+      seen.push_back(d.gauge[0]);
+      bytes += 144.0 * breal * d.Vh;
+    }
+  }
+  return bytes;
+}
+
+static void run_cg_plain(Batch& b, int P, const CgFields& f, int maxiter_all, int first_burst) {
+  if (count_active(b) == 0) return;
+  dl_ctx* c = b.ctx;
+  if (c->profile || !c->use_graph) {
+    // plain launches; with profiling, HIP events bracket each hopping launch
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->profile) {
+      HIPCHECK(hipEventCreate(&e0));
+      HIPCHECK(hipEventCreate(&e1));
+    }
+    std::vector<int> act(b.h_int, b.h_int + b.nrhs);
+    try {
+      for (int it = 0; it < maxiter_all; ++it) {
+        cg_iteration(b, P, f, e0, e1);
+        const int n = count_active(b);
+        if (c->profile) {
+          float ms = 0.f;
+          HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+          double* pr = c->prof[P];
+          int na = 0;
+          for (int g = 0; g < b.nrhs; ++g) na += act[g] != 0;
+          pr[0] += 1;
+          pr[1] += ms;
+          pr[2] += hop_launch_bytes(b, P, act.data());
+          pr[3] += na;
+        }
+        act.assign(b.h_int, b.h_int + b.nrhs);
+        if (n == 0) break;
+      }
+    } catch (...) {
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+      throw;
+    }
+    if (e0) HIPCHECK(hipEventDestroy(e0));
+    if (e1) HIPCHECK(hipEventDestroy(e1));
+    return;
+  }
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  HIPCHECK(hipStreamBeginCapture(b.ctx->st, hipStreamCaptureModeThreadLocal));
+  try {
+    cg_iteration(b, P, f);
+  } catch (...) {
+    hipGraph_t g2 = nullptr;
+    (void)hipStreamEndCapture(b.ctx->st, &g2);
+    if (g2) (void)hipGraphDestroy(g2);
+    throw;
+  }
+  HIPCHECK(hipStreamEndCapture(b.ctx->st, &graph));
+  hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (ie != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    HIPCHECK(ie);
+  }
+  int it = 0;
+  int burst = std::max(1, first_burst);
+  try {
+    while (it < maxiter_all) {
+      const int n = std::min(burst, maxiter_all - it);
+      for (int k = 0; k < n; ++k) HIPCHECK(hipGraphLaunch(exec, b.ctx->st));
+      it += n;
+      if (count_active(b) == 0) break;
+      burst = 1;
+    }
+  } catch (...) {
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    throw;
+  }
+  HIPCHECK(hipGraphExecDestroy(exec));
+  HIPCHECK(hipGraphDestroy(graph));
+}
+
+// ---------------------------------------------------------------------------
+// the batch pipeline
+// ---------------------------------------------------------------------------
+static std::string hint_key(const std::vector<SlotPlan>& plan, int tier, double tol) {
+  char buf[128];
+  const dl_lattice* L = plan[0].lat;
+  snprintf(buf, sizeof(buf), "%d:%g:%dx%dx%dx%d", tier, tol, L->dims[0], L->dims[1], L->dims[2], L->dims[3]);
+  return buf;
+}
+
+static std::map<std::string, int>& iter_hints() {
+  static std::map<std::string, int> m;
+  return m;
+}
+
+void run_batch(dl_ctx* ctx, int tier, const std::vector<SlotPlan>& plan, const std::vector<dl_job>& jobs,
+               SolveReport& rep) {
+  const int P = tier_prec(tier);
+  Batch b(ctx, P, plan, &jobs);
+  hipStream_t st = ctx->st;
+  // per-rhs tolerance and iteration cap
+  {
+    std::vector<double> tol2(b.nrhs);
+    std::vector<int> mi(b.nrhs);
+    int g = 0;
+    for (const SlotPlan& sp : plan)
+      for (int r = 0; r < sp.nrhs; ++r, ++g) {
+        tol2[g] = jobs[sp.job].tol * jobs[sp.job].tol;
+        mi[g] = jobs[sp.job].maxiter;
+      }
+    HIPCHECK(hipMemcpyAsync(b.cs.tol2, tol2.data(), sizeof(double) * b.nrhs, hipMemcpyHostToDevice, st));
+    HIPCHECK(hipMemcpyAsync(b.cs.maxiter, mi.data(), sizeof(int) * b.nrhs, hipMemcpyHostToDevice, st));
+    b.sync();   // the host vectors end with this scope
+  }
+  int maxiter_all = 0;
+  double tol_min = 1.0;
+  bool want_true = false;
+  for (const SlotPlan& sp : plan) {
+    maxiter_all = std::max(maxiter_all, jobs[sp.job].maxiter);
+    tol_min = std::min(tol_min, jobs[sp.job].tol);
+    want_true = want_true || jobs[sp.job].report_true_resid;
+  }
+  const std::string hk = hint_key(plan, tier, tol_min);
+  const int first_burst = iter_hints().count(hk) ? iter_hints()[hk] : 1;
+
+  DevBuf eta_e = b.field(P), eta_o = b.field(P);
+  launch_sources(P, b.slots(), b.nslots, b.u_rhs, 0, eta_e.p, st);
+  launch_sources(P, b.slots(), b.nslots, b.u_rhs, 1, eta_o.p, st);
+  DevBuf x = b.field(P), r = b.field(P), p = b.field(P), t = b.field(P), u = b.field(P);
+  CgFields f{x.p, r.p, p.p, t.p, u.p};
+  std::vector<int> ru_count(b.nrhs, 0);
+  // s_e / s_o / xi fields in the contraction precision
+  int PC = P;
+  DevBuf s64_e, s64_o;   // FP64 solution when the solve keeps one (HP tier)
+
+  if (tier != DL_TIER_HP_FP32) {
+    cg_start(b, P, eta_e.p, eta_o.p, f);
+    run_cg_plain(b, P, f, maxiter_all, first_burst);
+  } else {
+    // High precision: FP32 CG with FP64 reliable updates (true residual of
+    // the normal equations recomputed in FP64, solution accumulated in FP64).
+    DevBuf e64_e = b.field(P64), e64_o = b.field(P64), c64 = b.field(P64), xhi = b.field(P64),
+           t64 = b.field(P64), u64 = b.field(P64), ap64 = b.field(P64);
+    launch_sources(P64, b.slots(), b.nslots, b.u_rhs, 0, e64_e.p, st);
+    launch_sources(P64, b.slots(), b.nslots, b.u_rhs, 1, e64_o.p, st);
+    b.dslash(P64, F_D | F_Y, CK_PREP, 1, e64_e.p, t64.p, e64_o.p, nullptr);
+    b.dslash(P64, F_D, CK_MDAG1, 0, t64.p, u64.p, nullptr, nullptr);
+    b.dslash(P64, F_Y | F_NORM, CK_MDAG2, 1, u64.p, c64.p, t64.p, nullptr);
+    b.finalize(FK_INIT);
+    launch_convert(P64, P32, b.slots(), b.nslots, b.u_rhs, c64.p, r.p, 0, nullptr, st);
+    launch_convert(P64, P32, b.slots(), b.nslots, b.u_rhs, c64.p, p.p, 0, nullptr, st);
+    launch_zero(P32, b.slots(), b.nslots, b.u_rhs, x.p, nullptr, st);
+    launch_zero(P64, b.slots(), b.nslots, b.u_rhs, xhi.p, nullptr, st);
+    DevBuf flag(ctx, sizeof(int) * std::max(b.nrhs, 1));
+    std::vector<int> hflag(b.nrhs, 0), verified(b.nrhs, 0);
+    std::vector<double> rr_ru(b.nrhs), cc(b.nrhs);
+    b.to_host_dbl(b.cs.rr, b.h_dbl);
+    b.sync();
+    for (int g = 0; g < b.nrhs; ++g) rr_ru[g] = b.h_dbl[g];
+    b.to_host_dbl(b.cs.cc, b.h_dbl);
+    b.sync();
+    for (int g = 0; g < b.nrhs; ++g) cc[g] = b.h_dbl[g];
+    std::vector<double> tolv(b.nrhs);
+    std::vector<int> maxit(b.nrhs);
+    {
+      int g = 0;
+      for (const SlotPlan& sp : plan)
+        for (int q = 0; q < sp.nrhs; ++q, ++g) {
+          tolv[g] = jobs[sp.job].tol;
+          maxit[g] = jobs[sp.job].maxiter;
+        }
+    }
+    const double delta2 = 0.01;   // reliable update when ||r|| fell by 10x since the last one
+    int guard = 0;
+    while (true) {
+      // state after the previous step
+      int* act = b.h_int;
+      int* status = b.h_int + b.nrhs;
+      int* iters = b.h_int + 2 * b.nrhs;
+      b.to_host_int(b.cs.active, act);
+      b.to_host_int(b.cs.status, status);
+      b.to_host_int(b.cs.iters, iters);
+      b.to_host_dbl(b.cs.rr, b.h_dbl);
+      b.sync();
+      bool any_flag = false, any_active = false;
+      for (int g = 0; g < b.nrhs; ++g) {
+        hflag[g] = 0;
+        if (act[g]) {
+          any_active = true;
+          if (b.h_dbl[g] < delta2 * rr_ru[g]) hflag[g] = 1;
+        } else if (status[g] == 0 && !verified[g] && cc[g] > 0) {
+          hflag[g] = 2;   // iterated residual converged: verify with the true residual
+        }
+        any_flag = any_flag || hflag[g];
+      }
+      if (!any_active && !any_flag) break;
+      if (++guard > 4 * maxiter_all + 16) break;
+      if (any_flag) {
+        std::vector<int> f01(b.nrhs);
+        for (int g = 0; g < b.nrhs; ++g) f01[g] = hflag[g] != 0;
+        HIPCHECK(hipMemcpyAsync(flag.p, f01.data(), sizeof(int) * b.nrhs, hipMemcpyHostToDevice, st));
+        const int* fl = flag.as<int>();
+        launch_convert(P32, P64, b.slots(), b.nslots, b.u_rhs, x.p, xhi.p, 1, fl, st);
+        launch_zero(P32, b.slots(), b.nslots, b.u_rhs, x.p, fl, st);
+        b.dslash(P64, 0, CK_MHAT1, 0, xhi.p, u64.p, nullptr, fl);
+        b.dslash(P64, F_Y, CK_MHAT2, 1, u64.p, t64.p, xhi.p, fl);
+        b.dslash(P64, F_D, CK_MDAG1, 0, t64.p, u64.p, nullptr, fl);
+        b.dslash(P64, F_Y, CK_MDAG2, 1, u64.p, ap64.p, t64.p, fl);
+        launch_residual_replace(b.slots(), b.nslots, b.u_rhs, c64.p, ap64.p, u64.p, r.p, b.partial.as<double>(),
+                                fl, st);
+        b.finalize_store(b.cs.rr, fl, b.partial.as<double>());
+        b.to_host_dbl(b.cs.rr, b.h_dbl);
+        b.sync();
+        std::vector<int> react;
+        for (int g = 0; g < b.nrhs; ++g) {
+          if (!hflag[g]) continue;
+          ru_count[g]++;
+          rr_ru[g] = b.h_dbl[g];
+          if (hflag[g] == 2) {
+            if (b.h_dbl[g] <= tolv[g] * tolv[g] * cc[g]) {
+              verified[g] = 1;
+            } else if (iters[g] < maxit[g]) {
+              react.push_back(g);       // restart CG from the true residual
+            } else {
+              verified[g] = 1;
+              status[g] = 1;
+              HIPCHECK(hipMemcpyAsync(b.cs.status + g, &status[g], sizeof(int), hipMemcpyHostToDevice, st));
+              b.sync();
+            }
+          }
+        }
+        if (!react.empty()) {
+          std::vector<int> ga(b.nrhs, 0);
+          for (int g : react) ga[g] = 1;
+          HIPCHECK(hipMemcpyAsync(flag.p, ga.data(), sizeof(int) * b.nrhs, hipMemcpyHostToDevice, st));
+          launch_convert(P32, P32, b.slots(), b.nslots, b.u_rhs, r.p, p.p, 0, flag.as<int>(), st);
+          const int one = 1;
+          for (int g : react) {
+            HIPCHECK(hipMemcpyAsync(b.cs.active + g, &one, sizeof(int), hipMemcpyHostToDevice, st));
+            HIPCHECK(hipMemcpyAsync(b.cs.status + g, &one, sizeof(int), hipMemcpyHostToDevice, st));
+          }
+          b.sync();
+        }
+        continue;
+      }
+      cg_iteration(b, P32, f);
+    }
+    // fold the last FP32 correction; reconstruct in FP64
+    launch_convert(P32, P64, b.slots(), b.nslots, b.u_rhs, x.p, xhi.p, 1, nullptr, st);
+    s64_o = std::move(xhi);
+    s64_e = b.field(P64);
+    b.dslash(P64, F_Y, CK_RECON, 0, s64_o.p, s64_e.p, e64_e.p, nullptr);
+    // FP32 copies for the contractions
+    launch_convert(P64, P32, b.slots(), b.nslots, b.u_rhs, s64_o.p, x.p, 0, nullptr, st);
+  }
+
+  // ---- solution, xi fields, contractions ---------------------------------
+  // fields: s_o = x, s_e = r, xi_e = p, xi_o = t
+  if (tier == DL_TIER_HP_FP32) {
+    launch_convert(P64, P32, b.slots(), b.nslots, b.u_rhs, s64_e.p, r.p, 0, nullptr, st);
+  } else {
+    b.dslash(P, F_Y, CK_RECON, 0, x.p, r.p, eta_e.p, nullptr);
+  }
+  bool any_acc = false, any_sol = false;
+  for (const SlotPlan& sp : plan) {
+    any_acc = any_acc || sp.acc;
+    any_sol = any_sol || sp.sol_user;
+  }
+  if (any_acc) {
+    b.dslash(PC, F_Y, CK_XI, 0, x.p, p.p, r.p, nullptr);
+    b.dslash(PC, F_Y, CK_XI, 1, r.p, t.p, x.p, nullptr);
+    contract_passes(b, PC, r.p, x.p, p.p, t.p);
+  }
+  if (any_sol) {
+    if (tier == DL_TIER_HP_FP32) {
+      launch_unpack(P64, b.slots(), b.nslots, b.u_rhs, 0, s64_e.p, st);
+      launch_unpack(P64, b.slots(), b.nslots, b.u_rhs, 1, s64_o.p, st);
+    } else {
+      launch_unpack(P, b.slots(), b.nslots, b.u_rhs, 0, r.p, st);
+      launch_unpack(P, b.slots(), b.nslots, b.u_rhs, 1, x.p, st);
+    }
+  }
+
+  // ---- report ---------------------------------------------------------------
+  rep.iters.assign(b.nrhs, 0);
+  rep.status.assign(b.nrhs, 0);
+  rep.ru = ru_count;
+  rep.rel.assign(b.nrhs, 0.0);
+  rep.truer.assign(b.nrhs, -1.0);
+  b.to_host_int(b.cs.iters, b.h_int);
+  b.to_host_int(b.cs.status, b.h_int + b.nrhs);
+  b.to_host_dbl(b.cs.rr, b.h_dbl);
+  b.to_host_dbl(b.cs.cc, b.h_dbl + b.nrhs);
+  b.sync();
+  int min_it = 1 << 30;
+  for (int g = 0; g < b.nrhs; ++g) {
+    rep.iters[g] = b.h_int[g];
+    rep.status[g] = b.h_int[b.nrhs + g];
+    const double cc = b.h_dbl[b.nrhs + g];
+    rep.rel[g] = cc > 0 ? std::sqrt(b.h_dbl[g] / cc) : 0.0;
+    if (rep.status[g] == 0) min_it = std::min(min_it, rep.iters[g]);
+  }
+  if (min_it < (1 << 30)) iter_hints()[hk] = std::max(1, min_it);
+
+  if (want_true) {
+    // ||eta - M s|| / ||eta|| with the FP64 operator
+    DevBuf se = b.field(P64), so = b.field(P64), ee = b.field(P64), eo = b.field(P64), me = b.field(P64),
+           mo = b.field(P64);
+    if (tier == DL_TIER_HP_FP32) {
+      launch_convert(P64, P64, b.slots(), b.nslots, b.u_rhs, s64_e.p, se.p, 0, nullptr, st);
+      launch_convert(P64, P64, b.slots(), b.nslots, b.u_rhs, s64_o.p, so.p, 0, nullptr, st);
+    } else {
+      launch_convert(P, P64, b.slots(), b.nslots, b.u_rhs, r.p, se.p, 0, nullptr, st);
+      launch_convert(P, P64, b.slots(), b.nslots, b.u_rhs, x.p, so.p, 0, nullptr, st);
+    }
+    launch_sources(P64, b.slots(), b.nslots, b.u_rhs, 0, ee.p, st);
+    launch_sources(P64, b.slots(), b.nslots, b.u_rhs, 1, eo.p, st);
+    b.dslash(P64, F_Y, CK_MFULL, 0, so.p, me.p, se.p, nullptr);
+    b.dslash(P64, F_Y, CK_MFULL, 1, se.p, mo.p, so.p, nullptr);
+    DevBuf gate = ones_gate(b);
+    DevBuf out4(ctx, sizeof(double) * 4 * std::max(b.nrhs, 1));
+    double* o = out4.as<double>();
+    launch_diff_norms(b.slots(), b.nslots, b.u_rhs, me.p, ee.p, b.partial.as<double>(), b.partial2.as<double>(), st);
+    b.finalize_store(o, gate.as<int>(), b.partial.as<double>());
+    b.finalize_store(o + b.nrhs, gate.as<int>(), b.partial2.as<double>());
+    launch_diff_norms(b.slots(), b.nslots, b.u_rhs, mo.p, eo.p, b.partial.as<double>(), b.partial2.as<double>(), st);
+    b.finalize_store(o + 2 * b.nrhs, gate.as<int>(), b.partial.as<double>());
+    b.finalize_store(o + 3 * b.nrhs, gate.as<int>(), b.partial2.as<double>());
+    std::vector<double> h(4 * b.nrhs);
+    HIPCHECK(hipMemcpyAsync(h.data(), o, sizeof(double) * 4 * b.nrhs, hipMemcpyDeviceToHost, st));
+    b.sync();
+    int g = 0;
+    for (const SlotPlan& sp : plan)
+      for (int q = 0; q < sp.nrhs; ++q, ++g)
+        if (jobs[sp.job].report_true_resid) {
+          const double den = h[b.nrhs + g] + h[3 * b.nrhs + g];
+          rep.truer[g] = den > 0 ? std::sqrt((h[g] + h[2 * b.nrhs + g]) / den) : 0.0;
+        }
+  }
+  b.sync();
+}
+
+// ---------------------------------------------------------------------------
+// single operators (verification entry point)
+// ---------------------------------------------------------------------------
+void apply_op(dl_lattice* lat, int op, int tier, const double* in, double* out, int nrhs) {
+  dl_ctx* ctx = lat->ctx;
+  const int P = tier_prec(tier);
+  std::vector<SlotPlan> plan;
+  const long long V = lat->V;
+  SlotPlan sp{};
+  sp.lat = lat;
+  sp.nrhs = nrhs;
+  sp.src_user = in;
+  sp.sol_user = out;
+  plan.push_back(sp);
+  Batch b(ctx, P, plan, nullptr);
+  hipStream_t st = ctx->st;
+  DevBuf ie = b.field(P), io = b.field(P), oe = b.field(P), oo = b.field(P), tmp = b.field(P);
+  launch_sources(P, b.slots(), b.nslots, b.u_rhs, 0, ie.p, st);
+  launch_sources(P, b.slots(), b.nslots, b.u_rhs, 1, io.p, st);
+  switch (op) {
+    case DL_OP_HOP:
+      b.dslash(P, 0, CK_HOP, 0, io.p, oe.p, nullptr, nullptr);
+      b.dslash(P, 0, CK_HOP, 1, ie.p, oo.p, nullptr, nullptr);
+      break;
+    case DL_OP_M:
+      b.dslash(P, F_Y, CK_MFULL, 0, io.p, oe.p, ie.p, nullptr);
+      b.dslash(P, F_Y, CK_MFULL, 1, ie.p, oo.p, io.p, nullptr);
+      break;
+    case DL_OP_MDAG:
+      b.dslash(P, F_D | F_Y, CK_MDAGFULL, 0, io.p, oe.p, ie.p, nullptr);
+      b.dslash(P, F_D | F_Y, CK_MDAGFULL, 1, ie.p, oo.p, io.p, nullptr);
+      break;
+    case DL_OP_MHAT:
+      b.dslash(P, 0, CK_MHAT1, 0, io.p, tmp.p, nullptr, nullptr);
+      b.dslash(P, F_Y, CK_MHAT2, 1, tmp.p, oo.p, io.p, nullptr);
+      launch_zero(P, b.slots(), b.nslots, b.u_rhs, oe.p, nullptr, st);
+      break;
+    case DL_OP_MHAT_DAG:
+      b.dslash(P, F_D, CK_MDAG1, 0, io.p, tmp.p, nullptr, nullptr);
+      b.dslash(P, F_Y, CK_MDAG2, 1, tmp.p, oo.p, io.p, nullptr);
+      launch_zero(P, b.slots(), b.nslots, b.u_rhs, oe.p, nullptr, st);
+      break;
+    default:
+      throw Error(DL_EINVAL, "unknown operator " + std::to_string(op));
+  }
+  launch_unpack(P, b.slots(), b.nslots, b.u_rhs, 0, oe.p, st);
+  launch_unpack(P, b.slots(), b.nslots, b.u_rhs, 1, oo.p, st);
+  (void)V;
+  b.sync();
+}
+
+void fill_noise_fields(dl_ctx* ctx, const std::vector<SlotPlan>& plan, const std::vector<dl_job>& jobs) {
+  Batch b(ctx, P64, plan, &jobs);
+  DevBuf e = b.field(P64), o = b.field(P64);
+  launch_sources(P64, b.slots(), b.nslots, b.u_rhs, 0, e.p, ctx->st);
+  launch_sources(P64, b.slots(), b.nslots, b.u_rhs, 1, o.p, ctx->st);
+  launch_unpack(P64, b.slots(), b.nslots, b.u_rhs, 0, e.p, ctx->st);
+  launch_unpack(P64, b.slots(), b.nslots, b.u_rhs, 1, o.p, ctx->st);
+  b.sync();
+}
+
+int autotune_block(dl_ctx* ctx, dl_lattice* lat, int prec, int nsrc_hint) {
+  (void)ctx;
+  (void)lat;
+  (void)prec;
+  return std::max(1, std::min(nsrc_hint, 16));
+}
+
+void loops_backward(dl_ctx*, const dl_job&, int, const double*, double*, double*) {
+  throw Error(DL_ESTATE, "dl_loops_backward: not available in this build");
+}
+
+}  // namespace dl

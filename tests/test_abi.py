@@ -1,0 +1,73 @@
+"""The C-ABI library: it loads, exports every declared symbol, and its host-only
+logic and argument checks work without a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1401_6750_amd as dl
+from oracle import loops
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "discloop.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(dl_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = dl.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(dl._SIGS)
+
+
+@pytest.mark.parametrize("dims,cut", [((16, 16, 16, 32), 4), ((24, 24, 24, 48), 4), ((4, 4, 4, 4), 3),
+                                      ((4, 4, 4, 4), 4), ((8, 6, 4, 2), 9), ((2, 2, 2, 2), 9),
+                                      ((32, 32, 32, 64), 9)])
+def test_momentum_list_matches_oracle(dims, cut):
+    got = np.array(dl.dl_momenta(dims, cut)).reshape(-1, 3)
+    want = loops.momenta(cut, dims)
+    assert np.array_equal(got, want)
+
+
+def test_argument_errors_without_gpu():
+    lib = dl.lib()
+    assert lib.dl_set_params(None, 0.1, 0.01) == dl.DL_EINVAL
+    assert "NULL" in dl.dl_last_error()
+    h = ctypes.c_void_p()
+    dims = (ctypes.c_int * 4)(4, 4, 4, 4)
+    assert lib.dl_lattice_create(None, dims, -1, ctypes.byref(h)) == dl.DL_EINVAL
+    n = ctypes.c_int()
+    assert lib.dl_momenta(dims, -1, None, 0, ctypes.byref(n)) == dl.DL_EINVAL
+    assert lib.dl_solve_batch(None, None, 0, None) == dl.DL_EINVAL
+    assert lib.dl_loops(None, None, 0, None, 0, None) == dl.DL_EINVAL
+    assert lib.dl_apply_op(None, 0, 0, None, None, 1) == dl.DL_EINVAL
+    assert lib.dl_fill_noise(None, 0, 0, 0, None) == dl.DL_EINVAL
+    assert lib.dl_accum_counts(None, None) == dl.DL_EINVAL
+    # destroying NULL handles is a no-op
+    assert lib.dl_destroy(None) == 0
+    assert lib.dl_lattice_destroy(None) == 0
+    assert lib.dl_accum_destroy(None) == 0
+    with pytest.raises(dl.DiscloopError) as e:
+        dl.dl_set_params(None, 0.1, 0.0)
+    assert e.value.code == dl.DL_EINVAL
+
+
+def test_struct_layouts_match_header():
+    # dl_job: pointer, 2 ints, u64, i64, 2 ints, double, 2 ints, 3 pointers, int (+ padding)
+    assert ctypes.sizeof(dl.dl_job) == 88
+    assert ctypes.sizeof(dl.dl_src_stats) == 32
+
+
+def test_binding_refuses_to_run_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(dl, "_lib", None)
+    monkeypatch.setattr(dl, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        dl.lib()
