@@ -228,7 +228,7 @@ struct Batch {
       d.sol_user = sp.sol_user;
       ur += d.ntile * d.nrhs;
       us += 2 * d.ntile;
-      ud += 16 * d.ntile;
+      ud += 8 * d.ntile;
       rb += d.nrhs;
       fo += (long long)d.nrhs * d.Vh;
       hs.push_back(d);
@@ -366,7 +366,7 @@ static void contract_passes(Batch& b, int P, const void* s_e, const void* s_o, c
       d.ubeg[UK_SITE] = us;
       d.ubeg[UK_DERIV] = ud;
       us += 2 * d.ntile;
-      ud += 16 * d.ntile;
+      ud += 8 * d.ntile;
     }
     DevBuf ds(b.ctx, sizeof(SlotDesc) * pass.size());
     HIPCHECK(hipMemcpyAsync(ds.p, pass.data(), sizeof(SlotDesc) * pass.size(), hipMemcpyHostToDevice, b.ctx->st));
@@ -574,7 +574,7 @@ void run_batch(dl_ctx* ctx, int tier, const std::vector<SlotPlan>& plan, const s
           maxit[g] = jobs[sp.job].maxiter;
         }
     }
-    const double delta2 = 0.01;   // reliable update when ||r|| fell by 10x since the last one
+    const double delta2 = 1e-4;   // reliable update when ||r|| fell by 100x since the last one
     int guard = 0;
     while (true) {
       // state after the previous step
