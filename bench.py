@@ -114,7 +114,14 @@ def main() -> int:
         step()
         torch.cuda.synchronize()
         pr = dl.dl_profile_read(ctx, dl.DL_TIER_LP_BF16)
-        log(f"profile: {pr}")
+        log(f"profile: launches {pr[0]:.0f}, kernel ms {pr[1]:.3f}, alg bytes {pr[2]:.0f}, rhs {pr[3]:.0f}")
+        # calibration kernel of known traffic for the HBM byte counters:
+        # reads 1 GiB and writes 1 GiB (torch's elementwise multiply)
+        x = torch.ones(2 ** 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.mul(x, 2.0, out=y)
+        torch.cuda.synchronize()
+        log("calibration: elementwise multiply, 1073741824 bytes read, 1073741824 bytes written")
         return 0
 
     for i in range(a.warmup):

@@ -184,13 +184,19 @@ int dl_momenta(const int dims[4], int p2max, int* n_xyz, int cap, int* np_out);
 int dl_loops(dl_ctx* ctx, dl_accum* acc, int p2max, double* out, int out_on_device,
              int* np_out);
 
-/* Gradients of loops built from caller sources (DL_NOISE_USER, FP64 or
- * HP_FP32 tier) with respect to the sources and to mu: given
- * grad_loops = dF/dL^* for the loops L = dl_loops(...) of those sources
- * (complex128 [2][nops][16][T][Np], host), write dF/deta^* (device complex128
- * [nsrc][V][12], optional) and dF/dmu (host double, optional), by adjoint
- * solves with M^dag = gamma_5 M(-mu) gamma_5 (conjugate-Wirtinger
- * convention, F real). */
+/* Gradients of the loops of one job's sources with respect to the sources and
+ * to mu, for a real loss F.  The loops are the plain estimator over the job's
+ * nsrc sources (what dl_loops returns for an accumulator that holds only
+ * them); nops is that of job->accum (5 if job->accum is NULL).
+ * Complex gradients follow PyTorch's convention, dF/dRe z + i dF/dIm z:
+ *   grad_loops  host complex128 [2][nops][16][T][Np], the gradient of F with
+ *               respect to the loops;
+ *   grad_eta    device complex128 [nsrc][V][12] (optional): gradient with
+ *               respect to the sources eta (job->src_in for USER noise);
+ *   grad_mu     host double (optional): dF/dmu.
+ * If job->sol_out is set it must hold the solutions of the forward call
+ * (checkpoint) and is read; otherwise they are recomputed.  One adjoint solve
+ * per source, M^dag = gamma_5 M(-mu) gamma_5, at job->tier and job->tol. */
 int dl_loops_backward(dl_ctx* ctx, const dl_job* job, int p2max, const double* grad_loops,
                       double* grad_eta, double* grad_mu);
 

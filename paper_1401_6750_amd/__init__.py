@@ -239,3 +239,65 @@ def dl_apply_op(lat, op: int, tier: int, inp, out, nrhs: int) -> None:
 
 def dl_fill_noise(lat, noise: int, seed: int, src: int, out) -> None:
     _check(lib().dl_fill_noise(lat, noise, seed, src, _ptr(out)))
+
+
+def _make_disc_loops():
+    import torch
+
+    class DiscLoops(torch.autograd.Function):
+        """Loops of caller sources as a differentiable function of (eta, mu).
+
+        forward(eta, mu, ctx, lat, kappa, p2max, ops, tier, tol) -> loops
+          eta: complex128 CUDA tensor [nsrc, T, Z, Y, X, 4, 3]; mu: real 0-d tensor.
+          Returns the plain estimator over the sources, complex128 CUDA
+          [2, nops, 16, T, Np] (dl_loops layout).  The solutions are kept for
+          the backward pass (checkpoint), which calls dl_loops_backward.
+        """
+
+        @staticmethod
+        def forward(fctx, eta, mu, dlctx, lat, kappa, p2max, ops, tier, tol):
+            mu_v = float(mu)
+            dl_set_params(lat, kappa, mu_v)
+            eta = eta.contiguous()
+            nsrc = eta.shape[0]
+            acc = dl_accum_create(lat, ops)
+            sol = torch.empty_like(eta)
+            job = make_job(lat, noise=DL_NOISE_USER, tier=tier, nsrc=nsrc, tol=tol, maxiter=10000,
+                           src_in=eta, sol_out=sol, accum=acc, accum_set=DL_SET_HP)
+            dl_solve_batch(dlctx, job)
+            T = eta.shape[1]
+            nops = 5 if ops & DL_OPS_DERIV else 1
+            np_ = len(dl_momenta((eta.shape[4], eta.shape[3], eta.shape[2], T), p2max))
+            out = torch.empty((2, nops, 16, T, np_), dtype=torch.complex128, device=eta.device)
+            dl_loops(dlctx, acc, p2max, out, 1)
+            torch.cuda.current_stream().synchronize()
+            fctx.save_for_backward(eta, sol)
+            fctx.meta = (dlctx, lat, kappa, mu_v, p2max, acc, tier, tol)
+            return out
+
+        @staticmethod
+        def backward(fctx, gout):
+            eta, sol = fctx.saved_tensors
+            dlctx, lat, kappa, mu_v, p2max, acc, tier, tol = fctx.meta
+            dl_set_params(lat, kappa, mu_v)
+            g_host = gout.detach().to("cpu", torch.complex128).contiguous().numpy()
+            grad_eta = torch.empty_like(eta)
+            gmu = ctypes.c_double()
+            job = make_job(lat, noise=DL_NOISE_USER, tier=tier, nsrc=eta.shape[0], tol=tol, maxiter=10000,
+                           src_in=eta, sol_out=sol, accum=acc)
+            _check(lib().dl_loops_backward(dlctx, ctypes.byref(job), p2max, g_host.ctypes.data,
+                                           grad_eta.data_ptr(), ctypes.addressof(gmu)))
+            torch.cuda.current_stream().synchronize()
+            dl_accum_destroy(acc)
+            grad_mu = torch.tensor(gmu.value, dtype=torch.float64)
+            return grad_eta, grad_mu, None, None, None, None, None, None, None
+
+    return DiscLoops
+
+
+def __getattr__(name):
+    if name == "DiscLoops":
+        cls = _make_disc_loops()
+        globals()["DiscLoops"] = cls
+        return cls
+    raise AttributeError(name)

@@ -1,6 +1,7 @@
 // The C ABI (include/discloop.h): argument checks, job planning and error
 // translation.  No C++ exception crosses this boundary.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -98,7 +99,7 @@ int dl_lattice_create(dl_ctx* ctx, const int dims[4], int t_bc, dl_lattice** out
     L->Vh = V / 2;
     try {
       for (int p = 0; p < 4; ++p) {
-        const size_t bytes = (size_t)V * 4 * 9 * link_bytes(p);
+        const size_t bytes = (size_t)V * 4 * link_chunks(p) * 16;
         if (hipMalloc(&L->gauge[p], bytes) != hipSuccess) {
           (void)hipGetLastError();
           throw Error(DL_ENOMEM, "dl_lattice_create: gauge allocation failed");
@@ -280,70 +281,7 @@ int dl_solve_batch(dl_ctx* ctx, const dl_job* jobs, int njobs, dl_src_stats* sta
       first_stat[j + 1] = first_stat[j] + q.nsrc;
     }
     stream_enter(ctx);
-    bool all_ok = true;
-    const double budget = ctx->inflight_mb * 1048576.0;
-    const int max_rhs = ctx->inflight_rhs;
-    const int tiers[4] = {DL_TIER_FP64, DL_TIER_LP_BF16, DL_TIER_LP_FP16, DL_TIER_HP_FP32};
-    for (int tier : tiers) {
-      std::vector<SlotPlan> all;
-      for (int j = 0; j < njobs; ++j) {
-        const dl_job& q = J[j];
-        if (q.tier != tier || q.nsrc == 0) continue;
-        const int P = tier_prec(tier);
-        const int N = q.rhs_block > 0 ? q.rhs_block : autotune_block(ctx, q.lat, P, q.nsrc);
-        const long long V = q.lat->V;
-        for (int k = 0; k < q.nsrc; k += N) {
-          SlotPlan sp{};
-          sp.lat = q.lat;
-          sp.job = j;
-          sp.job_first = k;
-          sp.nrhs = std::min(N, q.nsrc - k);
-          sp.src0 = q.first_src + k;
-          sp.src_user = q.src_in ? q.src_in + (size_t)k * V * 24 : nullptr;
-          sp.sol_user = q.sol_out ? q.sol_out + (size_t)k * V * 24 : nullptr;
-          sp.acc = q.accum ? q.accum->acc[q.accum_set] : nullptr;
-          all.push_back(sp);
-        }
-      }
-      // waves bounded by device memory and rhs count
-      size_t i = 0;
-      while (i < all.size()) {
-        std::vector<SlotPlan> wave;
-        double bytes = 0;
-        int nrhs = 0;
-        while (i < all.size()) {
-          const SlotPlan& sp = all[i];
-          const int P = tier_prec(tier);
-          double per = (double)sp.lat->Vh * sp.nrhs * (7.0 * chunks_of(P) * 16);
-          if (tier == DL_TIER_HP_FP32) per += (double)sp.lat->Vh * sp.nrhs * 9.0 * 192;
-          if (J[sp.job].report_true_resid) per += (double)sp.lat->Vh * sp.nrhs * 6.0 * 192;
-          if (!wave.empty() && (bytes + per > budget || nrhs + sp.nrhs > max_rhs)) break;
-          wave.push_back(sp);
-          bytes += per;
-          nrhs += sp.nrhs;
-          ++i;
-        }
-        SolveReport rep;
-        run_batch(ctx, tier, wave, J, rep);
-        int g = 0;
-        for (const SlotPlan& sp : wave) {
-          for (int r = 0; r < sp.nrhs; ++r, ++g) {
-            if (rep.status[g] != 0) all_ok = false;
-            if (stats) {
-              dl_src_stats& s = stats[first_stat[sp.job] + sp.job_first + r];
-              s.iters = rep.iters[g];
-              s.status = rep.status[g];
-              s.rel_resid = rep.rel[g];
-              s.true_resid = rep.truer[g];
-              s.reliable_updates = rep.ru[g];
-              s.pad = 0;
-            }
-          }
-          const dl_job& q = J[sp.job];
-          if (q.accum) q.accum->count[q.accum_set] += sp.nrhs;
-        }
-      }
-    }
+    const bool all_ok = solve_jobs(ctx, J, stats);
     HIPCHECK(hipGetLastError());
     stream_exit(ctx);
     return all_ok ? 0 : DL_NOT_CONVERGED;

@@ -376,14 +376,18 @@ __global__ __launch_bounds__(256) void k_pack_gauge(const double* src, int X, in
   const int par = (x + y + z + t) & 1;
   const long long s = lex >> 1;
   const double2* u = (const double2*)src + (lex * 4 + mu) * 9;
-  for (int e = 0; e < 9; ++e) {
-    const double2 q = u[e];
-    const long long o = ((long long)(mu * 2 + par) * 9 + e) * vh + s;
-    ((double2*)g64)[o] = q;
-    ((float2*)g32)[o] = make_float2((float)q.x, (float)q.y);
+  const long long rec = (long long)(mu * 2 + par) * vh + s;   // link record index
+  double2* r64 = (double2*)g64 + rec * 9;
+  float2* r32 = (float2*)g32 + rec * 10;                      // 5 chunks = 10 complex
+  uint32_t* rb = (uint32_t*)gb16 + rec * 12;                  // 3 chunks = 12 complex
+  uint32_t* rh = (uint32_t*)gh16 + rec * 12;
+  for (int e = 0; e < 12; ++e) {
+    const double2 q = e < 9 ? u[e] : make_double2(0.0, 0.0);  // zero padding
+    if (e < 9) r64[e] = q;
+    if (e < 10) r32[e] = make_float2((float)q.x, (float)q.y);
     const cx<float> qf = mk<float>((float)q.x, (float)q.y);
-    ((uint32_t*)gb16)[o] = pack2<bf16s>(qf);
-    ((uint32_t*)gh16)[o] = pack2<f16s>(qf);
+    rb[e] = pack2<bf16s>(qf);
+    rh[e] = pack2<f16s>(qf);
   }
 }
 

@@ -31,7 +31,6 @@ template <> struct Traits<bf16s> { using R = float; static constexpr int NC = 3;
 template <> struct Traits<f16s> { using R = float; static constexpr int NC = 3; static constexpr int prec = PH16; };
 
 inline int chunks_of(int prec) { return prec == P64 ? 12 : (prec == P32 ? 6 : 3); }
-inline int link_bytes(int prec) { return prec == P64 ? 16 : (prec == P32 ? 8 : 4); }
 
 constexpr int TILE = 64;        // sites per unit (one wavefront)
 
@@ -40,11 +39,16 @@ constexpr int TILE = 64;        // sites per unit (one wavefront)
 // ---------------------------------------------------------------------------
 template <class R> struct cx { R re, im; };
 
+// Products are written as explicit fused multiply-adds: without reassociation
+// the compiler cannot turn  a += b*c - d*e  into two FMAs on its own.
+__device__ inline float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <class R> __host__ __device__ inline cx<R> mk(R a, R b) { return cx<R>{a, b}; }
 template <class R> __device__ inline cx<R> operator+(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }
 template <class R> __device__ inline cx<R> operator-(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }
 template <class R> __device__ inline cx<R> operator*(cx<R> a, cx<R> b) {
-  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+  return {fmadd(a.re, b.re, -(a.im * b.im)), fmadd(a.re, b.im, a.im * b.re)};
 }
 template <class R> __device__ inline cx<R> operator*(R s, cx<R> a) { return {s * a.re, s * a.im}; }
 template <class R> __device__ inline cx<R> conj(cx<R> a) { return {a.re, -a.im}; }
@@ -52,40 +56,43 @@ template <class R> __device__ inline cx<R> times_i(cx<R> a) { return {-a.im, a.r
 template <class R> __device__ inline cx<R> times_mi(cx<R> a) { return {a.im, -a.re}; }
 // a += conj(b) * c
 template <class R> __device__ inline void cjmac(cx<R>& a, cx<R> b, cx<R> c) {
-  a.re += b.re * c.re + b.im * c.im;
-  a.im += b.re * c.im - b.im * c.re;
+  a.re = fmadd(b.im, c.im, fmadd(b.re, c.re, a.re));
+  a.im = fmadd(-b.im, c.re, fmadd(b.re, c.im, a.im));
 }
 // a += b * c
 template <class R> __device__ inline void cmac(cx<R>& a, cx<R> b, cx<R> c) {
-  a.re += b.re * c.re - b.im * c.im;
-  a.im += b.re * c.im + b.im * c.re;
+  a.re = fmadd(-b.im, c.im, fmadd(b.re, c.re, a.re));
+  a.im = fmadd(b.im, c.re, fmadd(b.re, c.im, a.im));
 }
 
 // ---------------------------------------------------------------------------
 // 16-bit conversions (round to nearest even)
 // ---------------------------------------------------------------------------
-__device__ inline float bf16_to_f(uint32_t h) { return __uint_as_float(h << 16); }
-__device__ inline uint32_t f_to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x7fffffu)) return 0x7fc0u;  // NaN
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return u >> 16;
-}
 __device__ inline float f16_to_f(uint32_t h) {
   _Float16 v = __builtin_bit_cast(_Float16, (uint16_t)h);
   return (float)v;
 }
-__device__ inline uint32_t f_to_f16(float f) {
-  _Float16 v = (_Float16)f;
-  return (uint32_t)__builtin_bit_cast(uint16_t, v);
-}
+
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
 
 template <class S> __device__ inline cx<float> unpack2(uint32_t w);
-template <> __device__ inline cx<float> unpack2<bf16s>(uint32_t w) { return {bf16_to_f(w & 0xffffu), bf16_to_f(w >> 16)}; }
+template <> __device__ inline cx<float> unpack2<bf16s>(uint32_t w) {
+  return {__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u)};
+}
 template <> __device__ inline cx<float> unpack2<f16s>(uint32_t w) { return {f16_to_f(w & 0xffffu), f16_to_f(w >> 16)}; }
+// (re, im) -> one dword with two 16-bit values, hardware round-to-nearest-even
+// conversion of both halves in one instruction
 template <class S> __device__ inline uint32_t pack2(cx<float> v);
-template <> __device__ inline uint32_t pack2<bf16s>(cx<float> v) { return f_to_bf16(v.re) | (f_to_bf16(v.im) << 16); }
-template <> __device__ inline uint32_t pack2<f16s>(cx<float> v) { return f_to_f16(v.re) | (f_to_f16(v.im) << 16); }
+template <> __device__ inline uint32_t pack2<bf16s>(cx<float> v) {
+  const f32x2_t x = {v.re, v.im};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(x, bf16x2_t));
+}
+template <> __device__ inline uint32_t pack2<f16s>(cx<float> v) {
+  const f32x2_t x = {v.re, v.im};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(x, f16x2_t));
+}
 
 // ---------------------------------------------------------------------------
 // spinor loads / stores: base points at chunk 0 of one (rhs, parity) half
@@ -204,34 +211,44 @@ template <class S> __device__ inline void* field_at(void* base, long long off) {
 }
 
 // ---------------------------------------------------------------------------
-// gauge links: 9 complex entries, row-major
+// gauge links: one record per (mu, parity, site) = the 9 complex entries of
+// the 3x3 matrix, row-major, padded to whole 16-byte chunks (FP64 9 chunks,
+// FP32 5, 16-bit 3) so a lane fetches its link with 3-9 vector loads from one
+// address.  Record index (mu * 2 + parity) * Vh + site.
 // ---------------------------------------------------------------------------
+inline int link_chunks(int prec) { return prec == P64 ? 9 : (prec == P32 ? 5 : 3); }
+
 template <class S>
 __device__ inline void load_link(const void* g, long vh, int mu, int par, long s, cx<typename Traits<S>::R> (&u)[9]);
 
 template <>
 __device__ inline void load_link<double>(const void* g, long vh, int mu, int par, long s, cx<double> (&u)[9]) {
-  const double2* p = (const double2*)g + (long)(mu * 2 + par) * 9 * vh;
+  const double2* p = (const double2*)g + ((long)(mu * 2 + par) * vh + s) * 9;
 #pragma unroll
   for (int e = 0; e < 9; ++e) {
-    double2 w = p[e * vh + s];
+    double2 w = p[e];
     u[e] = {w.x, w.y};
   }
 }
 template <>
 __device__ inline void load_link<float>(const void* g, long vh, int mu, int par, long s, cx<float> (&u)[9]) {
-  const float2* p = (const float2*)g + (long)(mu * 2 + par) * 9 * vh;
+  const float4* p = (const float4*)g + ((long)(mu * 2 + par) * vh + s) * 5;
 #pragma unroll
-  for (int e = 0; e < 9; ++e) {
-    float2 w = p[e * vh + s];
-    u[e] = {w.x, w.y};
+  for (int k = 0; k < 4; ++k) {
+    float4 w = p[k];
+    u[2 * k] = {w.x, w.y};
+    u[2 * k + 1] = {w.z, w.w};
   }
+  float4 w = p[4];
+  u[8] = {w.x, w.y};
 }
 template <class S16>
 __device__ inline void load_link16(const void* g, long vh, int mu, int par, long s, cx<float> (&u)[9]) {
-  const uint32_t* p = (const uint32_t*)g + (long)(mu * 2 + par) * 9 * vh;
-#pragma unroll
-  for (int e = 0; e < 9; ++e) u[e] = unpack2<S16>(p[e * vh + s]);
+  const uint4* p = (const uint4*)g + ((long)(mu * 2 + par) * vh + s) * 3;
+  const uint4 a = p[0], b = p[1], c = p[2];
+  u[0] = unpack2<S16>(a.x); u[1] = unpack2<S16>(a.y); u[2] = unpack2<S16>(a.z); u[3] = unpack2<S16>(a.w);
+  u[4] = unpack2<S16>(b.x); u[5] = unpack2<S16>(b.y); u[6] = unpack2<S16>(b.z); u[7] = unpack2<S16>(b.w);
+  u[8] = unpack2<S16>(c.x);
 }
 template <>
 __device__ inline void load_link<bf16s>(const void* g, long vh, int mu, int par, long s, cx<float> (&u)[9]) {
@@ -245,12 +262,16 @@ __device__ inline void load_link<f16s>(const void* g, long vh, int mu, int par, 
 // ---------------------------------------------------------------------------
 // batch slots
 // ---------------------------------------------------------------------------
-enum UnitKind : int { UK_RHS = 0, UK_SITE = 1, UK_DERIV = 2 };
+// Unit kinds: UK_RHS (one tile x one rhs), UK_SITE (one tile x one parity),
+// UK_DERIV (one tile x parity x direction), UK_GRP (one tile x RG rhs: the
+// hopping kernel runs RG right-hand sides per wavefront).
+enum UnitKind : int { UK_RHS = 0, UK_SITE = 1, UK_DERIV = 2, UK_GRP = 3 };
+constexpr int RG = 2;
 
 struct SlotDesc {
   int X, Y, Z, T;
   int Xh, Vh, ntile, nrhs;
-  int ubeg[3];             // first unit of this slot per UnitKind
+  int ubeg[4];             // first unit of this slot per UnitKind
   int rhs_begin;           // global index of this slot's rhs 0
   long long fo;            // site offset of rhs 0 in every batch field
   double bc;               // time-boundary factor
@@ -265,9 +286,9 @@ struct SlotDesc {
 };
 
 // Per-slot site-diagonal spin coefficients of one dslash-type launch:
-//   out = e (.) H(d (.) in) + f (.) y     (per-spin complex factors)
+//   res = e (.) H(d (.) in) + f (.) y,  out = g (.) res   (per-spin complex factors)
 struct Coef {
-  double d[4][2], e[4][2], f[4][2];
+  double d[4][2], e[4][2], f[4][2], g[4][2];
 };
 
 // Hardware dispatches workgroup b to XCD (b mod 8); renumber so that each XCD

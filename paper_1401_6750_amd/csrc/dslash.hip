@@ -1,10 +1,15 @@
 // Even-odd twisted-mass Wilson hopping kernel with fused site-local epilogues.
 //
-// One wavefront handles one unit = 64 consecutive even-odd sites of one
-// right-hand side of one batch slot; units of one tile are consecutive for all
-// right-hand sides of the slot, and each XCD receives a contiguous range of
-// units, so a tile's gauge links are fetched once into that XCD's L2 and
-// reused by every right-hand side.
+// One wavefront handles one unit = 64 consecutive even-odd sites of RG right-
+// hand sides of one batch slot: the site coordinates, the eight neighbour
+// indices and every gauge link are computed / loaded once and used for all RG
+// right-hand sides.  Units of one tile are consecutive for all right-hand-side
+// groups of the slot, and each XCD receives a contiguous range of units, so a
+// tile's links are fetched once into that XCD's L2.  In 16-bit storage the
+// kernel is bound by instruction issue rather than HBM bandwidth, so the
+// design minimises per-(site, rhs) work that is not arithmetic of the hop:
+// conversions use the packed hardware converts, neighbour indices are
+// offsets of the lexicographic index.
 //
 // Operator pieces (kappa normalised, chiral basis, gamma_5 = diag(1,1,-1,-1)):
 //   (H psi)(x) = sum_mu (1 - gamma_mu) U_mu(x) psi(x+mu) + (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu)
@@ -13,8 +18,8 @@
 // rebuilt from them, so each neighbour costs two SU(3) x colour products.
 //
 // Epilogue (per-spin complex factors, set per slot):
-//   result = e (.) H(d (.) in) + f (.) y
-// optionally followed by the CG update x += alpha p, r -= alpha result.
+//   res = e (.) H(d (.) in) + f (.) y,   out = g (.) res
+// optionally followed by the CG update x += alpha p, r -= alpha res.
 #include <stdexcept>
 
 #include "kernels.h"
@@ -90,70 +95,45 @@ __device__ inline void reconstruct(cx<R> (&acc)[12], const cx<R> (&w0)[3], const
   }
 }
 
-template <class S, int MU, bool HAS_D>
-__device__ inline void hop_dir(const SlotDesc& sd, const void* gauge, const void* inb, const Coords& c,
-                               int s, int p_out, const cx<typename Traits<S>::R> (&d)[4],
-                               cx<typename Traits<S>::R> (&acc)[12]) {
+// One hop (direction MU, forward or backward) for every right-hand side of
+// the group: the link is loaded once.
+template <class S, int MU, bool FWD, bool HAS_D>
+__device__ inline void hop(const void* gauge, long vh, int link_par, int link_site, int nb, typename Traits<S>::R sign,
+                           const void* const (&inb)[RG], int nr, const bool (&act)[RG],
+                           const cx<typename Traits<S>::R> (&d)[4], cx<typename Traits<S>::R> (&acc)[RG][12]) {
   using R = typename Traits<S>::R;
-  const long vh = sd.Vh;
-  // forward neighbour x + mu
-  {
-    int xn = c.x, yn = c.y, zn = c.z, tn = c.t;
-    R sign = 1;
-    if (MU == 0) xn = (c.x + 1 == sd.X) ? 0 : c.x + 1;
-    if (MU == 1) yn = (c.y + 1 == sd.Y) ? 0 : c.y + 1;
-    if (MU == 2) zn = (c.z + 1 == sd.Z) ? 0 : c.z + 1;
-    if (MU == 3) {
-      if (c.t + 1 == sd.T) { tn = 0; sign = (R)sd.bc; } else tn = c.t + 1;
-    }
-    int sn = eo_index(sd, xn, yn, zn, tn);
+  cx<R> u[9];
+  load_link<S>(gauge, vh, MU, link_par, link_site, u);
+  if (MU == 3) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) u[k] = sign * u[k];
+  }
+#pragma unroll
+  for (int i = 0; i < RG; ++i) {
+    if (i >= nr || !act[i]) continue;
     cx<R> v[12];
-    load_spinor<S>(inb, vh, sn, v);
+    load_spinor<S>(inb[i], vh, nb, v);
     if (HAS_D) {
 #pragma unroll
       for (int k = 0; k < 12; ++k) v[k] = d[k / 3] * v[k];
     }
     cx<R> h0[3], h1[3], w0[3], w1[3];
-    project<MU, true>(v, h0, h1);
-    cx<R> u[9];
-    load_link<S>(gauge, vh, MU, p_out, s, u);
-    if (MU == 3) {
-#pragma unroll
-      for (int k = 0; k < 9; ++k) u[k] = sign * u[k];
+    project<MU, FWD>(v, h0, h1);
+    if (FWD) {
+      su3_mul(u, h0, w0);
+      su3_mul(u, h1, w1);
+    } else {
+      su3_dag_mul(u, h0, w0);
+      su3_dag_mul(u, h1, w1);
     }
-    su3_mul(u, h0, w0);
-    su3_mul(u, h1, w1);
-    reconstruct<MU, true>(acc, w0, w1);
+    reconstruct<MU, FWD>(acc[i], w0, w1);
   }
-  // backward neighbour x - mu
-  {
-    int xn = c.x, yn = c.y, zn = c.z, tn = c.t;
-    R sign = 1;
-    if (MU == 0) xn = (c.x == 0) ? sd.X - 1 : c.x - 1;
-    if (MU == 1) yn = (c.y == 0) ? sd.Y - 1 : c.y - 1;
-    if (MU == 2) zn = (c.z == 0) ? sd.Z - 1 : c.z - 1;
-    if (MU == 3) {
-      if (c.t == 0) { tn = sd.T - 1; sign = (R)sd.bc; } else tn = c.t - 1;
-    }
-    int sn = eo_index(sd, xn, yn, zn, tn);
-    cx<R> v[12];
-    load_spinor<S>(inb, vh, sn, v);
-    if (HAS_D) {
+}
+
+template <class R>
+__device__ inline void load_coef(const double (&c)[4][2], cx<R> (&out)[4]) {
 #pragma unroll
-      for (int k = 0; k < 12; ++k) v[k] = d[k / 3] * v[k];
-    }
-    cx<R> h0[3], h1[3], w0[3], w1[3];
-    project<MU, false>(v, h0, h1);
-    cx<R> u[9];
-    load_link<S>(gauge, vh, MU, 1 - p_out, sn, u);
-    if (MU == 3) {
-#pragma unroll
-      for (int k = 0; k < 9; ++k) u[k] = sign * u[k];
-    }
-    su3_dag_mul(u, h0, w0);
-    su3_dag_mul(u, h1, w1);
-    reconstruct<MU, false>(acc, w0, w1);
-  }
+  for (int k = 0; k < 4; ++k) out[k] = mk<R>((R)c[k][0], (R)c[k][1]);
 }
 
 template <class S, int F>
@@ -162,72 +142,121 @@ __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
   const int u = xcd_logical_block() * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (u >= a.total_units) return;
   const int lane = threadIdx.x & 63;
-  const int si = find_slot(a.slots, a.nslots, UK_RHS, u);
+  const int si = find_slot(a.slots, a.nslots, UK_GRP, u);
   const SlotDesc& sd = a.slots[si];
-  const int ul = u - sd.ubeg[UK_RHS];
-  const int tile = ul / sd.nrhs;
-  const int r = ul - tile * sd.nrhs;
-  const int g = sd.rhs_begin + r;
-  if (a.active && !a.active[g]) return;
+  const int ngrp = (sd.nrhs + RG - 1) / RG;
+  const int ul = u - sd.ubeg[UK_GRP];
+  const int tile = ul / ngrp;
+  const int r0 = (ul - tile * ngrp) * RG;
+  const int nr = min(RG, sd.nrhs - r0);
+  bool act[RG];
+  bool any = false;
+#pragma unroll
+  for (int i = 0; i < RG; ++i) {
+    act[i] = i < nr && (!a.active || a.active[sd.rhs_begin + r0 + i]);
+    any = any || act[i];
+  }
+  if (!any) return;
   const int s = tile * TILE + lane;
   const bool valid = s < sd.Vh;
   const long vh = sd.Vh;
-  const long long off = sd.fo + (long long)r * vh;
-  double nrm = 0.0;
+  long long off[RG];
+#pragma unroll
+  for (int i = 0; i < RG; ++i) off[i] = sd.fo + (long long)(r0 + i) * vh;
+  double nrm[RG];
+#pragma unroll
+  for (int i = 0; i < RG; ++i) nrm[i] = 0.0;
   if (valid) {
     const Coef& cf = a.coef[si];
-    cx<R> d[4], e[4], f[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      d[k] = mk<R>((R)cf.d[k][0], (R)cf.d[k][1]);
-      e[k] = mk<R>((R)cf.e[k][0], (R)cf.e[k][1]);
-      f[k] = mk<R>((R)cf.f[k][0], (R)cf.f[k][1]);
-    }
-    const Coords c = eo_coords(sd, s, a.p_out);
+    cx<R> d[4], e[4], f[4], g[4];
+    load_coef(cf.d, d);
+    load_coef(cf.e, e);
+    load_coef(cf.f, f);
+    load_coef(cf.g, g);
+    const int p_out = a.p_out;
+    const Coords c = eo_coords(sd, s, p_out);
+    // neighbour even-odd indices from the lexicographic index: a step along
+    // y, z or t moves lex by an even stride, one along x flips the parity bit
+    const int X = sd.X, XY = sd.X * sd.Y, XYZ = XY * sd.Z;
+    const int lex = c.x + X * c.y + XY * c.z + XYZ * c.t;
+    const int nxp = (c.x + 1 == sd.X ? lex - (X - 1) : lex + 1) >> 1;
+    const int nxm = (c.x == 0 ? lex + (X - 1) : lex - 1) >> 1;
+    const int nyp = (c.y + 1 == sd.Y ? lex - (XY - X) : lex + X) >> 1;
+    const int nym = (c.y == 0 ? lex + (XY - X) : lex - X) >> 1;
+    const int nzp = (c.z + 1 == sd.Z ? lex - (XYZ - XY) : lex + XY) >> 1;
+    const int nzm = (c.z == 0 ? lex + (XYZ - XY) : lex - XY) >> 1;
+    const int VV = XYZ * sd.T;
+    const int ntp = (c.t + 1 == sd.T ? lex - (VV - XYZ) : lex + XYZ) >> 1;
+    const int ntm = (c.t == 0 ? lex + (VV - XYZ) : lex - XYZ) >> 1;
+    const R sp = (c.t + 1 == sd.T) ? (R)sd.bc : (R)1;
+    const R sm = (c.t == 0) ? (R)sd.bc : (R)1;
     const void* gauge = sd.gauge[Traits<S>::prec];
-    const void* inb = field_at<S>(a.in, off);
-    cx<R> acc[12];
+    const void* inb[RG];
 #pragma unroll
-    for (int k = 0; k < 12; ++k) acc[k] = mk<R>(0, 0);
+    for (int i = 0; i < RG; ++i) inb[i] = field_at<S>(a.in, off[i]);
+    cx<R> acc[RG][12];
+#pragma unroll
+    for (int i = 0; i < RG; ++i)
+#pragma unroll
+      for (int k = 0; k < 12; ++k) acc[i][k] = mk<R>(0, 0);
     constexpr bool HD = (F & F_D) != 0;
-    hop_dir<S, 0, HD>(sd, gauge, inb, c, s, a.p_out, d, acc);
-    hop_dir<S, 1, HD>(sd, gauge, inb, c, s, a.p_out, d, acc);
-    hop_dir<S, 2, HD>(sd, gauge, inb, c, s, a.p_out, d, acc);
-    hop_dir<S, 3, HD>(sd, gauge, inb, c, s, a.p_out, d, acc);
-    cx<R> res[12];
+    const int q = 1 - p_out;
+    hop<S, 0, true, HD>(gauge, vh, p_out, s, nxp, (R)1, inb, nr, act, d, acc);
+    hop<S, 0, false, HD>(gauge, vh, q, nxm, nxm, (R)1, inb, nr, act, d, acc);
+    hop<S, 1, true, HD>(gauge, vh, p_out, s, nyp, (R)1, inb, nr, act, d, acc);
+    hop<S, 1, false, HD>(gauge, vh, q, nym, nym, (R)1, inb, nr, act, d, acc);
+    hop<S, 2, true, HD>(gauge, vh, p_out, s, nzp, (R)1, inb, nr, act, d, acc);
+    hop<S, 2, false, HD>(gauge, vh, q, nzm, nzm, (R)1, inb, nr, act, d, acc);
+    hop<S, 3, true, HD>(gauge, vh, p_out, s, ntp, sp, inb, nr, act, d, acc);
+    hop<S, 3, false, HD>(gauge, vh, q, ntm, ntm, sm, inb, nr, act, d, acc);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) res[k] = e[k / 3] * acc[k];
-    if (F & F_Y) {
-      cx<R> yv[12];
-      load_spinor<S>(field_at<S>(a.y, off), vh, s, yv);
+    for (int i = 0; i < RG; ++i) {
+      if (!act[i]) continue;
+      cx<R> res[12];
 #pragma unroll
-      for (int k = 0; k < 12; ++k) res[k] = res[k] + f[k / 3] * yv[k];
-    }
-    if (F & F_XR) {
-      const R al = (R)a.alpha[g];
-      cx<R> xv[12], rv[12], pv[12];
-      load_spinor<S>(field_at<S>(a.x, off), vh, s, xv);
-      load_spinor<S>(field_at<S>(a.r, off), vh, s, rv);
-      load_spinor<S>(field_at<S>(a.p, off), vh, s, pv);
+      for (int k = 0; k < 12; ++k) res[k] = e[k / 3] * acc[i][k];
+      if (F & F_Y) {
+        cx<R> yv[12];
+        load_spinor<S>(field_at<S>(a.y, off[i]), vh, s, yv);
 #pragma unroll
-      for (int k = 0; k < 12; ++k) {
-        xv[k] = xv[k] + al * pv[k];
-        rv[k] = rv[k] - al * res[k];
+        for (int k = 0; k < 12; ++k) res[k] = res[k] + f[k / 3] * yv[k];
       }
-      store_spinor<S>(field_at<S>(a.x, off), vh, s, xv);
-      quantize<S>(rv);                       // the norm is that of the stored residual
-      store_spinor<S>(field_at<S>(a.r, off), vh, s, rv);
-      if (F & F_NORM) nrm = norm2(rv);
-    } else {
-      quantize<S>(res);
-      store_spinor<S>(field_at<S>(a.out, off), vh, s, res);
-      if (F & F_OUT2) store_spinor<S>(field_at<S>(a.out2, off), vh, s, res);
-      if (F & F_NORM) nrm = norm2(res);
+      if (F & F_XR) {
+        const R al = (R)a.alpha[sd.rhs_begin + r0 + i];
+        cx<R> xv[12], rv[12], pv[12];
+        load_spinor<S>(field_at<S>(a.x, off[i]), vh, s, xv);
+        load_spinor<S>(field_at<S>(a.r, off[i]), vh, s, rv);
+        load_spinor<S>(field_at<S>(a.p, off[i]), vh, s, pv);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+          xv[k] = xv[k] + al * pv[k];
+          rv[k] = rv[k] - al * res[k];
+        }
+        store_spinor<S>(field_at<S>(a.x, off[i]), vh, s, xv);
+        quantize<S>(rv);                       // the norm is that of the stored residual
+        store_spinor<S>(field_at<S>(a.r, off[i]), vh, s, rv);
+        if (F & F_NORM) nrm[i] = norm2(rv);
+      } else {
+        if (F & F_POST) {
+          if (F & F_NORM) nrm[i] = norm2(res);  // norm before the post factor
+#pragma unroll
+          for (int k = 0; k < 12; ++k) res[k] = g[k / 3] * res[k];
+        } else if (F & F_NORM) {
+          quantize<S>(res);                     // the norm of the stored values
+          nrm[i] = norm2(res);
+        }
+        store_spinor<S>(field_at<S>(a.out, off[i]), vh, s, res);
+        if (F & F_OUT2) store_spinor<S>(field_at<S>(a.out2, off[i]), vh, s, res);
+      }
     }
   }
   if (F & F_NORM) {
-    nrm = wave_sum(nrm);
-    if (lane == 0) a.partial[u] = nrm;
+#pragma unroll
+    for (int i = 0; i < RG; ++i) {
+      if (i >= nr) break;
+      const double t = wave_sum(nrm[i]);
+      if (lane == 0 && act[i]) a.partial[sd.ubeg[UK_RHS] + tile * sd.nrhs + r0 + i] = t;
+    }
   }
 }
 
@@ -243,10 +272,13 @@ static void launch_dslash_t(int flags, const DslashArgs& a, hipStream_t st) {
     case F_Y: hipLaunchKernelGGL((k_dslash<S, F_Y>), grid, block, 0, st, a); break;
     case F_D | F_Y: hipLaunchKernelGGL((k_dslash<S, F_D | F_Y>), grid, block, 0, st, a); break;
     case F_Y | F_NORM: hipLaunchKernelGGL((k_dslash<S, F_Y | F_NORM>), grid, block, 0, st, a); break;
+    case F_Y | F_NORM | F_POST:
+      hipLaunchKernelGGL((k_dslash<S, F_Y | F_NORM | F_POST>), grid, block, 0, st, a); break;
     case F_Y | F_NORM | F_OUT2:
       hipLaunchKernelGGL((k_dslash<S, F_Y | F_NORM | F_OUT2>), grid, block, 0, st, a); break;
     case F_Y | F_XR | F_NORM:
       hipLaunchKernelGGL((k_dslash<S, F_Y | F_XR | F_NORM>), grid, block, 0, st, a); break;
+    case F_Y | F_POST: hipLaunchKernelGGL((k_dslash<S, F_Y | F_POST>), grid, block, 0, st, a); break;
     default: throw std::runtime_error("unsupported dslash flag combination");
   }
 }

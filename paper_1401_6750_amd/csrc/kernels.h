@@ -12,6 +12,7 @@ enum DslashFlags : int {
   F_NORM = 4,   // per-unit partial of ||result||^2 (or ||r||^2 with F_XR)
   F_XR = 8,     // CG update: x += alpha p, r -= alpha result (result not stored)
   F_OUT2 = 16,  // also store the result to a second field
+  F_POST = 32,  // store g (.) result (the norm is taken before the factor)
 };
 
 struct DslashArgs {
@@ -107,5 +108,22 @@ void launch_loops_finalize(const double* proj_lp, const double* proj_hp, const d
 
 // Number of FP64 accumulator components per site for an ops mask.
 int acc_components(int ops);
+
+// ---- backward pass ---------------------------------------------------------
+// Omega fields [2][nops][16][V] complex from the upstream gradient g
+// [2][nops][16][T][Np] (device) and the phase tables of the projection.
+void launch_omega(const double* g, int nops, int X, int Y, int Z, int T, int np, const double* phase_x,
+                  const double* phase_y, const double* phase_z, double kappa, double mu, long long nsrc,
+                  double* omega, hipStream_t st);
+// A = Q_1 s, C = gamma5 Q_t3 s + Q_t3^dag gamma5 s + Q_1 s + Q_1^dag M_0 s on parity p_out
+// (FP64 batch fields), per-unit partials of s^dag gamma5 Q_t3 s.
+void launch_insert_apply(const SlotDesc* slots, int nslots, int total_units, int p_out, int nops,
+                         const double* omega, const void* s_e, const void* s_o, const void* m_e, const void* m_o,
+                         void* a_out, void* c_out, double* part_re, double* part_im, hipStream_t st);
+// zout = gamma5 zin on complex128 site arrays; optional partials of conj(s) . zin per 256 sites
+void launch_g5_lex(const double* zin, double* zout, const double* s, long long nsite, double* part_re,
+                   double* part_im, hipStream_t st);
+// out[0] = fixed-order sum of n partials
+void launch_sum(const double* part, long long n, double* out, hipStream_t st);
 
 }  // namespace dl

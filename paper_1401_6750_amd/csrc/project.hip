@@ -165,6 +165,66 @@ void set_gamma_table(const int col[16][4], const double ph[16][4][2]) {
     throw std::runtime_error("hipMemcpyToSymbol(gamma table) failed");
 }
 
+// Backward of the projection and Gamma rebuild: per-site spin matrices
+//   Omega_{f,op}(x) = w_f sum_n [sum_p conj(g[f,op,n,t,p]) e^{-ip.x}] Gamma_n
+// (w_f = prefactor / number of sources), layout [f][op][entry 4a+b][V] complex.
+__global__ __launch_bounds__(256) void k_omega(const double2* g, int nops, int X, int Y, int Z, int T, int np,
+                                               const double2* px, const double2* py, const double2* pz,
+                                               double2 w_t3, double2 w_1, double2* omega) {
+  const long long V = (long long)X * Y * Z * T;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= V * 2 * nops) return;
+  const long long site = i % V;
+  const int fo = (int)(i / V);
+  const int op = fo % nops, fl = fo / nops;
+  const long long vh = V / 2;
+  const int par = (int)(site / vh);
+  const long long s = site - par * vh;
+  const int Xh = X / 2;
+  const int xh = (int)(s % Xh);
+  long long rest = s / Xh;
+  const int y = (int)(rest % Y);
+  rest /= Y;
+  const int z = (int)(rest % Z);
+  const int t = (int)(rest / Z);
+  const int x = 2 * xh + ((par + y + z + t) & 1);
+  const double2 w = fl == 0 ? w_t3 : w_1;
+  double2 m[16];
+  for (int e = 0; e < 16; ++e) m[e] = make_double2(0.0, 0.0);
+  for (int n = 0; n < 16; ++n) {
+    const double2* gn = g + ((((long long)fl * nops + op) * 16 + n) * T + t) * np;
+    double ar = 0.0, ai = 0.0;
+    for (int p = 0; p < np; ++p) {
+      const double2 fx = px[p * X + x], fy = py[p * Y + y], fz = pz[p * Z + z];
+      const double re1 = fx.x * fy.x - fx.y * fy.y, im1 = fx.x * fy.y + fx.y * fy.x;
+      const double phr = re1 * fz.x - im1 * fz.y, phi = re1 * fz.y + im1 * fz.x;
+      const double2 q = gn[p];   // conj(q) * phase
+      ar += q.x * phr + q.y * phi;
+      ai += q.x * phi - q.y * phr;
+    }
+    const double cr = w.x * ar - w.y * ai, ci = w.x * ai + w.y * ar;
+    for (int a = 0; a < 4; ++a) {
+      const int b = c_gamma.col[n][a];
+      const double gr = c_gamma.ph[n][a][0], gi = c_gamma.ph[n][a][1];
+      m[4 * a + b].x += cr * gr - ci * gi;
+      m[4 * a + b].y += cr * gi + ci * gr;
+    }
+  }
+  double2* o = omega + (long long)fo * 16 * V + site;
+  for (int e = 0; e < 16; ++e) o[e * V] = m[e];
+}
+
+void launch_omega(const double* g, int nops, int X, int Y, int Z, int T, int np, const double* phase_x,
+                  const double* phase_y, const double* phase_z, double kappa, double mu, long long nsrc,
+                  double* omega, hipStream_t st) {
+  const long long n = (long long)X * Y * Z * T * 2 * nops;
+  const double2 w_t3 = make_double2(0.0, -2.0 * mu * 4.0 * kappa * kappa / (double)nsrc);
+  const double2 w_1 = make_double2(4.0 * kappa / (double)nsrc, 0.0);
+  hipLaunchKernelGGL(k_omega, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (const double2*)g, nops, X, Y,
+                     Z, T, np, (const double2*)phase_x, (const double2*)phase_y, (const double2*)phase_z, w_t3, w_1,
+                     (double2*)omega);
+}
+
 void launch_loops_finalize(const double* proj_lp, const double* proj_hp, const double* proj_lpc, double w_lp,
                            double w_hp, int nops, int T, int np, double kappa, double mu, double* out,
                            hipStream_t st) {

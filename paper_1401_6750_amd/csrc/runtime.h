@@ -131,6 +131,11 @@ void init_gamma_table();
 
 int autotune_block(dl_ctx* ctx, dl_lattice* lat, int prec, int nsrc_hint);
 
+// Plan validated jobs into slots (autotuned block sizes) and memory-bounded
+// batches per precision class, run them, fill stats (job order) and the
+// accumulator counts.  Returns whether every source converged.
+bool solve_jobs(dl_ctx* ctx, const std::vector<dl_job>& J, dl_src_stats* stats);
+
 // Write the Z2 / Z4 sources of the plan's slots to their sol_user arrays.
 void fill_noise_fields(dl_ctx* ctx, const std::vector<SlotPlan>& plan, const std::vector<dl_job>& jobs);
 

@@ -7,11 +7,14 @@
 // right-hand side carries its own CG scalars and retires on its own
 // convergence, after which its units exit at once.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <complex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+
+#include <sys/stat.h>
 
 #include "runtime.h"
 
@@ -128,6 +131,14 @@ enum CoefKind : int {
   CK_MFULL,       // (M psi)_p = A psi_p - kappa H psi
   CK_MDAGFULL,    // (M^dag psi)_p = A(-mu) psi_p - kappa gamma5 H gamma5 psi
   CK_HOP,         // H psi
+  CK_G5V,         // gamma5 C_p - kappa H gamma5 A  (backward pass)
+  // CG-loop forms: the M-hat result is stored as t' = D t with
+  // D = gamma5 A^-1(-mu), which is exactly the input M-hat^dag needs at every
+  // neighbour, so its hop needs no per-neighbour factor; t = D^-1 t' is
+  // rebuilt per site where M-hat^dag adds it back.
+  CK_MHAT2P,      // t'_o = D (p_o - kappa^2 A^-1(mu) H_oe u_e), norm of t
+  CK_MDAG1P,      // u_e = A^-1(-mu) H_eo t'_o
+  CK_MDAG2P,      // out_o = D^-1 t'_o - kappa^2 gamma5 H_oe u_e
   CK_COUNT
 };
 
@@ -152,15 +163,20 @@ static Coef make_coef(int kind, double kappa, double mu) {
     Ami[s] = 1.0 / Am[s];
     G5[s] = g5[s];
   }
-  Cd d[4], e[4], f[4];
+  Cd d[4], e[4], f[4], g[4];
   for (int s = 0; s < 4; ++s) {
     d[s] = one[s];
     e[s] = one[s];
     f[s] = zero[s];
+    g[s] = one[s];
   }
   const double k2 = kappa * kappa;
   for (int s = 0; s < 4; ++s) {
+    const Cd D = G5[s] * Ami[s];
     switch (kind) {
+      case CK_MHAT2P: e[s] = -k2 * Ai[s]; f[s] = 1.0; g[s] = D; break;
+      case CK_MDAG1P: e[s] = Ami[s]; break;
+      case CK_MDAG2P: e[s] = -k2 * G5[s]; f[s] = 1.0 / D; break;
       case CK_MHAT1: e[s] = Ai[s]; break;
       case CK_MHAT2: e[s] = -k2 * Ai[s]; f[s] = 1.0; break;
       case CK_MDAG1: d[s] = G5[s] * Ami[s]; e[s] = Ami[s]; break;
@@ -171,12 +187,14 @@ static Coef make_coef(int kind, double kappa, double mu) {
       case CK_MFULL: e[s] = -kappa; f[s] = A[s]; break;
       case CK_MDAGFULL: d[s] = G5[s]; e[s] = -kappa * G5[s]; f[s] = Am[s]; break;
       case CK_HOP: break;
+      case CK_G5V: d[s] = G5[s]; e[s] = -kappa; f[s] = G5[s]; break;
     }
   }
   Coef c;
   put(c.d, d);
   put(c.e, e);
   put(c.f, f);
+  put(c.g, g);
   return c;
 }
 
@@ -189,7 +207,7 @@ struct Batch {
   std::vector<SlotDesc> hs;
   std::vector<Coef> coefs;     // host copies stay alive while their uploads are in flight
   DevBuf dslots, dcoef;
-  int nslots = 0, nrhs = 0, u_rhs = 0, u_site = 0, u_deriv = 0;
+  int nslots = 0, nrhs = 0, u_rhs = 0, u_site = 0, u_deriv = 0, u_grp = 0;
   long long sites = 0;
   DevBuf partial, partial2, scal;
   CgScalars cs{};
@@ -198,7 +216,7 @@ struct Batch {
 
   Batch(dl_ctx* c, int prec_, const std::vector<SlotPlan>& plan, const std::vector<dl_job>* jobs)
       : ctx(c), prec(prec_) {
-    int ur = 0, us = 0, ud = 0, rb = 0;
+    int ur = 0, us = 0, ud = 0, ug = 0, rb = 0;
     long long fo = 0;
     for (const SlotPlan& sp : plan) {
       const dl_lattice* L = sp.lat;
@@ -208,7 +226,7 @@ struct Batch {
       d.Vh = (int)L->Vh;
       d.ntile = (d.Vh + TILE - 1) / TILE;
       d.nrhs = sp.nrhs;
-      d.ubeg[UK_RHS] = ur; d.ubeg[UK_SITE] = us; d.ubeg[UK_DERIV] = ud;
+      d.ubeg[UK_RHS] = ur; d.ubeg[UK_SITE] = us; d.ubeg[UK_DERIV] = ud; d.ubeg[UK_GRP] = ug;
       d.rhs_begin = rb;
       d.fo = fo;
       d.bc = (double)L->bc;
@@ -229,13 +247,14 @@ struct Batch {
       ur += d.ntile * d.nrhs;
       us += 2 * d.ntile;
       ud += 8 * d.ntile;
+      ug += d.ntile * ((d.nrhs + RG - 1) / RG);
       rb += d.nrhs;
       fo += (long long)d.nrhs * d.Vh;
       hs.push_back(d);
     }
     nslots = (int)hs.size();
     nrhs = rb;
-    u_rhs = ur; u_site = us; u_deriv = ud;
+    u_rhs = ur; u_site = us; u_deriv = ud; u_grp = ug;
     sites = fo;
     dslots = DevBuf(ctx, sizeof(SlotDesc) * nslots);
     HIPCHECK(hipMemcpyAsync(dslots.p, hs.data(), sizeof(SlotDesc) * nslots, hipMemcpyHostToDevice, ctx->st));
@@ -273,7 +292,7 @@ struct Batch {
               const int* gate, void* x = nullptr, void* r = nullptr, const void* pp = nullptr,
               void* out2 = nullptr, double* part = nullptr) {
     DslashArgs a{};
-    a.slots = slots(); a.nslots = nslots; a.total_units = u_rhs; a.coef = coef(ck); a.p_out = p_out;
+    a.slots = slots(); a.nslots = nslots; a.total_units = u_grp; a.coef = coef(ck); a.p_out = p_out;
     a.in = in; a.out = out; a.y = y; a.partial = part ? part : partial.as<double>(); a.active = gate;
     a.x = x; a.r = r; a.p = pp; a.alpha = cs.alpha; a.out2 = out2;
     launch_dslash(p, flags, a, ctx->st);
@@ -317,10 +336,10 @@ static void cg_iteration(Batch& b, int P, const CgFields& f, hipEvent_t t0 = nul
   if (t0) HIPCHECK(hipEventRecord(t0, b.ctx->st));
   b.dslash(P, 0, CK_MHAT1, 0, f.p, f.u, nullptr, act);
   if (t1) HIPCHECK(hipEventRecord(t1, b.ctx->st));
-  b.dslash(P, F_Y | F_NORM, CK_MHAT2, 1, f.u, f.t, f.p, act);
+  b.dslash(P, F_Y | F_NORM | F_POST, CK_MHAT2P, 1, f.u, f.t, f.p, act);   // t' = D t
   b.finalize(FK_ALPHA);
-  b.dslash(P, F_D, CK_MDAG1, 0, f.t, f.u, nullptr, act);
-  b.dslash(P, F_Y | F_XR | F_NORM, CK_MDAG2, 1, f.u, nullptr, f.t, act, f.x, f.r, f.p);
+  b.dslash(P, 0, CK_MDAG1P, 0, f.t, f.u, nullptr, act);
+  b.dslash(P, F_Y | F_XR | F_NORM, CK_MDAG2P, 1, f.u, nullptr, f.t, act, f.x, f.r, f.p);
   b.finalize(FK_BETA);
   launch_update_p(P, b.slots(), b.nslots, b.u_rhs, f.p, f.r, b.cs.beta, act, b.ctx->st);
 }
@@ -805,15 +824,325 @@ void fill_noise_fields(dl_ctx* ctx, const std::vector<SlotPlan>& plan, const std
   b.sync();
 }
 
-int autotune_block(dl_ctx* ctx, dl_lattice* lat, int prec, int nsrc_hint) {
-  (void)ctx;
-  (void)lat;
-  (void)prec;
-  return std::max(1, std::min(nsrc_hint, 16));
+// ---------------------------------------------------------------------------
+// autotuner: right-hand sides interleaved per slot
+// ---------------------------------------------------------------------------
+// Within a slot the hopping kernel walks tile-major over its right-hand
+// sides, so one tile's links are fetched once for all of them; but the larger
+// the block, the longer a neighbour tile (+-t is Xh*Y*Z/64 tiles away) has to
+// survive in L2.  The best block size depends on lattice and precision and is
+// measured: the hopping launch is timed on a scratch batch for each candidate
+// and the fastest per right-hand side kept, in memory and in a JSON cache
+// (DL_TUNE_CACHE, default ~/.cache/discloop/tune-gfx950.json).
+static std::string tune_file() {
+  const char* e = getenv("DL_TUNE_CACHE");
+  if (e && *e) return e;
+  const char* h = getenv("HOME");
+  return std::string(h ? h : "/tmp") + "/.cache/discloop/tune-gfx950.json";
 }
 
-void loops_backward(dl_ctx*, const dl_job&, int, const double*, double*, double*) {
-  throw Error(DL_ESTATE, "dl_loops_backward: not available in this build");
+static void tune_load(dl_ctx* ctx) {
+  if (ctx->tune_loaded) return;
+  ctx->tune_loaded = true;
+  ctx->tune_path = tune_file();
+  FILE* f = fopen(ctx->tune_path.c_str(), "r");
+  if (!f) return;
+  char key[128];
+  int v;
+  // format: {"key": value, ...} one entry per line
+  char line[256];
+  while (fgets(line, sizeof(line), f)) {
+    if (sscanf(line, " \"%127[^\"]\" : %d", key, &v) == 2 && v >= 1) ctx->tune[key] = v;
+  }
+  fclose(f);
+}
+
+static void tune_save(dl_ctx* ctx) {
+  const std::string& p = ctx->tune_path;
+  const size_t slash = p.find_last_of('/');
+  if (slash != std::string::npos) {
+    std::string dir = p.substr(0, slash), acc;
+    for (size_t i = 0; i <= dir.size(); ++i) {
+      if (i == dir.size() || dir[i] == '/') {
+        if (!acc.empty()) (void)mkdir(acc.c_str(), 0755);
+      }
+      if (i < dir.size()) acc += dir[i];
+    }
+  }
+  FILE* f = fopen(p.c_str(), "w");
+  if (!f) return;   // an unwritable cache only costs a re-tune
+  fprintf(f, "{\n");
+  size_t i = 0;
+  for (const auto& kv : ctx->tune) fprintf(f, "  \"%s\": %d%s\n", kv.first.c_str(), kv.second, ++i < ctx->tune.size() ? "," : "");
+  fprintf(f, "}\n");
+  fclose(f);
+}
+
+int autotune_block(dl_ctx* ctx, dl_lattice* lat, int prec, int nsrc_hint) {
+  if (nsrc_hint <= 1) return 1;
+  tune_load(ctx);
+  static const char* pname[4] = {"fp64", "fp32", "bf16", "fp16"};
+  char key[96];
+  snprintf(key, sizeof(key), "%dx%dx%dx%d:%s", lat->dims[0], lat->dims[1], lat->dims[2], lat->dims[3], pname[prec]);
+  auto it = ctx->tune.find(key);
+  if (it == ctx->tune.end()) {
+    const int cands[] = {1, 2, 4, 8, 16, 32, 64};
+    const int total = 64;
+    double best_t = 1e300;
+    int best = 16;
+    hipEvent_t e0, e1;
+    HIPCHECK(hipEventCreate(&e0));
+    HIPCHECK(hipEventCreate(&e1));
+    for (int N : cands) {
+      std::vector<SlotPlan> plan;
+      for (int k = 0; k < total; k += N) {
+        SlotPlan sp{};
+        sp.lat = lat;
+        sp.nrhs = std::min(N, total - k);
+        plan.push_back(sp);
+      }
+      Batch b(ctx, prec, plan, nullptr);
+      DevBuf in = b.field(prec), out = b.field(prec);
+      HIPCHECK(hipMemsetAsync(in.p, 0, b.field_bytes(prec), ctx->st));
+      b.dslash(prec, 0, CK_MHAT1, 0, in.p, out.p, nullptr, nullptr);
+      HIPCHECK(hipEventRecord(e0, ctx->st));
+      for (int rep = 0; rep < 3; ++rep) b.dslash(prec, 0, CK_MHAT1, 0, in.p, out.p, nullptr, nullptr);
+      HIPCHECK(hipEventRecord(e1, ctx->st));
+      HIPCHECK(hipEventSynchronize(e1));
+      float ms = 0;
+      HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best_t * 0.98) {   // prefer the smaller block unless the larger one is clearly faster
+        best_t = ms;
+        best = N;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->tune[key] = best;
+    tune_save(ctx);
+    it = ctx->tune.find(key);
+  }
+  ctx->last_tune_block = it->second;
+  return std::max(1, std::min(nsrc_hint, it->second));
+}
+
+bool solve_jobs(dl_ctx* ctx, const std::vector<dl_job>& J, dl_src_stats* stats) {
+  const int njobs = (int)J.size();
+  std::vector<long long> first_stat(njobs + 1, 0);
+  for (int j = 0; j < njobs; ++j) first_stat[j + 1] = first_stat[j] + J[j].nsrc;
+  bool all_ok = true;
+  const double budget = ctx->inflight_mb * 1048576.0;
+  const int max_rhs = ctx->inflight_rhs;
+  const int tiers[4] = {DL_TIER_FP64, DL_TIER_LP_BF16, DL_TIER_LP_FP16, DL_TIER_HP_FP32};
+  for (int tier : tiers) {
+    const int P = tier_prec(tier);
+    std::vector<SlotPlan> all;
+    for (int j = 0; j < njobs; ++j) {
+      const dl_job& q = J[j];
+      if (q.tier != tier || q.nsrc == 0) continue;
+      const int N = q.rhs_block > 0 ? q.rhs_block : autotune_block(ctx, q.lat, P, q.nsrc);
+      const long long V = q.lat->V;
+      for (int k = 0; k < q.nsrc; k += N) {
+        SlotPlan sp{};
+        sp.lat = q.lat;
+        sp.job = j;
+        sp.job_first = k;
+        sp.nrhs = std::min(N, q.nsrc - k);
+        sp.src0 = q.first_src + k;
+        sp.src_user = q.src_in ? q.src_in + (size_t)k * V * 24 : nullptr;
+        sp.sol_user = q.sol_out ? q.sol_out + (size_t)k * V * 24 : nullptr;
+        sp.acc = q.accum ? q.accum->acc[q.accum_set] : nullptr;
+        all.push_back(sp);
+      }
+    }
+    // batches bounded by device memory and right-hand-side count
+    size_t i = 0;
+    while (i < all.size()) {
+      std::vector<SlotPlan> wave;
+      double bytes = 0;
+      int nrhs = 0;
+      while (i < all.size()) {
+        const SlotPlan& sp = all[i];
+        double per = (double)sp.lat->Vh * sp.nrhs * (7.0 * chunks_of(P) * 16);
+        if (tier == DL_TIER_HP_FP32) per += (double)sp.lat->Vh * sp.nrhs * 9.0 * 192;
+        if (J[sp.job].report_true_resid) per += (double)sp.lat->Vh * sp.nrhs * 6.0 * 192;
+        if (!wave.empty() && (bytes + per > budget || nrhs + sp.nrhs > max_rhs)) break;
+        wave.push_back(sp);
+        bytes += per;
+        nrhs += sp.nrhs;
+        ++i;
+      }
+      SolveReport rep;
+      run_batch(ctx, tier, wave, J, rep);
+      int g = 0;
+      for (const SlotPlan& sp : wave) {
+        for (int r = 0; r < sp.nrhs; ++r, ++g) {
+          if (rep.status[g] != 0) all_ok = false;
+          if (stats) {
+            dl_src_stats& s = stats[first_stat[sp.job] + sp.job_first + r];
+            s.iters = rep.iters[g];
+            s.status = rep.status[g];
+            s.rel_resid = rep.rel[g];
+            s.true_resid = rep.truer[g];
+            s.reliable_updates = rep.ru[g];
+            s.pad = 0;
+          }
+        }
+        const dl_job& q = J[sp.job];
+        if (q.accum) q.accum->count[q.accum_set] += sp.nrhs;
+      }
+    }
+  }
+  return all_ok;
+}
+
+// ---------------------------------------------------------------------------
+// backward pass: one adjoint solve per source
+// (gradients of a real loss F as dF/dRe + i dF/dIm for complex quantities)
+//   grad_eta = M^-dag (B + B^dag) s,  M^-dag = gamma5 M(-mu)^-1 gamma5
+//   dF/dmu   = (1/mu) Re sum_r s^dag gamma5 Q_t3 s - 2 kappa Im sum_r <s, gamma5 z>
+// ---------------------------------------------------------------------------
+void loops_backward(dl_ctx* ctx, const dl_job& job, int p2max, const double* grad_loops, double* grad_eta,
+                    double* grad_mu) {
+  dl_lattice* L = job.lat;
+  if (!L || !L->gauge_set || !L->params_set) throw Error(DL_EINVAL, "dl_loops_backward: lattice not ready");
+  if (job.nsrc < 1) throw Error(DL_EINVAL, "dl_loops_backward: nsrc must be >= 1");
+  if (p2max < 0) throw Error(DL_EINVAL, "dl_loops_backward: p2max must be >= 0");
+  if (!(job.tol > 0) || job.maxiter < 1) throw Error(DL_EINVAL, "dl_loops_backward: bad tol / maxiter");
+  if (job.noise == DL_NOISE_USER && !job.src_in) throw Error(DL_EINVAL, "dl_loops_backward: USER noise needs src_in");
+  (void)tier_prec(job.tier);
+  hipStream_t st = ctx->st;
+  const int nops = job.accum ? ((job.accum->ops & DL_OPS_DERIV) ? 5 : 1) : 5;
+  const int N = job.nsrc;
+  const long long V = L->V;
+  const int X = L->dims[0], Y = L->dims[1], Z = L->dims[2], T = L->dims[3];
+  // 1. solutions: the caller's checkpoint (job.sol_out) or recomputed
+  DevBuf s_buf;
+  const double* s_lex = job.sol_out;
+  if (!s_lex) {
+    s_buf = DevBuf(ctx, (size_t)N * V * 192);
+    std::vector<dl_job> J(1, job);
+    J[0].sol_out = s_buf.as<double>();
+    J[0].accum = nullptr;
+    J[0].report_true_resid = 0;
+    solve_jobs(ctx, J, nullptr);
+    s_lex = s_buf.as<double>();
+  }
+  // 2. Omega fields from the upstream gradient
+  std::vector<std::array<int, 3>> moms;
+  {
+    int lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = -(L->dims[k] / 2) + 1;
+      hi[k] = L->dims[k] / 2;
+    }
+    for (int a = lo[0]; a <= hi[0]; ++a)
+      for (int b = lo[1]; b <= hi[1]; ++b)
+        for (int c = lo[2]; c <= hi[2]; ++c)
+          if (a * a + b * b + c * c <= p2max) moms.push_back({a, b, c});
+    std::sort(moms.begin(), moms.end(), [](const std::array<int, 3>& x, const std::array<int, 3>& y) {
+      const int nx = x[0] * x[0] + x[1] * x[1] + x[2] * x[2], ny = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
+      return nx != ny ? nx < ny : x < y;
+    });
+  }
+  const int np = (int)moms.size();
+  std::vector<double> ph[3];
+  const int ext[3] = {X, Y, Z};
+  for (int k = 0; k < 3; ++k) {
+    ph[k].resize((size_t)np * ext[k] * 2);
+    for (int p = 0; p < np; ++p)
+      for (int x = 0; x < ext[k]; ++x) {
+        const double ang = -2.0 * M_PI * (double)moms[p][k] * x / ext[k];
+        ph[k][2 * ((size_t)p * ext[k] + x)] = std::cos(ang);
+        ph[k][2 * ((size_t)p * ext[k] + x) + 1] = std::sin(ang);
+      }
+  }
+  DevBuf dph[3];
+  for (int k = 0; k < 3; ++k) {
+    dph[k] = DevBuf(ctx, std::max<size_t>(ph[k].size() * sizeof(double), 16));
+    HIPCHECK(hipMemcpyAsync(dph[k].p, ph[k].data(), ph[k].size() * sizeof(double), hipMemcpyHostToDevice, st));
+  }
+  const size_t gbytes = sizeof(double) * 2 * 2 * nops * 16 * (size_t)T * np;
+  DevBuf dg(ctx, std::max<size_t>(gbytes, 16));
+  HIPCHECK(hipMemcpyAsync(dg.p, grad_loops, gbytes, hipMemcpyHostToDevice, st));
+  DevBuf omega(ctx, sizeof(double) * 2 * 2 * nops * 16 * (size_t)V);
+  launch_omega(dg.as<double>(), nops, X, Y, Z, T, np, dph[0].as<double>(), dph[1].as<double>(), dph[2].as<double>(),
+               L->kappa, L->mu, N, omega.as<double>(), st);
+  // 3. (B + B^dag) s, multiplied by gamma5: the right-hand side of M(-mu) z' = gamma5 v
+  DevBuf v_lex(ctx, (size_t)N * V * 192), z_lex(ctx, (size_t)N * V * 192);
+  std::vector<dl_job> J(1, job);
+  J[0].noise = DL_NOISE_USER;
+  std::vector<SlotPlan> plan;
+  const int blk = std::max(1, std::min(N, 64));
+  for (int k = 0; k < N; k += blk) {
+    SlotPlan sp{};
+    sp.lat = L;
+    sp.job = 0;
+    sp.job_first = k;
+    sp.nrhs = std::min(blk, N - k);
+    sp.src_user = s_lex + (size_t)k * V * 24;
+    sp.sol_user = v_lex.as<double>() + (size_t)k * V * 24;
+    plan.push_back(sp);
+  }
+  double sums[4] = {0, 0, 0, 0};
+  {
+    Batch b(ctx, P64, plan, &J);
+    DevBuf se = b.field(P64), so = b.field(P64), me = b.field(P64), mo = b.field(P64), ae = b.field(P64),
+           ao = b.field(P64), ce = b.field(P64), co = b.field(P64);
+    launch_sources(P64, b.slots(), b.nslots, b.u_rhs, 0, se.p, st);
+    launch_sources(P64, b.slots(), b.nslots, b.u_rhs, 1, so.p, st);
+    b.dslash(P64, F_Y, CK_XI, 0, so.p, me.p, se.p, nullptr);
+    b.dslash(P64, F_Y, CK_XI, 1, se.p, mo.p, so.p, nullptr);
+    DevBuf parts(ctx, sizeof(double) * 4 * std::max(b.u_rhs, 1)), red(ctx, sizeof(double) * 8);
+    double* pr = parts.as<double>();
+    const long long nu = std::max(b.u_rhs, 1);
+    launch_insert_apply(b.slots(), b.nslots, b.u_rhs, 0, nops, omega.as<double>(), se.p, so.p, me.p, mo.p, ae.p,
+                        ce.p, pr, pr + nu, st);
+    launch_insert_apply(b.slots(), b.nslots, b.u_rhs, 1, nops, omega.as<double>(), se.p, so.p, me.p, mo.p, ao.p,
+                        co.p, pr + 2 * nu, pr + 3 * nu, st);
+    // gamma5 v = gamma5 C - kappa H gamma5 A
+    b.dslash(P64, F_D | F_Y, CK_G5V, 0, ao.p, se.p, ce.p, nullptr);
+    b.dslash(P64, F_D | F_Y, CK_G5V, 1, ae.p, so.p, co.p, nullptr);
+    launch_unpack(P64, b.slots(), b.nslots, b.u_rhs, 0, se.p, st);
+    launch_unpack(P64, b.slots(), b.nslots, b.u_rhs, 1, so.p, st);
+    for (int k = 0; k < 4; ++k) launch_sum(pr + k * nu, b.u_rhs, red.as<double>() + k, st);
+    double h[4];
+    HIPCHECK(hipMemcpyAsync(h, red.p, sizeof(h), hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    sums[0] = h[0] + h[2];   // Re sum s^dag gamma5 Q_t3 s
+    sums[1] = h[1] + h[3];
+  }
+  // 4. adjoint solves M(-mu) z' = gamma5 v
+  dl_lattice Lm = *L;
+  Lm.mu = -L->mu;
+  {
+    std::vector<dl_job> A(1, job);
+    A[0].lat = &Lm;
+    A[0].noise = DL_NOISE_USER;
+    A[0].src_in = v_lex.as<double>();
+    A[0].sol_out = z_lex.as<double>();
+    A[0].accum = nullptr;
+    A[0].report_true_resid = 0;
+    A[0].first_src = 0;
+    solve_jobs(ctx, A, nullptr);
+  }
+  // 5. grad_eta = gamma5 z', and <s, z'> for the mu-derivative
+  const long long nsite = (long long)N * V;
+  const long long nblk = (nsite + 255) / 256;
+  DevBuf parts(ctx, sizeof(double) * 2 * nblk), red(ctx, sizeof(double) * 2);
+  DevBuf gtmp;
+  double* gout = grad_eta;
+  if (!gout) {
+    gtmp = DevBuf(ctx, (size_t)nsite * 192);
+    gout = gtmp.as<double>();
+  }
+  launch_g5_lex(z_lex.as<double>(), gout, s_lex, nsite, parts.as<double>(), parts.as<double>() + nblk, st);
+  launch_sum(parts.as<double>(), nblk, red.as<double>(), st);
+  launch_sum(parts.as<double>() + nblk, nblk, red.as<double>() + 1, st);
+  double h[2];
+  HIPCHECK(hipMemcpyAsync(h, red.p, sizeof(h), hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  if (grad_mu) *grad_mu = sums[0] / L->mu - 2.0 * L->kappa * h[1];
 }
 
 }  // namespace dl
