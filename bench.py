@@ -32,7 +32,138 @@ WORKLOADS = {
     # lattice name -> TSM sizes
     "batched_24x24x24x48": dict(n_lp=1000, n_hp=50, p2max=4, noise="Z4"),
     "tsm_16x16x16x32": dict(n_lp=200, n_hp=10, p2max=4, noise="Z2"),
+    # not TSM steps of one lattice: see bench_uneven / bench_grad
+    "uneven": None,
+    "grad_16x16x16x32": None,
 }
+
+# serving-shaped mix of lattices: (dims, eps, LP sources); kappa 0.1615, mu 0.004
+UNEVEN = [((8, 8, 8, 8), 0.1, 64), ((8, 8, 8, 8), 0.3, 4), ((16, 16, 16, 32), 0.2, 32),
+          ((16, 16, 16, 32), 0.1, 8), ((24, 24, 24, 48), 0.3, 16), ((24, 24, 24, 48), 0.2, 4)]
+
+
+def _setup_lattice(dl, torch, synth, ctx, dims, seed, eps, kappa, mu):
+    import numpy as np
+    U = synth.random_gauge(dims, seed, eps)
+    lat = dl.dl_lattice_create(ctx, dims, -1)
+    dl.dl_gauge_set(lat, torch.from_numpy(np.ascontiguousarray(U)).to("cuda"), 1)
+    dl.dl_set_params(lat, kappa, mu)
+    return lat, U
+
+
+def bench_uneven(a) -> int:
+    """Uneven batch: six lattices (8^4 .. 24^3x48) solved in one dl_solve_batch
+    call (shared launches) against one call per lattice.  Per lattice: FP16 LP
+    sources at rho = 1e-2, n/8 HP sources (FP32 + FP64 reliable updates) at 1e-8
+    and their LPC solves, all with local + derivative contractions."""
+    import numpy as np
+    import torch
+
+    import paper_1401_6750_amd as dl
+    import synth
+
+    ctx = dl.dl_create(0, torch.cuda.current_stream().cuda_stream)
+    dl.dl_set_option(ctx, "inflight_mb", a.inflight_mb)
+    lats, accs = [], []
+    for i, (dims, eps, n) in enumerate(UNEVEN):
+        lat, _ = _setup_lattice(dl, torch, synth, ctx, dims, 1410 + i, eps, 0.1615, 0.004)
+        lats.append(lat)
+        accs.append(dl.dl_accum_create(lat, dl.DL_OPS_LOCAL | dl.DL_OPS_DERIV))
+
+    def jobs(i):
+        lat, acc, n = lats[i], accs[i], UNEVEN[i][2]
+        nh = max(1, n // 8)
+        return [dl.make_job(lat, noise=dl.DL_NOISE_Z2, tier=dl.DL_TIER_LP_FP16, seed=6760 + i, nsrc=n, tol=1e-2,
+                            maxiter=500, accum=acc, accum_set=dl.DL_SET_LP),
+                dl.make_job(lat, noise=dl.DL_NOISE_Z2, tier=dl.DL_TIER_HP_FP32, seed=6760 + i, first_src=n,
+                            nsrc=nh, tol=1e-8, maxiter=2000, accum=acc, accum_set=dl.DL_SET_HP),
+                dl.make_job(lat, noise=dl.DL_NOISE_Z2, tier=dl.DL_TIER_LP_FP16, seed=6760 + i, first_src=n,
+                            nsrc=nh, tol=1e-2, maxiter=500, accum=acc, accum_set=dl.DL_SET_LPC)]
+
+    def together():
+        for acc in accs:
+            dl.dl_accum_reset(acc)
+        dl.dl_solve_batch(ctx, [j for i in range(len(UNEVEN)) for j in jobs(i)])
+
+    def separate():
+        for i, acc in enumerate(accs):
+            dl.dl_accum_reset(acc)
+            dl.dl_solve_batch(ctx, jobs(i))
+
+    def timed(fn):
+        for _ in range(a.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(a.steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / a.steps
+
+    t_tog, t_sep = timed(together), timed(separate)
+    n_lp = sum(n for _, _, n in UNEVEN)
+    res = {"metric": "uneven batch LP solves/s (one call for all lattices)", "value": round(n_lp / t_tog, 2),
+           "unit": "LP solves/s", "ms_per_step": round(t_tog * 1e3, 2), "ms_per_step_separate_calls":
+           round(t_sep * 1e3, 2), "batched_vs_separate": round(t_sep / t_tog, 3), "steps": a.steps,
+           "config": {"workload": "uneven", "lattices": [f"{'x'.join(map(str, d))} eps={e} n_lp={n}"
+                                                         for d, e, n in UNEVEN]}}
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+def bench_grad(a) -> int:
+    """Differentiation workload: 16^3x32, 64 Z2 sources; forward (HP tier solve,
+    contractions, projection) and backward (adjoint solves) through the
+    autograd function; checks d/dmu against central differences (FP64, h=1e-5)."""
+    import numpy as np
+    import torch
+
+    import paper_1401_6750_amd as dl
+    import synth
+    from oracle import noise as onoise
+
+    w = synth.WORKLOADS["tsm_16x16x16x32"]
+    dims = w["dims"]
+    ctx = dl.dl_create(0, torch.cuda.current_stream().cuda_stream)
+    lat, _ = _setup_lattice(dl, torch, synth, ctx, dims, w["gauge_seed"], w["eps"], w["kappa"], w["mu"])
+    nsrc, p2 = 64, 4
+    eta0 = torch.from_numpy(np.stack([onoise.source(dims, w["source_seed"], r, onoise.Z2)
+                                      for r in range(nsrc)])).to("cuda")
+    np_ = len(dl.dl_momenta(dims, p2))
+    rng = np.random.default_rng(0)
+    gw = torch.from_numpy(rng.standard_normal((2, 5, 16, dims[3], np_))
+                          + 1j * rng.standard_normal((2, 5, 16, dims[3], np_))).to("cuda")
+    ops = dl.DL_OPS_LOCAL | dl.DL_OPS_DERIV
+
+    def run(tier, tol, mu_val, grad=True):
+        eta = eta0.clone().requires_grad_(grad)
+        mu = torch.tensor(mu_val, dtype=torch.float64, requires_grad=grad)
+        L = dl.DiscLoops.apply(eta, mu, ctx, lat, w["kappa"], p2, ops, tier, tol)
+        F = (L * gw.conj()).real.sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if grad:
+            F.backward()
+            torch.cuda.synchronize()
+        return F.item(), (mu.grad.item() if grad else None), t1
+
+    run(dl.DL_TIER_HP_FP32, 1e-8, w["mu"])             # warm-up (autotuner, allocations)
+    t0 = time.perf_counter()
+    F, dmu, t1 = run(dl.DL_TIER_HP_FP32, 1e-8, w["mu"])
+    t2 = time.perf_counter()
+    h = 1e-5
+    fp = run(dl.DL_TIER_FP64, 1e-12, w["mu"] + h, grad=False)[0]
+    fm = run(dl.DL_TIER_FP64, 1e-12, w["mu"] - h, grad=False)[0]
+    fd = (fp - fm) / (2 * h)
+    _, dmu64, _ = run(dl.DL_TIER_FP64, 1e-12, w["mu"])
+    res = {"metric": "loop gradient (adjoint) cost", "forward_ms": round((t1 - t0) * 1e3, 2),
+           "backward_ms": round((t2 - t1) * 1e3, 2), "backward_over_forward": round((t2 - t1) / (t1 - t0), 3),
+           "dF_dmu_hp": dmu, "dF_dmu_fp64": dmu64, "dF_dmu_central_difference_fp64": fd,
+           "rel_err_fp64_vs_fd": abs(dmu64 - fd) / abs(fd), "rel_err_hp_vs_fd": abs(dmu - fd) / abs(fd),
+           "config": {"workload": "grad_16x16x16x32", "nsrc": nsrc, "p2max": p2, "forward_tier": "fp32+RU",
+                      "tol": 1e-8}}
+    print(json.dumps(res), flush=True)
+    return 0
 
 
 def kernel_hash() -> str:
@@ -72,6 +203,10 @@ def main() -> int:
     import synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if a.workload == "uneven":
+        return bench_uneven(a)
+    if a.workload == "grad_16x16x16x32":
+        return bench_grad(a)
     w = synth.WORKLOADS[a.workload]
     tw = WORKLOADS[a.workload]
     dims, kappa, mu = w["dims"], w["kappa"], w["mu"]

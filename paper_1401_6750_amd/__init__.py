@@ -271,6 +271,9 @@ def _make_disc_loops():
             out = torch.empty((2, nops, 16, T, np_), dtype=torch.complex128, device=eta.device)
             dl_loops(dlctx, acc, p2max, out, 1)
             torch.cuda.current_stream().synchronize()
+            if not any(fctx.needs_input_grad[:2]):
+                dl_accum_destroy(acc)          # no backward will come
+                acc = None
             fctx.save_for_backward(eta, sol)
             fctx.meta = (dlctx, lat, kappa, mu_v, p2max, acc, tier, tol)
             return out

@@ -266,7 +266,14 @@ __device__ inline void load_link<f16s>(const void* g, long vh, int mu, int par, 
 // UK_DERIV (one tile x parity x direction), UK_GRP (one tile x RG rhs: the
 // hopping kernel runs RG right-hand sides per wavefront).
 enum UnitKind : int { UK_RHS = 0, UK_SITE = 1, UK_DERIV = 2, UK_GRP = 3 };
-constexpr int RG = 2;
+// Right-hand sides per wavefront in the hopping kernel.  2 shares the link
+// loads and index arithmetic but costs occupancy (180 vs 120 registers in the
+// epilogue-heavy variants); on gfx950 1 measured faster (9.6 vs 10.8 ms per
+// 24^3x48 bf16 launch of ~525 right-hand sides).
+#ifndef DL_RHS_PER_WAVE
+#define DL_RHS_PER_WAVE 1
+#endif
+constexpr int RG = DL_RHS_PER_WAVE;
 
 struct SlotDesc {
   int X, Y, Z, T;

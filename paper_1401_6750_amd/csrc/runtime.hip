@@ -593,7 +593,7 @@ void run_batch(dl_ctx* ctx, int tier, const std::vector<SlotPlan>& plan, const s
           maxit[g] = jobs[sp.job].maxiter;
         }
     }
-    const double delta2 = 1e-4;   // reliable update when ||r|| fell by 100x since the last one
+    const double delta2 = 1e-5;   // reliable update when ||r|| fell by ~300x since the last one
     int guard = 0;
     while (true) {
       // state after the previous step

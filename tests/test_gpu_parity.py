@@ -271,6 +271,24 @@ def test_lp_map_is_independent_of_blocking(ctx, tier):
     lat.close()
 
 
+def test_graph_replay_equals_plain_launches(ctx):
+    """CG iterations replayed from a HIP graph give the same bits as plain launches,
+    and repeated graph runs with host work in between stay identical."""
+    lat = make_lattice(ctx, (6, 6, 6, 8), 25, 0.2, 0.1615, 0.004)
+    runs = []
+    for use_graph in (1, 0, 1, 1):
+        dl.dl_set_option(ctx, "use_graph", use_graph)
+        a, ia = _solve(ctx, lat, dl.DL_TIER_LP_BF16, 6, 3)
+        b, ib = _solve(ctx, lat, dl.DL_TIER_FP64, 2, 2)
+        runs.append((a, ia, b, ib))
+        _ = np.linalg.norm(a)          # host work between replays
+    dl.dl_set_option(ctx, "use_graph", 1)
+    for a, ia, b, ib in runs[1:]:
+        assert np.array_equal(a, runs[0][0]) and ia == runs[0][1]
+        assert np.array_equal(b, runs[0][2]) and ib == runs[0][3]
+    lat.close()
+
+
 def test_uneven_batch_equals_separate_runs(ctx):
     la = make_lattice(ctx, (4, 4, 4, 4), 31, 0.1, 0.1615, 0.004)
     lb = make_lattice(ctx, (8, 6, 4, 6), 32, 0.3, 0.1615, 0.004)
