@@ -224,6 +224,9 @@ def main() -> int:
     dl.dl_gauge_set(lat, U_dev, 1)
     dl.dl_set_params(lat, kappa, mu)
     acc = dl.dl_accum_create(lat, dl.DL_OPS_LOCAL | dl.DL_OPS_DERIV)
+    blocks = {"bf16": a.rhs_block or dl.dl_autotune(ctx, lat, dl.DL_TIER_LP_BF16),
+              "fp32": a.rhs_block or dl.dl_autotune(ctx, lat, dl.DL_TIER_HP_FP32)}
+    log(f"rhs blocks: {blocks}")
     nmom = len(dl.dl_momenta(dims, p2))
     out = torch.zeros((2, 5, 16, T, nmom), dtype=torch.complex128, device="cuda")
     seed = w["source_seed"]
@@ -348,7 +351,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": a.workload, "lattice": "x".join(map(str, dims)), "n_lp": n_lp, "n_hp": n_hp,
                    "n_lpc": n_hp, "lp_storage": "bf16", "hp": "fp32+fp64 reliable updates",
-                   "noise": tw["noise"], "p2max": p2, "insertions": 160, "rhs_block": a.rhs_block or "auto"},
+                   "noise": tw["noise"], "p2max": p2, "insertions": 160, "rhs_block": blocks},
         "iters_lp_mean": round(float(np.mean(it_lp)), 2), "iters_hp_mean": round(float(np.mean(it_hp)), 2),
         "reliable_updates_hp_mean": round(float(np.mean(ru_hp)), 2),
         "roofline": roofline,

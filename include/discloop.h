@@ -218,6 +218,18 @@ int dl_set_option(dl_ctx* ctx, const char* name, double value);
  * spinor once per active right-hand side), out[3] total active rhs. */
 int dl_profile_read(dl_ctx* ctx, int tier, double out[4]);
 
+/* Right-hand-side block (sources per batch slot) that dl_solve_batch uses for
+ * jobs of `tier` on `lat` when job->rhs_block is 0.  The first call per
+ * (lattice shape, storage precision) runs the autotuner: it times the
+ * hopping kernel on 128 scratch right-hand sides split into slots of
+ * 1, 2, 4, ..., 128 and keeps the fastest (a larger block only when it is
+ * more than 2% faster).  Results are cached in the context and in the JSON
+ * file named by the environment variable DL_TUNE_CACHE (default
+ * ~/.cache/discloop/tune-gfx950.json); an unwritable file only costs a
+ * re-tune.  Synchronises the context stream.  Errors: DL_EINVAL (NULL
+ * argument, unknown tier), DL_EHIP. */
+int dl_autotune(dl_ctx* ctx, dl_lattice* lat, int tier, int* block_out);
+
 /* ---- single operators, for verification -------------------------------- */
 
 /* Operators of dl_apply_op. */

@@ -99,7 +99,7 @@ int dl_lattice_create(dl_ctx* ctx, const int dims[4], int t_bc, dl_lattice** out
     L->Vh = V / 2;
     try {
       for (int p = 0; p < 4; ++p) {
-        const size_t bytes = (size_t)V * 4 * link_chunks(p) * 16;
+        const size_t bytes = (size_t)(2 * pad_half(V / 2)) * 4 * link_chunks(p) * 16;
         if (hipMalloc(&L->gauge[p], bytes) != hipSuccess) {
           (void)hipGetLastError();
           throw Error(DL_ENOMEM, "dl_lattice_create: gauge allocation failed");
@@ -172,7 +172,7 @@ int dl_accum_create(dl_lattice* lat, int ops, dl_accum** out) {
     a->lat = lat;
     a->ops = ops;
     a->nq = acc_components(ops);
-    const size_t bytes = sizeof(double) * (size_t)a->nq * lat->V;
+    const size_t bytes = sizeof(double) * (size_t)a->nq * 2 * pad_half(lat->Vh);
     for (int s = 0; s < 3; ++s) {
       if (hipMalloc((void**)&a->acc[s], bytes) != hipSuccess) {
         (void)hipGetLastError();
@@ -192,7 +192,7 @@ int dl_accum_reset(dl_accum* a) {
     require(a != nullptr, "dl_accum_reset: NULL");
     dl_ctx* c = a->lat->ctx;
     stream_enter(c);
-    const size_t bytes = sizeof(double) * (size_t)a->nq * a->lat->V;
+    const size_t bytes = sizeof(double) * (size_t)a->nq * 2 * pad_half(a->lat->Vh);
     for (int s = 0; s < 3; ++s) {
       HIPCHECK(hipMemsetAsync(a->acc[s], 0, bytes, c->st));
       a->count[s] = 0;
@@ -301,46 +301,81 @@ int dl_loops(dl_ctx* ctx, dl_accum* a, int p2max, double* out, int out_on_device
     const int np = (int)moms.size();
     if (np_out) *np_out = np;
     const int X = L->dims[0], Y = L->dims[1], Z = L->dims[2], T = L->dims[3];
-    std::vector<double> ph[3];
-    const int ext[3] = {X, Y, Z};
-    for (int k = 0; k < 3; ++k) {
-      ph[k].resize((size_t)np * ext[k] * 2);
-      for (int p = 0; p < np; ++p)
-        for (int x = 0; x < ext[k]; ++x) {
-          const double ang = -2.0 * M_PI * (double)moms[p][k] * x / ext[k];
-          ph[k][2 * ((size_t)p * ext[k] + x)] = std::cos(ang);
-          ph[k][2 * ((size_t)p * ext[k] + x) + 1] = std::sin(ang);
-        }
-    }
-    stream_enter(ctx);
-    DevBuf dph[3];
-    for (int k = 0; k < 3; ++k) {
-      dph[k] = DevBuf(ctx, std::max<size_t>(ph[k].size() * sizeof(double), 16));
-      HIPCHECK(hipMemcpyAsync(dph[k].p, ph[k].data(), ph[k].size() * sizeof(double), hipMemcpyHostToDevice, ctx->st));
-    }
-    const size_t pbytes = std::max<size_t>(sizeof(double) * 2 * (size_t)a->nq * T * np, 16);
-    DevBuf proj[3];
-    for (int s = 0; s < 3; ++s) {
-      proj[s] = DevBuf(ctx, pbytes);
-      if (a->count[s] > 0) {
-        launch_project(a->acc[s], a->nq, X, Y, Z, T, np, dph[0].as<double>(), dph[1].as<double>(),
-                       dph[2].as<double>(), proj[s].as<double>(), ctx->st);
-      } else {
-        HIPCHECK(hipMemsetAsync(proj[s].p, 0, pbytes, ctx->st));
+    // tables of the separable projection: distinct kx, distinct (kx, ky)
+    std::vector<int> kxs, pair_ix, pj(np);
+    std::vector<std::array<int, 2>> pairs;
+    for (int p = 0; p < np; ++p) {
+      const int kx = moms[p][0], ky = moms[p][1];
+      int ix = (int)(std::find(kxs.begin(), kxs.end(), kx) - kxs.begin());
+      if (ix == (int)kxs.size()) kxs.push_back(kx);
+      const std::array<int, 2> pr{kx, ky};
+      int j = (int)(std::find(pairs.begin(), pairs.end(), pr) - pairs.begin());
+      if (j == (int)pairs.size()) {
+        pairs.push_back(pr);
+        pair_ix.push_back(ix);
       }
+      pj[p] = j;
+    }
+    const int nkx = (int)kxs.size(), nkxy = (int)pairs.size();
+    auto phase = [](double n, int x, int ext, double* out) {
+      const double ang = -2.0 * M_PI * n * x / ext;
+      out[0] = std::cos(ang);
+      out[1] = std::sin(ang);
+    };
+    std::vector<double> tabs;   // px | py | pz | shift, complex
+    const size_t o_px = 0, o_py = o_px + 2ull * nkx * X, o_pz = o_py + 2ull * nkxy * Y,
+                 o_sh = o_pz + 2ull * np * Z, n_tab = o_sh + 6ull * np;
+    tabs.resize(std::max<size_t>(n_tab, 2));
+    for (int k = 0; k < nkx; ++k)
+      for (int x = 0; x < X; ++x) phase(kxs[k], x, X, &tabs[o_px + 2 * ((size_t)k * X + x)]);
+    for (int k = 0; k < nkxy; ++k)
+      for (int y = 0; y < Y; ++y) phase(pairs[k][1], y, Y, &tabs[o_py + 2 * ((size_t)k * Y + y)]);
+    const int ext[3] = {X, Y, Z};
+    for (int p = 0; p < np; ++p) {
+      for (int z = 0; z < Z; ++z) phase(moms[p][2], z, Z, &tabs[o_pz + 2 * ((size_t)p * Z + z)]);
+      for (int nu = 0; nu < 3; ++nu) {
+        double* f = &tabs[o_sh + 2 * ((size_t)p * 3 + nu)];
+        phase(moms[p][nu], 1, ext[nu], f);
+        f[0] += 1.0;
+      }
+    }
+    std::vector<int> itab(pair_ix);
+    itab.insert(itab.end(), pj.begin(), pj.end());
+    stream_enter(ctx);
+    DevBuf dtab(ctx, tabs.size() * sizeof(double)), ditab(ctx, std::max<size_t>(itab.size(), 1) * sizeof(int));
+    HIPCHECK(hipMemcpyAsync(dtab.p, tabs.data(), tabs.size() * sizeof(double), hipMemcpyHostToDevice, ctx->st));
+    if (!itab.empty())
+      HIPCHECK(hipMemcpyAsync(ditab.p, itab.data(), itab.size() * sizeof(int), hipMemcpyHostToDevice, ctx->st));
+    ProjTables tb{};
+    tb.np = np; tb.nkx = nkx; tb.nkxy = nkxy;
+    const double* dt = dtab.as<double>();
+    tb.px = dt + o_px; tb.py = dt + o_py; tb.pz = dt + o_pz; tb.shift = dt + o_sh;
+    tb.pair_ix = ditab.as<int>(); tb.pj = ditab.as<int>() + nkxy;
+    // TSM combination L = S_LP / N_LP + (S_HP - S_LPC) / N_HP, taken on the
+    // accumulators so one projection serves all three sets
+    const double w_lp = a->count[DL_SET_LP] > 0 ? 1.0 / (double)a->count[DL_SET_LP] : 0.0;
+    const double w_hp = a->count[DL_SET_HP] > 0 ? 1.0 / (double)a->count[DL_SET_HP] : 0.0;
+    const double* sets[3] = {w_lp != 0.0 ? a->acc[DL_SET_LP] : nullptr, w_hp != 0.0 ? a->acc[DL_SET_HP] : nullptr,
+                             (w_hp != 0.0 && a->count[DL_SET_LPC] > 0) ? a->acc[DL_SET_LPC] : nullptr};
+    const double wts[3] = {w_lp, w_hp, -w_hp};
+    const size_t pbytes = std::max<size_t>(sizeof(double) * 2 * (size_t)a->nq * T * np, 16);
+    DevBuf proj(ctx, pbytes);
+    if (sets[0] || sets[1] || sets[2]) {
+      DevBuf r2(ctx, std::max<size_t>(sizeof(double) * 2 * (size_t)a->nq * T * Z * nkxy, 16));
+      // derivative rows (q >= 48) hold link-centred sums
+      launch_project(sets, wts, a->nq, 48, X, Y, Z, T, tb, r2.as<double>(), proj.as<double>(), ctx->st);
+    } else {
+      HIPCHECK(hipMemsetAsync(proj.p, 0, pbytes, ctx->st));
     }
     const int nops = (a->ops & DL_OPS_DERIV) ? 5 : 1;
     const size_t obytes = sizeof(double) * 2 * 2 * nops * 16 * (size_t)T * np;
-    const double w_lp = a->count[DL_SET_LP] > 0 ? 1.0 / (double)a->count[DL_SET_LP] : 0.0;
-    const double w_hp = a->count[DL_SET_HP] > 0 ? 1.0 / (double)a->count[DL_SET_HP] : 0.0;
     DevBuf dout;
     double* target = out;
     if (!out_on_device) {
       dout = DevBuf(ctx, std::max<size_t>(obytes, 16));
       target = dout.as<double>();
     }
-    launch_loops_finalize(proj[0].as<double>(), proj[1].as<double>(), proj[2].as<double>(), w_lp, w_hp, nops, T, np,
-                          L->kappa, L->mu, target, ctx->st);
+    launch_loops_finalize(proj.as<double>(), nops, T, np, L->kappa, L->mu, target, ctx->st);
     HIPCHECK(hipGetLastError());
     if (!out_on_device) {
       HIPCHECK(hipMemcpyAsync(out, target, obytes, hipMemcpyDeviceToHost, ctx->st));
@@ -382,6 +417,18 @@ int dl_profile_read(dl_ctx* ctx, int tier, double out[4]) {
       out[k] = ctx->prof[P][k];
       ctx->prof[P][k] = 0;
     }
+    return 0;
+  });
+}
+
+int dl_autotune(dl_ctx* ctx, dl_lattice* lat, int tier, int* block_out) {
+  return guarded([&] {
+    require(ctx && lat && block_out, "dl_autotune: NULL argument");
+    require(lat->ctx == ctx, "dl_autotune: lattice belongs to another context");
+    const int P = tier_prec(tier);
+    stream_enter(ctx);
+    *block_out = autotune_block(ctx, lat, P, 1 << 30);
+    stream_exit(ctx);
     return 0;
   });
 }

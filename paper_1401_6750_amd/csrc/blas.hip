@@ -90,7 +90,7 @@ struct UnitRhs {
 };
 
 __device__ inline bool decode_rhs_unit(const SlotDesc* slots, int nslots, int total_units, UnitRhs& w) {
-  const int u = xcd_logical_block() * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int u = wave_unit();
   if (u >= total_units) return false;
   w.si = find_slot(slots, nslots, UK_RHS, u);
   const SlotDesc& sd = slots[w.si];
@@ -100,7 +100,7 @@ __device__ inline bool decode_rhs_unit(const SlotDesc* slots, int nslots, int to
   w.g = sd.rhs_begin + w.r;
   w.s = tile * TILE + (threadIdx.x & 63);
   w.valid = w.s < sd.Vh;
-  w.off = sd.fo + (long long)w.r * sd.Vh;
+  w.off = sd.fo + (long long)w.r * sd.Vp;
   return true;
 }
 
@@ -111,14 +111,14 @@ __global__ __launch_bounds__(256) void k_update_p(const SlotDesc* slots, int nsl
   UnitRhs w;
   if (!decode_rhs_unit(slots, nslots, total_units, w)) return;
   if (!active[w.g] || !w.valid) return;
-  const long vh = slots[w.si].Vh;
+  const long vp = slots[w.si].Vp;
   const R b = (R)beta[w.g];
   cx<R> pv[12], rv[12];
-  load_spinor<S>(field_at<S>(p, w.off), vh, w.s, pv);
-  load_spinor<S>(field_at<S>(r, w.off), vh, w.s, rv);
+  load_spinor<S>(field_at<S>(p, w.off), vp, w.s, pv);
+  load_spinor<S>(field_at<S>(r, w.off), vp, w.s, rv);
 #pragma unroll
   for (int k = 0; k < 12; ++k) pv[k] = rv[k] + b * pv[k];
-  store_spinor<S>(field_at<S>(p, w.off), vh, w.s, pv);
+  store_spinor<S>(field_at<S>(p, w.off), vp, w.s, pv);
 }
 
 template <class S>
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(256) void k_zero(const SlotDesc* slots, int nslots,
   cx<R> z[12];
 #pragma unroll
   for (int k = 0; k < 12; ++k) z[k] = mk<R>(0, 0);
-  store_spinor<S>(field_at<S>(f, w.off), slots[w.si].Vh, w.s, z);
+  store_spinor<S>(field_at<S>(f, w.off), slots[w.si].Vp, w.s, z);
 }
 
 #define DISPATCH_PREC(prec, KERNEL, ...)                                                     \
@@ -203,7 +203,7 @@ __global__ __launch_bounds__(256) void k_sources(const SlotDesc* slots, int nslo
       }
     }
   }
-  store_spinor<S>(field_at<S>(eta, w.off), sd.Vh, w.s, v);
+  store_spinor<S>(field_at<S>(eta, w.off), sd.Vp, w.s, v);
 }
 
 void launch_sources(int prec, const SlotDesc* slots, int nslots, int total_units, int parity, void* eta,
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(256) void k_unpack(const SlotDesc* slots, int nslot
   const long long lex = c.x + (long long)sd.X * (c.y + (long long)sd.Y * (c.z + (long long)sd.Z * c.t));
   const long long V = 2ll * sd.Vh;
   cx<R> v[12];
-  load_spinor<S>(field_at<S>(f, w.off), sd.Vh, w.s, v);
+  load_spinor<S>(field_at<S>(f, w.off), sd.Vp, w.s, v);
   double2* dst = (double2*)sd.sol_user + ((long long)w.r * V + lex) * 12;
 #pragma unroll
   for (int k = 0; k < 12; ++k) dst[k] = make_double2((double)v[k].re, (double)v[k].im);
@@ -250,19 +250,19 @@ __global__ __launch_bounds__(256) void k_convert(const SlotDesc* slots, int nslo
   UnitRhs w;
   if (!decode_rhs_unit(slots, nslots, total_units, w)) return;
   if ((active && !active[w.g]) || !w.valid) return;
-  const long vh = slots[w.si].Vh;
+  const long vp = slots[w.si].Vp;
   cx<RI> a[12];
-  load_spinor<SI>(field_at<SI>(in, w.off), vh, w.s, a);
+  load_spinor<SI>(field_at<SI>(in, w.off), vp, w.s, a);
   cx<RO> b[12];
   if (add) {
-    load_spinor<SO>(field_at<SO>(out, w.off), vh, w.s, b);
+    load_spinor<SO>(field_at<SO>(out, w.off), vp, w.s, b);
 #pragma unroll
     for (int k = 0; k < 12; ++k) b[k] = mk<RO>(b[k].re + (RO)a[k].re, b[k].im + (RO)a[k].im);
   } else {
 #pragma unroll
     for (int k = 0; k < 12; ++k) b[k] = mk<RO>((RO)a[k].re, (RO)a[k].im);
   }
-  store_spinor<SO>(field_at<SO>(out, w.off), vh, w.s, b);
+  store_spinor<SO>(field_at<SO>(out, w.off), vp, w.s, b);
 }
 
 template <class SI>
@@ -294,23 +294,23 @@ __global__ __launch_bounds__(256) void k_residual_replace(const SlotDesc* slots,
                                                           const void* c64, const void* ap64, void* r64,
                                                           void* r32, double* partial, const int* flag) {
   UnitRhs w;
-  const int u = xcd_logical_block() * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int u = wave_unit();
   if (!decode_rhs_unit(slots, nslots, total_units, w)) return;
   if (!flag[w.g]) return;
   double n = 0.0;
   if (w.valid) {
-    const long vh = slots[w.si].Vh;
+    const long vp = slots[w.si].Vp;
     cx<double> c[12], ap[12];
-    load_spinor<double>(field_at<double>(c64, w.off), vh, w.s, c);
-    load_spinor<double>(field_at<double>(ap64, w.off), vh, w.s, ap);
+    load_spinor<double>(field_at<double>(c64, w.off), vp, w.s, c);
+    load_spinor<double>(field_at<double>(ap64, w.off), vp, w.s, ap);
     cx<float> rf[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
       c[k] = c[k] - ap[k];
       rf[k] = mk<float>((float)c[k].re, (float)c[k].im);
     }
-    store_spinor<double>(field_at<double>(r64, w.off), vh, w.s, c);
-    store_spinor<float>(field_at<float>(r32, w.off), vh, w.s, rf);
+    store_spinor<double>(field_at<double>(r64, w.off), vp, w.s, c);
+    store_spinor<float>(field_at<float>(r32, w.off), vp, w.s, rf);
     n = norm2(c);
   }
   n = wave_sum(n);
@@ -328,14 +328,14 @@ void launch_residual_replace(const SlotDesc* slots, int nslots, int total_units,
 __global__ __launch_bounds__(256) void k_diff_norms(const SlotDesc* slots, int nslots, int total_units,
                                                     const void* a, const void* b, double* pd, double* pb) {
   UnitRhs w;
-  const int u = xcd_logical_block() * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int u = wave_unit();
   if (!decode_rhs_unit(slots, nslots, total_units, w)) return;
   double nd = 0.0, nb = 0.0;
   if (w.valid) {
-    const long vh = slots[w.si].Vh;
+    const long vp = slots[w.si].Vp;
     cx<double> x[12], y[12];
-    load_spinor<double>(field_at<double>(a, w.off), vh, w.s, x);
-    load_spinor<double>(field_at<double>(b, w.off), vh, w.s, y);
+    load_spinor<double>(field_at<double>(a, w.off), vp, w.s, x);
+    load_spinor<double>(field_at<double>(b, w.off), vp, w.s, y);
     nb = norm2(y);
 #pragma unroll
     for (int k = 0; k < 12; ++k) x[k] = x[k] - y[k];
@@ -362,7 +362,7 @@ void launch_diff_norms(const SlotDesc* slots, int nslots, int total_units, const
 __global__ __launch_bounds__(256) void k_pack_gauge(const double* src, int X, int Y, int Z, int T, void* g64,
                                                     void* g32, void* gb16, void* gh16) {
   const long long V = (long long)X * Y * Z * T;
-  const long long vh = V / 2;
+  const long long vp = pad_half(V / 2);   // record stride per (mu, parity)
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= V * 4) return;
   const int mu = (int)(i / V);
@@ -376,7 +376,7 @@ __global__ __launch_bounds__(256) void k_pack_gauge(const double* src, int X, in
   const int par = (x + y + z + t) & 1;
   const long long s = lex >> 1;
   const double2* u = (const double2*)src + (lex * 4 + mu) * 9;
-  const long long rec = (long long)(mu * 2 + par) * vh + s;   // link record index
+  const long long rec = (long long)(mu * 2 + par) * vp + s;   // link record index
   double2* r64 = (double2*)g64 + rec * 9;
   float2* r32 = (float2*)g32 + rec * 10;                      // 5 chunks = 10 complex
   uint32_t* rb = (uint32_t*)gb16 + rec * 12;                  // 3 chunks = 12 complex

@@ -275,9 +275,22 @@ enum UnitKind : int { UK_RHS = 0, UK_SITE = 1, UK_DERIV = 2, UK_GRP = 3 };
 #endif
 constexpr int RG = DL_RHS_PER_WAVE;
 
+// Site stride of every per-parity device array (spinor chunk rows, link
+// records, accumulator rows): Vh rounded up to an odd number of 64-site
+// tiles.  Rows then start an odd number of KiB apart; with the unpadded Vh
+// (2^12 * 81 at 24^3x48, 2^15 at 16^3x32) the rows of one site sit at
+// multiples of 64 KiB and compete for the same L2 sets.
+__host__ __device__ inline long long pad_half(long long vh) {
+  long long nt = (vh + TILE - 1) / TILE;
+  if (!(nt & 1)) ++nt;
+  return nt * TILE;
+}
+
 struct SlotDesc {
   int X, Y, Z, T;
   int Xh, Vh, ntile, nrhs;
+  int Vp;                  // pad_half(Vh): row stride of fields, links, accumulators
+  int pad0;
   int ubeg[4];             // first unit of this slot per UnitKind
   int rhs_begin;           // global index of this slot's rhs 0
   long long fo;            // site offset of rhs 0 in every batch field
@@ -305,6 +318,31 @@ __device__ inline int xcd_logical_block() {
   int nb = gridDim.x, b = blockIdx.x;
   int q = nb >> 3, rem = nb & 7, x = b & 7, k = b >> 3;
   return x * q + (x < rem ? x : rem) + k;
+}
+
+// Unit handled by the calling wavefront (wave-uniform, so the slot and tile
+// arithmetic that follows runs on the scalar unit).
+__device__ inline int wave_unit() {
+  return __builtin_amdgcn_readfirstlane(xcd_logical_block() * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6));
+}
+
+// Order in which the hopping kernel visits the tiles of a slot.  Tiles are
+// taken in blocks of TBLK time slices; inside a block the TBLK tiles at the
+// same place of successive slices are consecutive.  A tile's -t / +t
+// neighbours are then a few tiles away instead of a whole time slice
+// (Xh*Y*Z/64 tiles), so they are still in L2 when read, while the z
+// neighbours move only TBLK times further.  The order needs whole tiles per
+// time slice; other lattices keep the lexicographic order.
+constexpr int TBLK = 4;
+__device__ inline int tile_of(const SlotDesc& sd, int lt) {
+  const int slice = sd.Xh * sd.Y * sd.Z;
+  if (slice % TILE != 0) return lt;
+  const int ts = slice / TILE;
+  const int b = lt / (TBLK * ts);
+  const int rem = lt - b * (TBLK * ts);
+  const int bt = min(TBLK, sd.T - b * TBLK);
+  const int k = rem / bt;
+  return (b * TBLK + (rem - k * bt)) * ts + k;
 }
 
 __device__ inline int find_slot(const SlotDesc* slots, int nslots, int kind, int u) {

@@ -6,7 +6,9 @@
 //   without tau_3: xi = (1 - kappa H) s -> C_ab = sum_c conj(xi_ac) s_bc
 // and, for the one-derivative insertions along nu,
 //   E_ab = 1/2 sum_c [conj(xi_ac) (D s)_bc - conj((D xi)_ac) s_bc],
-//   (D psi)(x) = 1/2 [U_nu(x) psi(x+nu) - U_nu(x-nu)^dag psi(x-nu)].
+//   (D psi)(x) = 1/2 [U_nu(x) psi(x+nu) - U_nu(x-nu)^dag psi(x-nu)],
+// accumulated per link as F(x) with E(x) = F(x) + F(x - nu) (see
+// k_contract_deriv); the projection applies the shift.
 // The s-s products are Hermitian (local) or anti-Hermitian (derivative), so
 // the tau_3 structure keeps 16 reals and the other 32 reals per operator; the
 // gamma_5 of the tau_3 structure is applied when the loops are assembled.
@@ -19,7 +21,8 @@
 // the FP64 accumulator: the accumulator traffic falls as 1/KB and every
 // source is visited in a fixed order (deterministic).
 //
-// Accumulator component layout per site (reals):
+// Accumulator layout: FP64 rows [q][parity * Vp + s], Vp = pad_half(Vh).
+// Components per site (reals):
 //   local:   q  0..15  s-s Hermitian   (4 real diagonal, then (re, im) of
 //                      (0,1) (0,2) (0,3) (1,2) (1,3) (2,3))
 //            q 16..47  xi-s general    (re, im) of (a, b), index 2 (4 a + b)
@@ -61,7 +64,7 @@ __global__ __launch_bounds__(256) void k_contract_local(const SlotDesc* slots, i
                                                         const void* xi_o) {
   using R = typename Traits<S>::R;
   using A = typename AccT<S>::A;
-  const int u = xcd_logical_block() * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int u = wave_unit();
   if (u >= total_units) return;
   const int si = find_slot(slots, nslots, UK_SITE, u);
   const SlotDesc& sd = slots[si];
@@ -69,10 +72,10 @@ __global__ __launch_bounds__(256) void k_contract_local(const SlotDesc* slots, i
   const int par = ul & 1, tile = ul >> 1;
   const int s = tile * TILE + (threadIdx.x & 63);
   if (s >= sd.Vh || !sd.acc) return;
-  const long vh = sd.Vh;
-  const long long V = 2ll * vh;
+  const long vp = sd.Vp;
+  const long long V = 2ll * vp;
   double* acc = sd.acc;
-  const int lane_off = par * (int)vh + s;
+  const int lane_off = par * (int)vp + s;
   const void* sf = par ? s_o : s_e;
   const void* xf = par ? xi_o : xi_e;
   A a[48];
@@ -81,10 +84,10 @@ __global__ __launch_bounds__(256) void k_contract_local(const SlotDesc* slots, i
   int inblk = 0;
 #pragma unroll 1
   for (int r = 0; r < sd.nrhs; ++r) {
-    const long long off = sd.fo + (long long)r * vh;
+    const long long off = sd.fo + (long long)r * vp;
     cx<R> sv[12], xv[12];
-    load_spinor<S>(field_at<S>(sf, off), vh, s, sv);
-    load_spinor<S>(field_at<S>(xf, off), vh, s, xv);
+    load_spinor<S>(field_at<S>(sf, off), vp, s, sv);
+    load_spinor<S>(field_at<S>(xf, off), vp, s, xv);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       R d = 0;
@@ -118,44 +121,41 @@ __global__ __launch_bounds__(256) void k_contract_local(const SlotDesc* slots, i
   if (inblk) flush(acc, V, lane_off, a);
 }
 
-// (D psi)(x) along nu from the neighbour spinors of one rhs field:
-// 1/2 [U_nu(x) psi(x+nu) bp - U_nu(x-nu)^dag psi(x-nu) bm], bp / bm the
-// time-boundary factors.
+// Forward transport of one rhs field along nu: out = b U_nu(x) psi(x+nu),
+// b the time-boundary factor of the link.
 template <class S>
-__device__ inline void cov_deriv(const void* f_other, long vh, int sp, int sm, typename Traits<S>::R bp,
-                                 typename Traits<S>::R bm, const cx<typename Traits<S>::R> (&up)[9],
-                                 const cx<typename Traits<S>::R> (&um)[9], cx<typename Traits<S>::R> (&out)[12]) {
+__device__ inline void transport_fwd(const void* f_other, long vp, int sp, typename Traits<S>::R b,
+                                     const cx<typename Traits<S>::R> (&u)[9], cx<typename Traits<S>::R> (&out)[12]) {
   using R = typename Traits<S>::R;
   cx<R> v[12];
-  load_spinor<S>(f_other, vh, sp, v);
+  load_spinor<S>(f_other, vp, sp, v);
 #pragma unroll
-  for (int sp4 = 0; sp4 < 4; ++sp4)
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      cx<R> f = mk<R>(0, 0);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) cmac(f, up[3 * a + k], v[3 * sp4 + k]);
-      out[3 * sp4 + a] = bp * f;
-    }
-  load_spinor<S>(f_other, vh, sm, v);
-#pragma unroll
-  for (int sp4 = 0; sp4 < 4; ++sp4)
+  for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      cx<R> b = mk<R>(0, 0);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) cjmac(b, um[3 * k + a], v[3 * sp4 + k]);
-      out[3 * sp4 + a] = out[3 * sp4 + a] - bm * b;
+      cx<R> f = u[3 * a] * v[3 * s4];
+      cmac(f, u[3 * a + 1], v[3 * s4 + 1]);
+      cmac(f, u[3 * a + 2], v[3 * s4 + 2]);
+      out[3 * s4 + a] = b * f;
     }
 }
 
+// One-derivative contractions in link-centred form.  With T_psi(x) =
+// U_nu(x) psi(x+nu) (boundary factor included), the symmetric insertion
+//   E_ab(x) = 1/2 sum_c [conj(xi_ac)(D s)_bc - conj((D xi)_ac) s_bc]
+// equals F_ab(x) + F_ab(x - nu) with the per-link quantity
+//   F_ab(x) = 1/4 sum_c [conj(xi_ac(x)) T_s,bc(x) - conj(T_xi,ac(x)) s_bc(x)]
+// (the backward half of D at x+nu reproduces the forward half at x).  So
+// each (site, nu) needs two transports instead of four, and the projection
+// adds F(x - nu) (a momentum phase for spatial nu, the previous time slice
+// for nu = t).  The s-s block (xi -> s) stays anti-Hermitian.
 template <class S>
 __global__ __launch_bounds__(256) void k_contract_deriv(const SlotDesc* slots, int nslots, int total_units,
                                                         const void* s_e, const void* s_o, const void* xi_e,
                                                         const void* xi_o) {
   using R = typename Traits<S>::R;
   using A = typename AccT<S>::A;
-  const int u = xcd_logical_block() * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int u = wave_unit();
   if (u >= total_units) return;
   const int si = find_slot(slots, nslots, UK_DERIV, u);
   const SlotDesc& sd = slots[si];
@@ -163,83 +163,79 @@ __global__ __launch_bounds__(256) void k_contract_deriv(const SlotDesc* slots, i
   const int nu = ul & 3, par = (ul >> 2) & 1, tile = ul >> 3;
   const int s = tile * TILE + (threadIdx.x & 63);
   if (s >= sd.Vh || !sd.acc || !(sd.acc_ops & 2)) return;
-  const long vh = sd.Vh;
+  const long vp = sd.Vp;
   const Coords c = eo_coords(sd, s, par);
-  int xp[4] = {c.x, c.y, c.z, c.t}, xm[4] = {c.x, c.y, c.z, c.t};
+  int xp[4] = {c.x, c.y, c.z, c.t};
   const int ext[4] = {sd.X, sd.Y, sd.Z, sd.T};
-  R bp = (R)0.5, bm = (R)0.5;
+  R b = (R)1;
   xp[nu] += 1;
-  if (xp[nu] == ext[nu]) { xp[nu] = 0; if (nu == 3) bp = (R)(0.5 * sd.bc); }
-  xm[nu] -= 1;
-  if (xm[nu] < 0) { xm[nu] = ext[nu] - 1; if (nu == 3) bm = (R)(0.5 * sd.bc); }
+  if (xp[nu] == ext[nu]) { xp[nu] = 0; if (nu == 3) b = (R)sd.bc; }
   const int sp = eo_index(sd, xp[0], xp[1], xp[2], xp[3]);
-  const int sm = eo_index(sd, xm[0], xm[1], xm[2], xm[3]);
   const void* gauge = sd.gauge[Traits<S>::prec];
-  cx<R> up[9], um[9];
-  load_link<S>(gauge, vh, nu, par, s, up);
-  load_link<S>(gauge, vh, nu, 1 - par, sm, um);
+  cx<R> up[9];
+  load_link<S>(gauge, vp, nu, par, s, up);
   const void* s_here = par ? s_o : s_e;
   const void* s_other = par ? s_e : s_o;
   const void* x_here = par ? xi_o : xi_e;
   const void* x_other = par ? xi_e : xi_o;
-  const long long V = 2ll * vh;
+  const long long V = 2ll * vp;
   double* acc = sd.acc + (long long)(48 + 48 * nu) * V;
-  const int lane_off = par * (int)vh + s;
+  const int lane_off = par * (int)vp + s;
   A a[48];
 #pragma unroll
   for (int q = 0; q < 48; ++q) a[q] = (A)0;
   int inblk = 0;
 #pragma unroll 1
   for (int r = 0; r < sd.nrhs; ++r) {
-    const long long off = sd.fo + (long long)r * vh;
-    cx<R> sv[12], d[12];
-    load_spinor<S>(field_at<S>(s_here, off), vh, s, sv);
-    cov_deriv<S>(field_at<S>(s_other, off), vh, sp, sm, bp, bm, up, um, d);   // d = D s
-    // s-s block: E_ab = 1/2 sum_c [conj(s_a) (Ds)_b - conj((Ds)_a) s_b], anti-Hermitian
+    const long long off = sd.fo + (long long)r * vp;
+    cx<R> sv[12], t[12];
+    load_spinor<S>(field_at<S>(s_here, off), vp, s, sv);
+    transport_fwd<S>(field_at<S>(s_other, off), vp, sp, b, up, t);   // t = T_s
+    // s-s block: F_ab = 1/4 sum_c [conj(s_a) T_b - conj(T_a) s_b]
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       R im = 0;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) im += sv[3 * i + k].re * d[3 * i + k].im - sv[3 * i + k].im * d[3 * i + k].re;
-      a[i] += (A)im;
+      for (int k = 0; k < 3; ++k) im += sv[3 * i + k].re * t[3 * i + k].im - sv[3 * i + k].im * t[3 * i + k].re;
+      a[i] += (A)((R)0.5 * im);                  // F_aa = (i/2) Im sum_c conj(s_a) T_a
     }
 #pragma unroll
     for (int k6 = 0; k6 < 6; ++k6) {
       cx<R> t1 = mk<R>(0, 0), t2 = mk<R>(0, 0);
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        cjmac(t1, sv[3 * up_a(k6) + k], d[3 * up_b(k6) + k]);
-        cjmac(t2, d[3 * up_a(k6) + k], sv[3 * up_b(k6) + k]);
+        cjmac(t1, sv[3 * up_a(k6) + k], t[3 * up_b(k6) + k]);
+        cjmac(t2, t[3 * up_a(k6) + k], sv[3 * up_b(k6) + k]);
       }
-      a[4 + 2 * k6] += (A)((R)0.5 * (t1.re - t2.re));
-      a[5 + 2 * k6] += (A)((R)0.5 * (t1.im - t2.im));
+      a[4 + 2 * k6] += (A)((R)0.25 * (t1.re - t2.re));
+      a[5 + 2 * k6] += (A)((R)0.25 * (t1.im - t2.im));
     }
-    // xi-s block, first half: 1/2 conj(xi_a) (Ds)_b
+    // xi-s block, first half: 1/4 conj(xi_a) T_s,b
     {
       cx<R> xv[12];
-      load_spinor<S>(field_at<S>(x_here, off), vh, s, xv);
+      load_spinor<S>(field_at<S>(x_here, off), vp, s, xv);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          cx<R> t = mk<R>(0, 0);
+          cx<R> w = mk<R>(0, 0);
 #pragma unroll
-          for (int k = 0; k < 3; ++k) cjmac(t, xv[3 * i + k], d[3 * j + k]);
-          a[16 + 2 * (4 * i + j)] += (A)((R)0.5 * t.re);
-          a[17 + 2 * (4 * i + j)] += (A)((R)0.5 * t.im);
+          for (int k = 0; k < 3; ++k) cjmac(w, xv[3 * i + k], t[3 * j + k]);
+          a[16 + 2 * (4 * i + j)] += (A)((R)0.25 * w.re);
+          a[17 + 2 * (4 * i + j)] += (A)((R)0.25 * w.im);
         }
     }
-    // second half: -1/2 conj((D xi)_a) s_b
-    cov_deriv<S>(field_at<S>(x_other, off), vh, sp, sm, bp, bm, up, um, d);   // d = D xi
+    // second half: -1/4 conj(T_xi,a) s_b
+    transport_fwd<S>(field_at<S>(x_other, off), vp, sp, b, up, t);   // t = T_xi
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        cx<R> t = mk<R>(0, 0);
+        cx<R> w = mk<R>(0, 0);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) cjmac(t, d[3 * i + k], sv[3 * j + k]);
-        a[16 + 2 * (4 * i + j)] -= (A)((R)0.5 * t.re);
-        a[17 + 2 * (4 * i + j)] -= (A)((R)0.5 * t.im);
+        for (int k = 0; k < 3; ++k) cjmac(w, t[3 * i + k], sv[3 * j + k]);
+        a[16 + 2 * (4 * i + j)] -= (A)((R)0.25 * w.re);
+        a[17 + 2 * (4 * i + j)] -= (A)((R)0.25 * w.im);
       }
     if (++inblk == AccT<S>::KB) {
       flush(acc, V, lane_off, a);

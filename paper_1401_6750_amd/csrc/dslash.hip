@@ -98,12 +98,12 @@ __device__ inline void reconstruct(cx<R> (&acc)[12], const cx<R> (&w0)[3], const
 // One hop (direction MU, forward or backward) for every right-hand side of
 // the group: the link is loaded once.
 template <class S, int MU, bool FWD, bool HAS_D>
-__device__ inline void hop(const void* gauge, long vh, int link_par, int link_site, int nb, typename Traits<S>::R sign,
+__device__ inline void hop(const void* gauge, long vp, int link_par, int link_site, int nb, typename Traits<S>::R sign,
                            const void* const (&inb)[RG], int nr, const bool (&act)[RG],
                            const cx<typename Traits<S>::R> (&d)[4], cx<typename Traits<S>::R> (&acc)[RG][12]) {
   using R = typename Traits<S>::R;
   cx<R> u[9];
-  load_link<S>(gauge, vh, MU, link_par, link_site, u);
+  load_link<S>(gauge, vp, MU, link_par, link_site, u);
   if (MU == 3) {
 #pragma unroll
     for (int k = 0; k < 9; ++k) u[k] = sign * u[k];
@@ -112,7 +112,7 @@ __device__ inline void hop(const void* gauge, long vh, int link_par, int link_si
   for (int i = 0; i < RG; ++i) {
     if (i >= nr || !act[i]) continue;
     cx<R> v[12];
-    load_spinor<S>(inb[i], vh, nb, v);
+    load_spinor<S>(inb[i], vp, nb, v);
     if (HAS_D) {
 #pragma unroll
       for (int k = 0; k < 12; ++k) v[k] = d[k / 3] * v[k];
@@ -139,15 +139,16 @@ __device__ inline void load_coef(const double (&c)[4][2], cx<R> (&out)[4]) {
 template <class S, int F>
 __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
   using R = typename Traits<S>::R;
-  const int u = xcd_logical_block() * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int u = wave_unit();
   if (u >= a.total_units) return;
   const int lane = threadIdx.x & 63;
   const int si = find_slot(a.slots, a.nslots, UK_GRP, u);
   const SlotDesc& sd = a.slots[si];
   const int ngrp = (sd.nrhs + RG - 1) / RG;
   const int ul = u - sd.ubeg[UK_GRP];
-  const int tile = ul / ngrp;
-  const int r0 = (ul - tile * ngrp) * RG;
+  const int lt = ul / ngrp;
+  const int tile = tile_of(sd, lt);
+  const int r0 = (ul - lt * ngrp) * RG;
   const int nr = min(RG, sd.nrhs - r0);
   bool act[RG];
   bool any = false;
@@ -159,10 +160,10 @@ __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
   if (!any) return;
   const int s = tile * TILE + lane;
   const bool valid = s < sd.Vh;
-  const long vh = sd.Vh;
+  const long vp = sd.Vp;   // row stride of fields and link records
   long long off[RG];
 #pragma unroll
-  for (int i = 0; i < RG; ++i) off[i] = sd.fo + (long long)(r0 + i) * vh;
+  for (int i = 0; i < RG; ++i) off[i] = sd.fo + (long long)(r0 + i) * vp;
   double nrm[RG];
 #pragma unroll
   for (int i = 0; i < RG; ++i) nrm[i] = 0.0;
@@ -201,14 +202,14 @@ __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
       for (int k = 0; k < 12; ++k) acc[i][k] = mk<R>(0, 0);
     constexpr bool HD = (F & F_D) != 0;
     const int q = 1 - p_out;
-    hop<S, 0, true, HD>(gauge, vh, p_out, s, nxp, (R)1, inb, nr, act, d, acc);
-    hop<S, 0, false, HD>(gauge, vh, q, nxm, nxm, (R)1, inb, nr, act, d, acc);
-    hop<S, 1, true, HD>(gauge, vh, p_out, s, nyp, (R)1, inb, nr, act, d, acc);
-    hop<S, 1, false, HD>(gauge, vh, q, nym, nym, (R)1, inb, nr, act, d, acc);
-    hop<S, 2, true, HD>(gauge, vh, p_out, s, nzp, (R)1, inb, nr, act, d, acc);
-    hop<S, 2, false, HD>(gauge, vh, q, nzm, nzm, (R)1, inb, nr, act, d, acc);
-    hop<S, 3, true, HD>(gauge, vh, p_out, s, ntp, sp, inb, nr, act, d, acc);
-    hop<S, 3, false, HD>(gauge, vh, q, ntm, ntm, sm, inb, nr, act, d, acc);
+    hop<S, 0, true, HD>(gauge, vp, p_out, s, nxp, (R)1, inb, nr, act, d, acc);
+    hop<S, 0, false, HD>(gauge, vp, q, nxm, nxm, (R)1, inb, nr, act, d, acc);
+    hop<S, 1, true, HD>(gauge, vp, p_out, s, nyp, (R)1, inb, nr, act, d, acc);
+    hop<S, 1, false, HD>(gauge, vp, q, nym, nym, (R)1, inb, nr, act, d, acc);
+    hop<S, 2, true, HD>(gauge, vp, p_out, s, nzp, (R)1, inb, nr, act, d, acc);
+    hop<S, 2, false, HD>(gauge, vp, q, nzm, nzm, (R)1, inb, nr, act, d, acc);
+    hop<S, 3, true, HD>(gauge, vp, p_out, s, ntp, sp, inb, nr, act, d, acc);
+    hop<S, 3, false, HD>(gauge, vp, q, ntm, ntm, sm, inb, nr, act, d, acc);
 #pragma unroll
     for (int i = 0; i < RG; ++i) {
       if (!act[i]) continue;
@@ -217,24 +218,24 @@ __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
       for (int k = 0; k < 12; ++k) res[k] = e[k / 3] * acc[i][k];
       if (F & F_Y) {
         cx<R> yv[12];
-        load_spinor<S>(field_at<S>(a.y, off[i]), vh, s, yv);
+        load_spinor<S>(field_at<S>(a.y, off[i]), vp, s, yv);
 #pragma unroll
         for (int k = 0; k < 12; ++k) res[k] = res[k] + f[k / 3] * yv[k];
       }
       if (F & F_XR) {
         const R al = (R)a.alpha[sd.rhs_begin + r0 + i];
         cx<R> xv[12], rv[12], pv[12];
-        load_spinor<S>(field_at<S>(a.x, off[i]), vh, s, xv);
-        load_spinor<S>(field_at<S>(a.r, off[i]), vh, s, rv);
-        load_spinor<S>(field_at<S>(a.p, off[i]), vh, s, pv);
+        load_spinor<S>(field_at<S>(a.x, off[i]), vp, s, xv);
+        load_spinor<S>(field_at<S>(a.r, off[i]), vp, s, rv);
+        load_spinor<S>(field_at<S>(a.p, off[i]), vp, s, pv);
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
           xv[k] = xv[k] + al * pv[k];
           rv[k] = rv[k] - al * res[k];
         }
-        store_spinor<S>(field_at<S>(a.x, off[i]), vh, s, xv);
+        store_spinor<S>(field_at<S>(a.x, off[i]), vp, s, xv);
         quantize<S>(rv);                       // the norm is that of the stored residual
-        store_spinor<S>(field_at<S>(a.r, off[i]), vh, s, rv);
+        store_spinor<S>(field_at<S>(a.r, off[i]), vp, s, rv);
         if (F & F_NORM) nrm[i] = norm2(rv);
       } else {
         if (F & F_POST) {
@@ -245,8 +246,8 @@ __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
           quantize<S>(res);                     // the norm of the stored values
           nrm[i] = norm2(res);
         }
-        store_spinor<S>(field_at<S>(a.out, off[i]), vh, s, res);
-        if (F & F_OUT2) store_spinor<S>(field_at<S>(a.out2, off[i]), vh, s, res);
+        store_spinor<S>(field_at<S>(a.out, off[i]), vp, s, res);
+        if (F & F_OUT2) store_spinor<S>(field_at<S>(a.out2, off[i]), vp, s, res);
       }
     }
   }

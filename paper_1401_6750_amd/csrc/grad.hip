@@ -52,11 +52,11 @@ __device__ inline void g5(cx<double> (&v)[12]) {
 
 // transported neighbours along nu for one field (FP64 batch field of the
 // other parity): tp = U(x) u(x+nu) bp, tm = U(x-nu)^dag u(x-nu) bm
-__device__ inline void transport(const void* f_other, long vh, int sp, int sm, double bp, double bm,
+__device__ inline void transport(const void* f_other, long vp, int sp, int sm, double bp, double bm,
                                  const cx<double> (&up)[9], const cx<double> (&um)[9], cx<double> (&tp)[12],
                                  cx<double> (&tm)[12]) {
   cx<double> v[12];
-  load_spinor<double>(f_other, vh, sp, v);
+  load_spinor<double>(f_other, vp, sp, v);
 #pragma unroll
   for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
@@ -66,7 +66,7 @@ __device__ inline void transport(const void* f_other, long vh, int sp, int sm, d
       for (int k = 0; k < 3; ++k) cmac(f, up[3 * a + k], v[3 * s4 + k]);
       tp[3 * s4 + a] = bp * f;
     }
-  load_spinor<double>(f_other, vh, sm, v);
+  load_spinor<double>(f_other, vp, sm, v);
 #pragma unroll
   for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(256) void k_insert_apply(const SlotDesc* slots, int
                                                       const void* s_o, const void* m_e, const void* m_o,
                                                       void* a_out, void* c_out, double* part_re,
                                                       double* part_im) {
-  const int u = xcd_logical_block() * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int u = wave_unit();
   if (u >= total_units) return;
   const int lane = threadIdx.x & 63;
   const int si = find_slot(slots, nslots, UK_RHS, u);
@@ -92,9 +92,10 @@ __global__ __launch_bounds__(256) void k_insert_apply(const SlotDesc* slots, int
   const int tile = ul / sd.nrhs;
   const int r = ul - tile * sd.nrhs;
   const int s = tile * TILE + lane;
-  const long vh = sd.Vh;
+  const long vh = sd.Vh;                 // Omega: [..][V] over par * Vh + s
+  const long vp = sd.Vp;                 // fields and links: padded rows
   const long long V = 2ll * vh;
-  const long long off = sd.fo + (long long)r * vh;
+  const long long off = sd.fo + (long long)r * vp;
   double dre = 0.0, dim = 0.0;
   if (s < sd.Vh) {
     const int par = p_out;
@@ -104,8 +105,8 @@ __global__ __launch_bounds__(256) void k_insert_apply(const SlotDesc* slots, int
     const void* m_here = field_at<double>(par ? m_o : m_e, off);
     const void* m_oth = field_at<double>(par ? m_e : m_o, off);
     cx<double> sv[12], mv[12], s5[12];
-    load_spinor<double>(s_here, vh, s, sv);
-    load_spinor<double>(m_here, vh, s, mv);
+    load_spinor<double>(s_here, vp, s, sv);
+    load_spinor<double>(m_here, vp, s, mv);
 #pragma unroll
     for (int k = 0; k < 12; ++k) s5[k] = sv[k];
     g5(s5);
@@ -137,10 +138,10 @@ __global__ __launch_bounds__(256) void k_insert_apply(const SlotDesc* slots, int
         const int sm = eo_index(sd, xm[0], xm[1], xm[2], xm[3]);
         const long long site_p = (long long)(1 - par) * vh + sp, site_m = (long long)(1 - par) * vh + sm;
         cx<double> up[9], um[9];
-        load_link<double>(g64, vh, nu, par, s, up);
-        load_link<double>(g64, vh, nu, 1 - par, sm, um);
+        load_link<double>(g64, vp, nu, par, s, up);
+        load_link<double>(g64, vp, nu, 1 - par, sm, um);
         cx<double> tp[12], tm[12], dt[12];
-        transport(s_oth, vh, sp, sm, bp, bm, up, um, tp, tm);
+        transport(s_oth, vp, sp, sm, bp, bm, up, um, tp, tm);
 #pragma unroll
         for (int k = 0; k < 12; ++k) dt[k] = tp[k] - tm[k];
         // tau_3 flavour: Q s and Q^dag (gamma5 s); gamma5 commutes with the transport
@@ -168,7 +169,7 @@ __global__ __launch_bounds__(256) void k_insert_apply(const SlotDesc* slots, int
         spin_mat_acc<false>(w, tp, 0.25, A);
         load_omega(o1, V, site_m, w);
         spin_mat_acc<false>(w, tm, -0.25, A);
-        transport(m_oth, vh, sp, sm, bp, bm, up, um, tp, tm);
+        transport(m_oth, vp, sp, sm, bp, bm, up, um, tp, tm);
 #pragma unroll
         for (int k = 0; k < 12; ++k) dt[k] = tp[k] - tm[k];
         load_omega(o1, V, site, w);
@@ -190,8 +191,8 @@ __global__ __launch_bounds__(256) void k_insert_apply(const SlotDesc* slots, int
       dre += sv[k].re * q5[k].re + sv[k].im * q5[k].im;
       dim += sv[k].re * q5[k].im - sv[k].im * q5[k].re;
     }
-    store_spinor<double>(field_at<double>(a_out, off), vh, s, A);
-    store_spinor<double>(field_at<double>(c_out, off), vh, s, C);
+    store_spinor<double>(field_at<double>(a_out, off), vp, s, A);
+    store_spinor<double>(field_at<double>(c_out, off), vp, s, C);
   }
   dre = wave_sum(dre);
   dim = wave_sum(dim);

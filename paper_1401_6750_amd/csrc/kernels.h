@@ -96,15 +96,26 @@ void launch_contract_deriv(int prec, const SlotDesc* slots, int nslots, int tota
                            const void* s_e, const void* s_o, const void* xi_e, const void* xi_o,
                            hipStream_t st);
 
-// momentum projection of accumulator components: acc [nq][V] -> proj [nq][T][Np] complex
-void launch_project(const double* acc, int nq, int X, int Y, int Z, int T, int np,
-                    const double* phase_x, const double* phase_y, const double* phase_z,
-                    double* proj, hipStream_t st);
+// Tables of the separable momentum projection (device pointers), built on the
+// host from the momentum list: distinct kx values, distinct (kx, ky) pairs.
+struct ProjTables {
+  int np, nkx, nkxy;
+  const double* px;     // [nkx][X] complex e^{-2 pi i kx x / X}
+  const double* py;     // [nkxy][Y] complex e^{-2 pi i ky y / Y}, ky of pair j
+  const int* pair_ix;   // [nkxy] kx index of pair j
+  const double* pz;     // [np][Z] complex e^{-2 pi i kz z / Z}
+  const int* pj;        // [np] pair index of momentum p
+  const double* shift;  // [np][3] complex 1 + e^{-2 pi i n_nu / L_nu}
+};
+// proj [nq][T][Np] complex = projection of sum_k w[k] acc[k] (null sets
+// skipped); rows q >= q_link are link-centred derivative sums (pass nq for
+// none).  r2: scratch of nq*T*Z*nkxy complex.
+void launch_project(const double* const acc[3], const double w[3], int nq, int q_link, int X, int Y, int Z, int T,
+                    const ProjTables& tb, double* r2, double* proj, hipStream_t st);
 
-// Gamma rebuild, TSM combination and prefactors -> out [2][nops][16][T][Np] complex
-void launch_loops_finalize(const double* proj_lp, const double* proj_hp, const double* proj_lpc,
-                           double w_lp, double w_hp, int nops, int T, int np, double kappa,
-                           double mu, double* out, hipStream_t st);
+// Gamma rebuild and prefactors -> out [2][nops][16][T][Np] complex
+void launch_loops_finalize(const double* proj, int nops, int T, int np, double kappa, double mu, double* out,
+                           hipStream_t st);
 
 // Number of FP64 accumulator components per site for an ops mask.
 int acc_components(int ops);

@@ -7,86 +7,122 @@
 
 namespace dl {
 // ---------------------------------------------------------------------------
-// momentum projection: proj[q][t][p] = sum_xvec phase_p(xvec) acc[q][x]
-// phase_p(x) = px[p][x] py[p][y] pz[p][z], complex128 tables [Np][L]
+// momentum projection, separable over x, y, z:
+//   proj[q][t][p] = sum_{x,y,z} e^{-2 pi i (kx x/X + ky y/Y + kz z/Z)} v_q(x,y,z,t)
+// of the TSM-combined accumulator value v = sum_sets w_set acc_set.
+// Stage 1+2 (one workgroup per (q, t, z) plane): the plane goes to LDS, is
+// summed over x for every distinct kx, then over y for every distinct
+// (kx, ky) pair of the momentum list.  Stage 3 (one thread per (q, t, p)):
+// the sum over z.  Each accumulator value is read once, in whole rows.
 // ---------------------------------------------------------------------------
-template <int PC>
-__global__ __launch_bounds__(256) void k_project(const double* acc, int X, int Y, int Z, int T, int np,
-                                                 const double2* px, const double2* py, const double2* pz,
-                                                 double2* proj) {
-  const int nchunk = (np + PC - 1) / PC;
+__global__ __launch_bounds__(256) void k_proj_plane(const double* a0, const double* a1, const double* a2, double w0,
+                                                    double w1, double w2, int X, int Y, int Z, int T, long long vp,
+                                                    int nkx, int nkxy, const double2* px, const double2* py,
+                                                    const int* pair_ix, double2* r2) {
+  extern __shared__ double lds[];
+  double* v = lds;                               // [Y][X]
+  double2* r1 = (double2*)(lds + X * Y);         // [Y][nkx]
   int b = blockIdx.x;
-  const int ch = b % nchunk;
-  b /= nchunk;
+  const int z = b % Z;
+  b /= Z;
   const int t = b % T;
   const int q = b / T;
-  const int p0 = ch * PC;
-  const int Vs = X * Y * Z;
-  const long long vh = (long long)Vs * T / 2;
-  const int Xh = X / 2;
-  double sre[PC], sim[PC];
-#pragma unroll
-  for (int j = 0; j < PC; ++j) sre[j] = sim[j] = 0.0;
-  const double* a = acc + (long long)q * 2 * vh;
-  for (int i = threadIdx.x; i < Vs; i += blockDim.x) {
-    const int par = i / (Vs / 2);
-    const int sl = i - par * (Vs / 2);
-    const long long s = (long long)t * (Vs / 2) + sl;
-    const int xh = sl % Xh;
-    int rest = sl / Xh;
-    const int y = rest % Y;
-    const int z = rest / Y;
+  const int Xh = X / 2, half = Xh * Y;
+  const long long base = (long long)q * 2 * vp + (long long)half * (z + (long long)Z * t);
+  for (int i = threadIdx.x; i < X * Y; i += blockDim.x) {
+    const int par = i / half, rem = i - par * half;
+    const int y = rem / Xh, xh = rem - y * Xh;
     const int x = 2 * xh + ((par + y + z + t) & 1);
-    const double v = a[par * vh + s];
-#pragma unroll
-    for (int j = 0; j < PC; ++j) {
-      const int p = p0 + j;
-      if (p < np) {
-        const double2 fx = px[p * X + x], fy = py[p * Y + y], fz = pz[p * Z + z];
-        const double re1 = fx.x * fy.x - fx.y * fy.y, im1 = fx.x * fy.y + fx.y * fy.x;
-        const double re = re1 * fz.x - im1 * fz.y, im = re1 * fz.y + im1 * fz.x;
-        sre[j] += v * re;
-        sim[j] += v * im;
-      }
-    }
-  }
-  __shared__ double red[4][PC][2];
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-#pragma unroll
-  for (int j = 0; j < PC; ++j) {
-    const double r = wave_sum(sre[j]), im = wave_sum(sim[j]);
-    if (lane == 0) { red[wv][j][0] = r; red[wv][j][1] = im; }
+    const long long k = base + par * vp + rem;
+    double val = 0.0;
+    if (a0) val += w0 * a0[k];
+    if (a1) val += w1 * a1[k];
+    if (a2) val += w2 * a2[k];
+    v[y * X + x] = val;
   }
   __syncthreads();
-  if (threadIdx.x < PC) {
-    const int j = threadIdx.x, p = p0 + j;
-    if (p < np) {
-      const double r = (red[0][j][0] + red[1][j][0]) + (red[2][j][0] + red[3][j][0]);
-      const double im = (red[0][j][1] + red[1][j][1]) + (red[2][j][1] + red[3][j][1]);
-      proj[((long long)q * T + t) * np + p] = make_double2(r, im);
+  for (int o = threadIdx.x; o < Y * nkx; o += blockDim.x) {
+    const int y = o / nkx, ix = o - y * nkx;
+    const double2* ph = px + (long long)ix * X;
+    double re = 0.0, im = 0.0;
+    for (int x = 0; x < X; ++x) {
+      const double val = v[y * X + x];
+      re += val * ph[x].x;
+      im += val * ph[x].y;
     }
+    r1[o] = make_double2(re, im);
+  }
+  __syncthreads();
+  double2* out = r2 + ((long long)(q * T + t) * Z + z) * nkxy;
+  for (int j = threadIdx.x; j < nkxy; j += blockDim.x) {
+    const int ix = pair_ix[j];
+    const double2* ph = py + (long long)j * Y;
+    double re = 0.0, im = 0.0;
+    for (int y = 0; y < Y; ++y) {
+      const double2 a = r1[y * nkx + ix], f = ph[y];
+      re += a.x * f.x - a.y * f.y;
+      im += a.x * f.y + a.y * f.x;
+    }
+    out[j] = make_double2(re, im);
   }
 }
 
-void launch_project(const double* acc, int nq, int X, int Y, int Z, int T, int np, const double* phase_x,
-                    const double* phase_y, const double* phase_z, double* proj, hipStream_t st) {
-  if (np <= 0 || nq <= 0) return;
-  const double2 *px = (const double2*)phase_x, *py = (const double2*)phase_y, *pz = (const double2*)phase_z;
-  if (np <= 8) {
-    hipLaunchKernelGGL(k_project<8>, dim3(nq * T), dim3(256), 0, st, acc, X, Y, Z, T, np, px, py, pz,
-                       (double2*)proj);
-  } else if (np <= 16) {
-    hipLaunchKernelGGL(k_project<16>, dim3(nq * T), dim3(256), 0, st, acc, X, Y, Z, T, np, px, py, pz,
-                       (double2*)proj);
-  } else {
-    const int nchunk = (np + 31) / 32;
-    hipLaunchKernelGGL(k_project<32>, dim3(nq * T * nchunk), dim3(256), 0, st, acc, X, Y, Z, T, np, px, py,
-                       pz, (double2*)proj);
+// Stage 3.  Rows q >= q_link hold link-centred derivative sums F(x, nu)
+// (nu = (q - q_link) / 48) whose site value is F(x) + F(x - nu): spatial nu
+// multiplies the projection by 1 + e^{-2 pi i n_nu / L_nu}, nu = t adds the
+// projection of time slice t - 1 (periodic wrap; the boundary sign is inside F).
+__global__ __launch_bounds__(256) void k_proj_z(const double2* r2, int nq, int q_link, int Z, int T, int np, int nkxy,
+                                                const double2* pz, const int* pj, const double2* shift,
+                                                double2* proj) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)nq * T * np) return;
+  const int p = (int)(i % np);
+  const long long qt = i / np;
+  const int t = (int)(qt % T), q = (int)(qt / T);
+  const int j = pj[p];
+  const double2* ph = pz + (long long)p * Z;
+  auto zsum = [&](int tt) {
+    const double2* row = r2 + (long long)(q * T + tt) * Z * nkxy + j;
+    double re = 0.0, im = 0.0;
+    for (int z = 0; z < Z; ++z) {
+      const double2 a = row[(long long)z * nkxy], f = ph[z];
+      re += a.x * f.x - a.y * f.y;
+      im += a.x * f.y + a.y * f.x;
+    }
+    return make_double2(re, im);
+  };
+  double2 r = zsum(t);
+  if (q >= q_link) {
+    const int nu = (q - q_link) / 48;
+    if (nu < 3) {
+      const double2 f = shift[p * 3 + nu];
+      r = make_double2(r.x * f.x - r.y * f.y, r.x * f.y + r.y * f.x);
+    } else {
+      const double2 o = zsum(t == 0 ? T - 1 : t - 1);
+      r.x += o.x;
+      r.y += o.y;
+    }
   }
+  proj[i] = r;
+}
+
+void launch_project(const double* const acc[3], const double w[3], int nq, int q_link, int X, int Y, int Z, int T,
+                    const ProjTables& tb, double* r2, double* proj, hipStream_t st) {
+  if (tb.np <= 0 || nq <= 0) return;
+  const long long vp = pad_half((long long)X * Y * Z * T / 2);
+  const size_t lds = sizeof(double) * (size_t)X * Y + sizeof(double2) * (size_t)Y * tb.nkx;
+  if (lds > 65536) throw std::runtime_error("momentum projection: x-y plane too large for LDS");
+  hipLaunchKernelGGL(k_proj_plane, dim3((unsigned)(nq * T * Z)), dim3(256), lds, st, acc[0], acc[1], acc[2], w[0],
+                     w[1], w[2], X, Y, Z, T, vp, tb.nkx, tb.nkxy, (const double2*)tb.px, (const double2*)tb.py,
+                     tb.pair_ix, (double2*)r2);
+  const long long n = (long long)nq * T * tb.np;
+  hipLaunchKernelGGL(k_proj_z, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (const double2*)r2, nq, q_link,
+                     Z, T, tb.np, tb.nkxy, (const double2*)tb.pz, tb.pj, (const double2*)tb.shift, (double2*)proj);
 }
 
 // ---------------------------------------------------------------------------
-// final assembly: Gamma rebuild, TSM combination, prefactors
+// final assembly: Gamma rebuild and prefactors (the TSM sets are combined
+// before the projection)
 // ---------------------------------------------------------------------------
 struct GammaTable {
   int col[16][4];       // Gamma_n has one nonzero per row a, at column col[n][a]
@@ -116,9 +152,8 @@ __device__ inline double2 op_entry(const double2* blk, int hermitian_kind, int a
   return make_double2(-re.x - im.y, -re.y + im.x);          // -P(re) + i P(im)
 }
 
-__global__ __launch_bounds__(256) void k_loops_finalize(const double2* plp, const double2* php, const double2* plc,
-                                                        double w_lp, double w_hp, int nops, int T, int np,
-                                                        double2 pf_t3, double2 pf_1, double2* out) {
+__global__ __launch_bounds__(256) void k_loops_finalize(const double2* pr, int nops, int T, int np, double2 pf_t3,
+                                                        double2 pf_1, double2* out) {
   const long long n_out = 2ll * nops * 16 * T * np;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_out) return;
@@ -136,16 +171,7 @@ __global__ __launch_bounds__(256) void k_loops_finalize(const double2* plp, cons
     const int b = c_gamma.col[n][a];
     const double gr = c_gamma.ph[n][a][0], gi = c_gamma.ph[n][a][1];
     const double g5 = (fl == 0 && a >= 2) ? -1.0 : 1.0;   // tau_3 structure: xi = gamma_5 s
-    double2 v = make_double2(0.0, 0.0);
-    if (w_lp != 0.0) {
-      const double2 x = op_entry(plp + (long long)base * stride, kind, a, b, stride, tp);
-      v.x += w_lp * x.x; v.y += w_lp * x.y;
-    }
-    if (w_hp != 0.0) {
-      const double2 x = op_entry(php + (long long)base * stride, kind, a, b, stride, tp);
-      const double2 y = op_entry(plc + (long long)base * stride, kind, a, b, stride, tp);
-      v.x += w_hp * (x.x - y.x); v.y += w_hp * (x.y - y.y);
-    }
+    const double2 v = op_entry(pr + (long long)base * stride, kind, a, b, stride, tp);
     re += g5 * (gr * v.x - gi * v.y);
     im += g5 * (gr * v.y + gi * v.x);
   }
@@ -225,8 +251,7 @@ void launch_omega(const double* g, int nops, int X, int Y, int Z, int T, int np,
                      (double2*)omega);
 }
 
-void launch_loops_finalize(const double* proj_lp, const double* proj_hp, const double* proj_lpc, double w_lp,
-                           double w_hp, int nops, int T, int np, double kappa, double mu, double* out,
+void launch_loops_finalize(const double* proj, int nops, int T, int np, double kappa, double mu, double* out,
                            hipStream_t st) {
   const long long n_out = 2ll * nops * 16 * T * np;
   if (n_out == 0) return;
@@ -234,8 +259,7 @@ void launch_loops_finalize(const double* proj_lp, const double* proj_hp, const d
   const double2 pf_t3 = make_double2(0.0, -2.0 * mu * 4.0 * kappa * kappa);
   const double2 pf_1 = make_double2(4.0 * kappa, 0.0);
   hipLaunchKernelGGL(k_loops_finalize, dim3((unsigned)((n_out + 255) / 256)), dim3(256), 0, st,
-                     (const double2*)proj_lp, (const double2*)proj_hp, (const double2*)proj_lpc, w_lp, w_hp,
-                     nops, T, np, pf_t3, pf_1, (double2*)out);
+                     (const double2*)proj, nops, T, np, pf_t3, pf_1, (double2*)out);
 }
 
 }  // namespace dl

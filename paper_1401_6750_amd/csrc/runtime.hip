@@ -225,6 +225,7 @@ struct Batch {
       d.Xh = d.X / 2;
       d.Vh = (int)L->Vh;
       d.ntile = (d.Vh + TILE - 1) / TILE;
+      d.Vp = (int)pad_half(d.Vh);
       d.nrhs = sp.nrhs;
       d.ubeg[UK_RHS] = ur; d.ubeg[UK_SITE] = us; d.ubeg[UK_DERIV] = ud; d.ubeg[UK_GRP] = ug;
       d.rhs_begin = rb;
@@ -249,7 +250,7 @@ struct Batch {
       ud += 8 * d.ntile;
       ug += d.ntile * ((d.nrhs + RG - 1) / RG);
       rb += d.nrhs;
-      fo += (long long)d.nrhs * d.Vh;
+      fo += (long long)d.nrhs * d.Vp;
       hs.push_back(d);
     }
     nslots = (int)hs.size();
@@ -365,7 +366,7 @@ static void contract_passes(Batch& b, int P, const void* s_e, const void* s_o, c
     if (!d.acc) continue;
     if (!merged.empty()) {
       SlotDesc& m = merged.back();
-      if (m.acc == d.acc && m.gauge[0] == d.gauge[0] && m.fo + (long long)m.nrhs * m.Vh == d.fo) {
+      if (m.acc == d.acc && m.gauge[0] == d.gauge[0] && m.fo + (long long)m.nrhs * m.Vp == d.fo) {
         m.nrhs += d.nrhs;
         continue;
       }
@@ -886,8 +887,8 @@ int autotune_block(dl_ctx* ctx, dl_lattice* lat, int prec, int nsrc_hint) {
   snprintf(key, sizeof(key), "%dx%dx%dx%d:%s", lat->dims[0], lat->dims[1], lat->dims[2], lat->dims[3], pname[prec]);
   auto it = ctx->tune.find(key);
   if (it == ctx->tune.end()) {
-    const int cands[] = {1, 2, 4, 8, 16, 32, 64};
-    const int total = 64;
+    const int cands[] = {1, 2, 4, 8, 16, 32, 64, 128};
+    const int total = 128;
     double best_t = 1e300;
     int best = 16;
     hipEvent_t e0, e1;
@@ -963,9 +964,10 @@ bool solve_jobs(dl_ctx* ctx, const std::vector<dl_job>& J, dl_src_stats* stats) 
       int nrhs = 0;
       while (i < all.size()) {
         const SlotPlan& sp = all[i];
-        double per = (double)sp.lat->Vh * sp.nrhs * (7.0 * chunks_of(P) * 16);
-        if (tier == DL_TIER_HP_FP32) per += (double)sp.lat->Vh * sp.nrhs * 9.0 * 192;
-        if (J[sp.job].report_true_resid) per += (double)sp.lat->Vh * sp.nrhs * 6.0 * 192;
+        const double vp = (double)pad_half(sp.lat->Vh);
+        double per = vp * sp.nrhs * (7.0 * chunks_of(P) * 16);
+        if (tier == DL_TIER_HP_FP32) per += vp * sp.nrhs * 9.0 * 192;
+        if (J[sp.job].report_true_resid) per += vp * sp.nrhs * 6.0 * 192;
         if (!wave.empty() && (bytes + per > budget || nrhs + sp.nrhs > max_rhs)) break;
         wave.push_back(sp);
         bytes += per;

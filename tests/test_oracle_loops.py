@@ -205,3 +205,28 @@ def test_tsm_is_unbiased():
     # the LP-only estimate is biased by much more than the TSM one for some component
     lp_only = loops.estimate(per_lp, kappa, mu)
     assert np.abs(lp_only - exact).max() > np.abs(est - exact).max()
+
+
+def test_derivative_insertion_link_centred_form():
+    """E(x) = F(x) + F(x - nu) with the per-link F(x) = 1/4 [xi(x)^dag Gamma T_phi(x)
+    - T_xi(x)^dag Gamma phi(x)], T_psi(x) = U_nu(x) psi(x + nu): the form in which the
+    GPU accumulates the one-derivative insertions before projecting (the backward half of
+    D at x + nu repeats the forward half at x).  Random fields, antiperiodic in t."""
+    dims = (4, 2, 4, 6)
+    X, Y, Z, T = dims
+    U = synth.random_gauge(dims, 77, 0.5)
+    rng = np.random.default_rng(5)
+    shape = (T, Z, Y, X, 4, 3)
+    xi = rng.normal(size=shape) + 1j * rng.normal(size=shape)
+    phi = rng.normal(size=shape) + 1j * rng.normal(size=shape)
+    bc = -1
+    site = loops.site_loops(U, xi, phi, bc, deriv=True)            # [5, 16, T, Z, Y, X]
+    for nu in range(4):
+        ax = dirac.SPINOR_AXIS[nu]
+        t_phi = dirac.color_mul(U[..., nu, :, :], dirac.shift_forward(phi, nu, bc, ax))
+        t_xi = dirac.color_mul(U[..., nu, :, :], dirac.shift_forward(xi, nu, bc, ax))
+        f = 0.25 * (loops.insert_gammas(loops.outer_product(xi, t_phi))
+                    - loops.insert_gammas(loops.outer_product(t_xi, phi)))   # [16, T, Z, Y, X]
+        lat_axis = 1 + (3 - nu)                                     # axes of f: n, t, z, y, x
+        f_back = np.roll(f, 1, axis=lat_axis)                       # F(x - nu), no extra sign
+        assert rel(f + f_back, site[1 + nu]) < 1e-13, nu
