@@ -9,7 +9,8 @@ all 160 local and one-derivative insertions accumulated in FP64 on the GPU,
 and the momentum projection (p^2 <= 4) with the TSM combination.  Inputs are
 resident on the GPU before timing starts; the loops stay in device memory.
 
-Prints one JSON line ("Measurement").
+Prints one JSON line: the metric, the roofline of the dominant hopping kernel
+and the single-thread oracle baseline.
 """
 from __future__ import annotations
 
@@ -192,7 +193,7 @@ def main() -> int:
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; the per-GPU share of a multi-GPU run is the "
-              "N=1 workload (sources shard across GPUs with one final reduction, see DESIGN.md)",
+              "N=1 workload (sources shard across GPUs with one final reduction of the projected loops)",
               file=sys.stderr)
         return 2
 

@@ -1,7 +1,7 @@
 """Gradients of the one-end-trick loops with respect to the sources and mu (FP64).
 
 The paper computes loops but no gradients; this is the derivative of the same
-estimator (SURVEY's differentiation workload).  Convention (PyTorch's for
+estimator, used by the backward pass of the loop function.  Convention (PyTorch's for
 complex tensors): the gradient of a real loss F with respect to a complex z is
 dF/dRe z + i dF/dIm z (= 2 dF/dz^*).  With upstream gradient g of the loops L,
 F = Re sum_k conj(g_k) L_k to first order, and:

@@ -266,14 +266,23 @@ __device__ inline void load_link<f16s>(const void* g, long vh, int mu, int par, 
 // UK_DERIV (one tile x parity x direction), UK_GRP (one tile x RG rhs: the
 // hopping kernel runs RG right-hand sides per wavefront).
 enum UnitKind : int { UK_RHS = 0, UK_SITE = 1, UK_DERIV = 2, UK_GRP = 3 };
-// Right-hand sides per wavefront in the hopping kernel.  2 shares the link
-// loads and index arithmetic but costs occupancy (180 vs 120 registers in the
-// epilogue-heavy variants); on gfx950 1 measured faster (9.6 vs 10.8 ms per
-// 24^3x48 bf16 launch of ~525 right-hand sides).
+// Right-hand sides per wavefront in the hopping kernel.  Sharing a wave
+// shares the link loads, the link-word preparation and the index arithmetic,
+// at the cost of registers.  Measured on gfx950 at 24^3x48: bf16 8.2 ms per
+// 525-rhs launch with two against 8.9 ms with one (the 16-bit kernels keep
+// spinors packed, so two fit in ~110 registers); FP32 HP solves +10 % and the
+// FP64 single-rhs path +27 % with two.  DL_RHS_PER_WAVE_WIDE sets FP32 / FP64
+// separately (1 or RG).  UK_GRP units are groups of RG right-hand sides.
 #ifndef DL_RHS_PER_WAVE
-#define DL_RHS_PER_WAVE 1
+#define DL_RHS_PER_WAVE 2
+#endif
+#ifndef DL_RHS_PER_WAVE_WIDE
+#define DL_RHS_PER_WAVE_WIDE 2
 #endif
 constexpr int RG = DL_RHS_PER_WAVE;
+static_assert(DL_RHS_PER_WAVE_WIDE == 1 || DL_RHS_PER_WAVE_WIDE == RG, "wide types use 1 or RG rhs per wave");
+template <class S> constexpr int rhs_per_wave() { return Traits<S>::NC == 3 ? RG : DL_RHS_PER_WAVE_WIDE; }
+inline int rhs_per_wave_prec(int prec) { return (prec == PB16 || prec == PH16) ? RG : DL_RHS_PER_WAVE_WIDE; }
 
 // Site stride of every per-parity device array (spinor chunk rows, link
 // records, accumulator rows): Vh rounded up to an odd number of 64-site

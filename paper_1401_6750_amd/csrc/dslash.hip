@@ -1,21 +1,24 @@
 // Even-odd twisted-mass Wilson hopping kernel with fused site-local epilogues.
 //
-// One wavefront handles one unit = 64 consecutive even-odd sites of RG right-
-// hand sides of one batch slot: the site coordinates, the eight neighbour
-// indices and every gauge link are computed / loaded once and used for all RG
+// One wavefront handles one unit = 64 consecutive even-odd sites of G right-
+// hand sides of one batch slot (G = rhs_per_wave: two for 16-bit storage,
+// one for FP32 / FP64): the site coordinates, the eight neighbour indices
+// and every gauge link are computed / loaded once and used for all G
 // right-hand sides.  Units of one tile are consecutive for all right-hand-side
-// groups of the slot, and each XCD receives a contiguous range of units, so a
-// tile's links are fetched once into that XCD's L2.  In 16-bit storage the
-// kernel is bound by instruction issue rather than HBM bandwidth, so the
-// design minimises per-(site, rhs) work that is not arithmetic of the hop:
-// conversions use the packed hardware converts, neighbour indices are
-// offsets of the lexicographic index.
+// groups of the slot, tiles are visited in time-blocked order (tile_of), and
+// each XCD receives a contiguous range of units, so a tile's links are
+// fetched once into that XCD's L2.  In 16-bit storage the kernel is bound by
+// instruction issue rather than HBM bandwidth, so the design minimises
+// per-(site, rhs) work that is not arithmetic of the hop: the colour
+// products run on the packed 16-bit words (dot2), conversions use the packed
+// hardware converts, neighbour indices are offsets of the lexicographic index.
 //
 // Operator pieces (kappa normalised, chiral basis, gamma_5 = diag(1,1,-1,-1)):
 //   (H psi)(x) = sum_mu (1 - gamma_mu) U_mu(x) psi(x+mu) + (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu)
-// A hop through (1 -+ gamma_mu) is done on the two independent spin
-// combinations h0, h1 (colour vectors) and the lower two spin components are
-// rebuilt from them, so each neighbour costs two SU(3) x colour products.
+// In FP32 / FP64 a hop through (1 -+ gamma_mu) is done on the two independent
+// spin combinations h0, h1 (colour vectors) and the lower two spin components
+// are rebuilt from them, so each neighbour costs two SU(3) x colour products;
+// the 16-bit path multiplies all four spin components (see hop).
 //
 // Epilogue (per-spin complex factors, set per slot):
 //   res = e (.) H(d (.) in) + f (.) y,   out = g (.) res
@@ -72,61 +75,156 @@ __device__ inline void project(const cx<R> (&v)[12], cx<R> (&h0)[3], cx<R> (&h1)
   }
 }
 
-// Accumulate the full four-spinor rebuilt from the projected pair (w0, w1).
-template <int MU, bool FWD, class R>
-__device__ inline void reconstruct(cx<R> (&acc)[12], const cx<R> (&w0)[3], const cx<R> (&w1)[3]) {
+// Accumulate the full four-spinor rebuilt from the projected pair (w0, w1),
+// times the hop's boundary factor `sign` (used for MU = 3 only, folded into
+// the adds as FMAs).  INIT: the first hop of a site assigns instead of adding.
+template <int MU, bool FWD, bool INIT, class R>
+__device__ inline void reconstruct(cx<R> (&acc)[12], const cx<R> (&w0)[3], const cx<R> (&w1)[3], R sign) {
+  auto put = [&](cx<R>& a, cx<R> w) {
+    if (INIT) a = w; else a = a + w;
+  };
+  auto put_s = [&](cx<R>& a, cx<R> w, R f) {   // a (+)= f w
+    if (INIT) a = f * w; else a = mk<R>(fmadd(f, w.re, a.re), fmadd(f, w.im, a.im));
+  };
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    acc[c] = acc[c] + w0[c];
-    acc[3 + c] = acc[3 + c] + w1[c];
     if (MU == 0) {
-      acc[6 + c] = acc[6 + c] + (FWD ? times_mi(w1[c]) : times_i(w1[c]));
-      acc[9 + c] = acc[9 + c] + (FWD ? times_mi(w0[c]) : times_i(w0[c]));
+      put(acc[c], w0[c]);
+      put(acc[3 + c], w1[c]);
+      put(acc[6 + c], FWD ? times_mi(w1[c]) : times_i(w1[c]));
+      put(acc[9 + c], FWD ? times_mi(w0[c]) : times_i(w0[c]));
     } else if (MU == 1) {
-      acc[6 + c] = FWD ? acc[6 + c] - w1[c] : acc[6 + c] + w1[c];
-      acc[9 + c] = FWD ? acc[9 + c] + w0[c] : acc[9 + c] - w0[c];
+      put(acc[c], w0[c]);
+      put(acc[3 + c], w1[c]);
+      if (INIT) {
+        acc[6 + c] = FWD ? mk<R>(-w1[c].re, -w1[c].im) : w1[c];
+        acc[9 + c] = FWD ? w0[c] : mk<R>(-w0[c].re, -w0[c].im);
+      } else {
+        acc[6 + c] = FWD ? acc[6 + c] - w1[c] : acc[6 + c] + w1[c];
+        acc[9 + c] = FWD ? acc[9 + c] + w0[c] : acc[9 + c] - w0[c];
+      }
     } else if (MU == 2) {
-      acc[6 + c] = acc[6 + c] + (FWD ? times_mi(w0[c]) : times_i(w0[c]));
-      acc[9 + c] = acc[9 + c] + (FWD ? times_i(w1[c]) : times_mi(w1[c]));
+      put(acc[c], w0[c]);
+      put(acc[3 + c], w1[c]);
+      put(acc[6 + c], FWD ? times_mi(w0[c]) : times_i(w0[c]));
+      put(acc[9 + c], FWD ? times_i(w1[c]) : times_mi(w1[c]));
     } else {
-      acc[6 + c] = FWD ? acc[6 + c] - w0[c] : acc[6 + c] + w0[c];
-      acc[9 + c] = FWD ? acc[9 + c] - w1[c] : acc[9 + c] + w1[c];
+      const R ms = -sign;
+      put_s(acc[c], w0[c], sign);
+      put_s(acc[3 + c], w1[c], sign);
+      put_s(acc[6 + c], w0[c], FWD ? ms : sign);
+      put_s(acc[9 + c], w1[c], FWD ? ms : sign);
     }
   }
 }
 
+// 16-bit storage: FP32 dot product of two packed (re, im) pairs, c + a.lo b.lo
+// + a.hi b.hi.  The products of 16-bit values are exact in FP32, so this is
+// FP32 arithmetic on the stored values without unpacking them.
+template <class S> __device__ inline float dot2(uint32_t a, uint32_t b, float c);
+template <> __device__ inline float dot2<bf16s>(uint32_t a, uint32_t b, float c) {
+  return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a), __builtin_bit_cast(bf16x2_t, b), c, false);
+}
+template <> __device__ inline float dot2<f16s>(uint32_t a, uint32_t b, float c) {
+  return __builtin_amdgcn_fdot2(__builtin_bit_cast(f16x2_t, a), __builtin_bit_cast(f16x2_t, b), c, false);
+}
+// First product of a chain: the three-operand form with an inline zero
+// accumulator (the two-operand form accumulates into its destination and
+// would need the register cleared first).
+template <class S> __device__ inline float dot2_first(uint32_t a, uint32_t b);
+template <> __device__ inline float dot2_first<bf16s>(uint32_t a, uint32_t b) {
+  float r;
+  asm("v_dot2_f32_bf16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+template <> __device__ inline float dot2_first<f16s>(uint32_t a, uint32_t b) {
+  float r;
+  asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ inline uint32_t swap16(uint32_t w) { return (w >> 16) | (w << 16); }
+
 // One hop (direction MU, forward or backward) for every right-hand side of
 // the group: the link is loaded once.
-template <class S, int MU, bool FWD, bool HAS_D>
+//
+// 16-bit storage without the input factor d: the colour products are formed
+// on the packed words.  With M = U (forward) or U^dag (backward), each entry
+// M_ab contributes Re += dot2(cr_ab, psi_b), Im += dot2(ci_ab, psi_b) where
+//   forward:  cr = (Re U_ab, -Im U_ab), ci = (Im U_ab, Re U_ab)
+//   backward: cr = (Re U_ba,  Im U_ba), ci = (-Im U_ba, Re U_ba),
+// so every spin component is multiplied (4 colour vectors instead of the 2
+// projected ones, at half the instructions per product) and the spin
+// projection is taken on the products, M(1 -+ gamma) psi = (1 -+ gamma) M psi.
+template <class S, int MU, bool FWD, bool HAS_D, bool INIT, int G>
 __device__ inline void hop(const void* gauge, long vp, int link_par, int link_site, int nb, typename Traits<S>::R sign,
-                           const void* const (&inb)[RG], int nr, const bool (&act)[RG],
-                           const cx<typename Traits<S>::R> (&d)[4], cx<typename Traits<S>::R> (&acc)[RG][12]) {
+                           const void* const (&inb)[G], int nr, const bool (&act)[G],
+                           const cx<typename Traits<S>::R> (&d)[4], cx<typename Traits<S>::R> (&acc)[G][12]) {
   using R = typename Traits<S>::R;
-  cx<R> u[9];
-  load_link<S>(gauge, vp, MU, link_par, link_site, u);
-  if (MU == 3) {
+  if constexpr (Traits<S>::NC == 3 && !HAS_D) {
+    const uint4* lp = (const uint4*)gauge + ((long)(MU * 2 + link_par) * vp + link_site) * 3;
+    const uint4 l0 = lp[0], l1 = lp[1], l2 = lp[2];
+    const uint32_t e[9] = {l0.x, l0.y, l0.z, l0.w, l1.x, l1.y, l1.z, l1.w, l2.x};
+    uint32_t cr[9], ci[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) u[k] = sign * u[k];
-  }
+    for (int a = 0; a < 3; ++a)
 #pragma unroll
-  for (int i = 0; i < RG; ++i) {
-    if (i >= nr || !act[i]) continue;
-    cx<R> v[12];
-    load_spinor<S>(inb[i], vp, nb, v);
-    if (HAS_D) {
+      for (int b = 0; b < 3; ++b) {
+        if (FWD) {
+          const uint32_t w = e[3 * a + b];
+          cr[3 * a + b] = w ^ 0x80000000u;
+          ci[3 * a + b] = swap16(w);
+        } else {
+          const uint32_t w = e[3 * b + a];
+          cr[3 * a + b] = w;
+          ci[3 * a + b] = swap16(w) ^ 0x00008000u;
+        }
+      }
 #pragma unroll
-      for (int k = 0; k < 12; ++k) v[k] = d[k / 3] * v[k];
+    for (int i = 0; i < G; ++i) {
+      if (i >= nr || !act[i]) continue;
+      const uint4* q = (const uint4*)inb[i];
+      const uint4 q0 = q[nb], q1 = q[vp + nb], q2 = q[2 * vp + nb];
+      const uint32_t v[12] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w};
+      cx<float> chi[12];
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          float re = dot2_first<S>(cr[3 * a], v[3 * s4]);
+          re = dot2<S>(cr[3 * a + 1], v[3 * s4 + 1], re);
+          re = dot2<S>(cr[3 * a + 2], v[3 * s4 + 2], re);
+          float im = dot2_first<S>(ci[3 * a], v[3 * s4]);
+          im = dot2<S>(ci[3 * a + 1], v[3 * s4 + 1], im);
+          im = dot2<S>(ci[3 * a + 2], v[3 * s4 + 2], im);
+          chi[3 * s4 + a] = mk<float>(re, im);
+        }
+      cx<float> w0[3], w1[3];
+      project<MU, FWD>(chi, w0, w1);
+      reconstruct<MU, FWD, INIT>(acc[i], w0, w1, sign);
     }
-    cx<R> h0[3], h1[3], w0[3], w1[3];
-    project<MU, FWD>(v, h0, h1);
-    if (FWD) {
-      su3_mul(u, h0, w0);
-      su3_mul(u, h1, w1);
-    } else {
-      su3_dag_mul(u, h0, w0);
-      su3_dag_mul(u, h1, w1);
+  } else {
+    cx<R> u[9];
+    load_link<S>(gauge, vp, MU, link_par, link_site, u);
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      if (i >= nr || !act[i]) continue;
+      cx<R> v[12];
+      load_spinor<S>(inb[i], vp, nb, v);
+      if (HAS_D) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) v[k] = d[k / 3] * v[k];
+      }
+      cx<R> h0[3], h1[3], w0[3], w1[3];
+      project<MU, FWD>(v, h0, h1);
+      if (FWD) {
+        su3_mul(u, h0, w0);
+        su3_mul(u, h1, w1);
+      } else {
+        su3_dag_mul(u, h0, w0);
+        su3_dag_mul(u, h1, w1);
+      }
+      reconstruct<MU, FWD, INIT>(acc[i], w0, w1, sign);
     }
-    reconstruct<MU, FWD>(acc[i], w0, w1);
   }
 }
 
@@ -139,21 +237,23 @@ __device__ inline void load_coef(const double (&c)[4][2], cx<R> (&out)[4]) {
 template <class S, int F>
 __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
   using R = typename Traits<S>::R;
+  constexpr int G = rhs_per_wave<S>();
+  constexpr int UK = G == 1 ? UK_RHS : UK_GRP;
   const int u = wave_unit();
   if (u >= a.total_units) return;
   const int lane = threadIdx.x & 63;
-  const int si = find_slot(a.slots, a.nslots, UK_GRP, u);
+  const int si = find_slot(a.slots, a.nslots, UK, u);
   const SlotDesc& sd = a.slots[si];
-  const int ngrp = (sd.nrhs + RG - 1) / RG;
-  const int ul = u - sd.ubeg[UK_GRP];
+  const int ngrp = (sd.nrhs + G - 1) / G;
+  const int ul = u - sd.ubeg[UK];
   const int lt = ul / ngrp;
   const int tile = tile_of(sd, lt);
-  const int r0 = (ul - lt * ngrp) * RG;
-  const int nr = min(RG, sd.nrhs - r0);
-  bool act[RG];
+  const int r0 = (ul - lt * ngrp) * G;
+  const int nr = min(G, sd.nrhs - r0);
+  bool act[G];
   bool any = false;
 #pragma unroll
-  for (int i = 0; i < RG; ++i) {
+  for (int i = 0; i < G; ++i) {
     act[i] = i < nr && (!a.active || a.active[sd.rhs_begin + r0 + i]);
     any = any || act[i];
   }
@@ -161,12 +261,12 @@ __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
   const int s = tile * TILE + lane;
   const bool valid = s < sd.Vh;
   const long vp = sd.Vp;   // row stride of fields and link records
-  long long off[RG];
+  long long off[G];
 #pragma unroll
-  for (int i = 0; i < RG; ++i) off[i] = sd.fo + (long long)(r0 + i) * vp;
-  double nrm[RG];
+  for (int i = 0; i < G; ++i) off[i] = sd.fo + (long long)(r0 + i) * vp;
+  double nrm[G];
 #pragma unroll
-  for (int i = 0; i < RG; ++i) nrm[i] = 0.0;
+  for (int i = 0; i < G; ++i) nrm[i] = 0.0;
   if (valid) {
     const Coef& cf = a.coef[si];
     cx<R> d[4], e[4], f[4], g[4];
@@ -192,26 +292,26 @@ __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
     const R sp = (c.t + 1 == sd.T) ? (R)sd.bc : (R)1;
     const R sm = (c.t == 0) ? (R)sd.bc : (R)1;
     const void* gauge = sd.gauge[Traits<S>::prec];
-    const void* inb[RG];
+    const void* inb[G];
 #pragma unroll
-    for (int i = 0; i < RG; ++i) inb[i] = field_at<S>(a.in, off[i]);
-    cx<R> acc[RG][12];
+    for (int i = 0; i < G; ++i) inb[i] = field_at<S>(a.in, off[i]);
+    cx<R> acc[G][12];
 #pragma unroll
-    for (int i = 0; i < RG; ++i)
+    for (int i = 0; i < G; ++i)
 #pragma unroll
-      for (int k = 0; k < 12; ++k) acc[i][k] = mk<R>(0, 0);
+      for (int k = 0; k < 12; ++k) acc[i][k] = mk<R>(0, 0);   // inactive groups keep zeros
     constexpr bool HD = (F & F_D) != 0;
     const int q = 1 - p_out;
-    hop<S, 0, true, HD>(gauge, vp, p_out, s, nxp, (R)1, inb, nr, act, d, acc);
-    hop<S, 0, false, HD>(gauge, vp, q, nxm, nxm, (R)1, inb, nr, act, d, acc);
-    hop<S, 1, true, HD>(gauge, vp, p_out, s, nyp, (R)1, inb, nr, act, d, acc);
-    hop<S, 1, false, HD>(gauge, vp, q, nym, nym, (R)1, inb, nr, act, d, acc);
-    hop<S, 2, true, HD>(gauge, vp, p_out, s, nzp, (R)1, inb, nr, act, d, acc);
-    hop<S, 2, false, HD>(gauge, vp, q, nzm, nzm, (R)1, inb, nr, act, d, acc);
-    hop<S, 3, true, HD>(gauge, vp, p_out, s, ntp, sp, inb, nr, act, d, acc);
-    hop<S, 3, false, HD>(gauge, vp, q, ntm, ntm, sm, inb, nr, act, d, acc);
+    hop<S, 0, true, HD, true>(gauge, vp, p_out, s, nxp, (R)1, inb, nr, act, d, acc);
+    hop<S, 0, false, HD, false>(gauge, vp, q, nxm, nxm, (R)1, inb, nr, act, d, acc);
+    hop<S, 1, true, HD, false>(gauge, vp, p_out, s, nyp, (R)1, inb, nr, act, d, acc);
+    hop<S, 1, false, HD, false>(gauge, vp, q, nym, nym, (R)1, inb, nr, act, d, acc);
+    hop<S, 2, true, HD, false>(gauge, vp, p_out, s, nzp, (R)1, inb, nr, act, d, acc);
+    hop<S, 2, false, HD, false>(gauge, vp, q, nzm, nzm, (R)1, inb, nr, act, d, acc);
+    hop<S, 3, true, HD, false>(gauge, vp, p_out, s, ntp, sp, inb, nr, act, d, acc);
+    hop<S, 3, false, HD, false>(gauge, vp, q, ntm, ntm, sm, inb, nr, act, d, acc);
 #pragma unroll
-    for (int i = 0; i < RG; ++i) {
+    for (int i = 0; i < G; ++i) {
       if (!act[i]) continue;
       cx<R> res[12];
 #pragma unroll
@@ -253,7 +353,7 @@ __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
   }
   if (F & F_NORM) {
 #pragma unroll
-    for (int i = 0; i < RG; ++i) {
+    for (int i = 0; i < G; ++i) {
       if (i >= nr) break;
       const double t = wave_sum(nrm[i]);
       if (lane == 0 && act[i]) a.partial[sd.ubeg[UK_RHS] + tile * sd.nrhs + r0 + i] = t;

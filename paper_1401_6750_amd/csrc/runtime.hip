@@ -293,7 +293,8 @@ struct Batch {
               const int* gate, void* x = nullptr, void* r = nullptr, const void* pp = nullptr,
               void* out2 = nullptr, double* part = nullptr) {
     DslashArgs a{};
-    a.slots = slots(); a.nslots = nslots; a.total_units = u_grp; a.coef = coef(ck); a.p_out = p_out;
+    a.slots = slots(); a.nslots = nslots; a.coef = coef(ck); a.p_out = p_out;
+    a.total_units = rhs_per_wave_prec(p) == 1 ? u_rhs : u_grp;
     a.in = in; a.out = out; a.y = y; a.partial = part ? part : partial.as<double>(); a.active = gate;
     a.x = x; a.r = r; a.p = pp; a.alpha = cs.alpha; a.out2 = out2;
     launch_dslash(p, flags, a, ctx->st);
