@@ -30,7 +30,10 @@ __global__ __launch_bounds__(64) void k_finalize(int kind, const SlotDesc* slots
   const int g = blockIdx.x;
   if (g >= nrhs_total) return;
   const int lane = threadIdx.x;
-  if (kind != FK_INIT && kind != FK_STORE && !cs.active[g]) return;
+  if (kind != FK_INIT && kind != FK_STORE && !cs.active[g]) {
+    if (kind == FK_ALPHA && threadIdx.x == 0) cs.upd[g] = 0;   // no step this iteration
+    return;
+  }
   const SlotDesc& sd = slots[find_slot_by_rhs(slots, nslots, g)];
   const int r = g - sd.rhs_begin;
   double v = 0.0;
@@ -43,15 +46,17 @@ __global__ __launch_bounds__(64) void k_finalize(int kind, const SlotDesc* slots
       cs.cc[g] = v;
       cs.rr[g] = v;
       cs.iters[g] = 0;
+      cs.upd[g] = 0;
       if (!finite) { cs.active[g] = 0; cs.status[g] = 2; }
       else if (v == 0.0) { cs.active[g] = 0; cs.status[g] = 0; }
       else { cs.active[g] = 1; cs.status[g] = 1; }
       break;
     case FK_ALPHA:
       if (!(finite && v > 0.0)) {
-        cs.active[g] = 0; cs.status[g] = 2; cs.alpha[g] = 0.0;
+        cs.active[g] = 0; cs.status[g] = 2; cs.alpha[g] = 0.0; cs.upd[g] = 0;
       } else {
         cs.alpha[g] = cs.rr[g] / v;
+        cs.upd[g] = 1;
       }
       break;
     case FK_BETA: {
@@ -106,19 +111,32 @@ __device__ inline bool decode_rhs_unit(const SlotDesc* slots, int nslots, int to
 
 template <class S>
 __global__ __launch_bounds__(256) void k_update_p(const SlotDesc* slots, int nslots, int total_units, void* p,
-                                                  const void* r, const double* beta, const int* active) {
+                                                  const void* r, void* x, const double* alpha,
+                                                  const double* beta, const int* active, const int* upd) {
   using R = typename Traits<S>::R;
   UnitRhs w;
   if (!decode_rhs_unit(slots, nslots, total_units, w)) return;
-  if (!active[w.g] || !w.valid) return;
+  const bool ux = upd[w.g] != 0, up = active[w.g] != 0;
+  if (!(ux || up) || !w.valid) return;
   const long vp = slots[w.si].Vp;
-  const R b = (R)beta[w.g];
-  cx<R> pv[12], rv[12];
+  cx<R> pv[12];
   load_spinor<S>(field_at<S>(p, w.off), vp, w.s, pv);
-  load_spinor<S>(field_at<S>(r, w.off), vp, w.s, rv);
+  if (ux) {
+    const R al = (R)alpha[w.g];
+    cx<R> xv[12];
+    load_spinor<S>(field_at<S>(x, w.off), vp, w.s, xv);
 #pragma unroll
-  for (int k = 0; k < 12; ++k) pv[k] = rv[k] + b * pv[k];
-  store_spinor<S>(field_at<S>(p, w.off), vp, w.s, pv);
+    for (int k = 0; k < 12; ++k) xv[k] = xv[k] + al * pv[k];
+    store_spinor<S>(field_at<S>(x, w.off), vp, w.s, xv);
+  }
+  if (up) {
+    const R b = (R)beta[w.g];
+    cx<R> rv[12];
+    load_spinor<S>(field_at<S>(r, w.off), vp, w.s, rv);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) pv[k] = rv[k] + b * pv[k];
+    store_spinor<S>(field_at<S>(p, w.off), vp, w.s, pv);
+  }
 }
 
 template <class S>
@@ -144,10 +162,11 @@ __global__ __launch_bounds__(256) void k_zero(const SlotDesc* slots, int nslots,
   }
 
 void launch_update_p(int prec, const SlotDesc* slots, int nslots, int total_units, void* p, const void* r,
-                     const double* beta, const int* active, hipStream_t st) {
+                     void* x, const double* alpha, const double* beta, const int* active, const int* upd,
+                     hipStream_t st) {
   if (!total_units) return;
   DISPATCH_PREC(prec, k_update_p, dim3(grid_for(total_units, 4)), dim3(256), 0, st, slots, nslots,
-                total_units, p, r, beta, active);
+                total_units, p, r, x, alpha, beta, active, upd);
 }
 
 void launch_zero(int prec, const SlotDesc* slots, int nslots, int total_units, void* f, const int* active,

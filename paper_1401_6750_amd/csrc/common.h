@@ -95,6 +95,78 @@ template <> __device__ inline uint32_t pack2<f16s>(cx<float> v) {
 }
 
 // ---------------------------------------------------------------------------
+// packed 16-bit colour products
+// ---------------------------------------------------------------------------
+// 16-bit storage: FP32 dot product of two packed (re, im) pairs, c + a.lo b.lo
+// + a.hi b.hi.  The products of 16-bit values are exact in FP32, so this is
+// FP32 arithmetic on the stored values without unpacking them.
+template <class S> __device__ inline float dot2(uint32_t a, uint32_t b, float c);
+template <> __device__ inline float dot2<bf16s>(uint32_t a, uint32_t b, float c) {
+  return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a), __builtin_bit_cast(bf16x2_t, b), c, false);
+}
+template <> __device__ inline float dot2<f16s>(uint32_t a, uint32_t b, float c) {
+  return __builtin_amdgcn_fdot2(__builtin_bit_cast(f16x2_t, a), __builtin_bit_cast(f16x2_t, b), c, false);
+}
+// First product of a chain: the three-operand form with an inline zero
+// accumulator (the two-operand form accumulates into its destination and
+// would need the register cleared first).
+template <class S> __device__ inline float dot2_first(uint32_t a, uint32_t b);
+template <> __device__ inline float dot2_first<bf16s>(uint32_t a, uint32_t b) {
+  float r;
+  asm("v_dot2_f32_bf16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+template <> __device__ inline float dot2_first<f16s>(uint32_t a, uint32_t b) {
+  float r;
+  asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ inline uint32_t swap16(uint32_t w) { return (w >> 16) | (w << 16); }
+
+// Colour-product coefficients of one link for the packed path: row a of
+// M = U (forward) or U^dag (backward) contributes Re += dot2(cr[3a+b], psi_b),
+// Im += dot2(ci[3a+b], psi_b), with
+//   forward:  cr = (Re U_ab, -Im U_ab), ci = (Im U_ab, Re U_ab)
+//   backward: cr = (Re U_ba,  Im U_ba), ci = (-Im U_ba, Re U_ba).
+// `neg` flips the sign of every entry (a -1 boundary factor of the link).
+template <bool FWD>
+__device__ inline void link_coef16(const uint32_t (&e)[9], bool neg, uint32_t (&cr)[9], uint32_t (&ci)[9]) {
+  const uint32_t m = neg ? 0x80008000u : 0u;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      if (FWD) {
+        const uint32_t w = e[3 * a + b] ^ m;
+        cr[3 * a + b] = w ^ 0x80000000u;
+        ci[3 * a + b] = swap16(w);
+      } else {
+        const uint32_t w = e[3 * b + a] ^ m;
+        cr[3 * a + b] = w;
+        ci[3 * a + b] = swap16(w) ^ 0x00008000u;
+      }
+    }
+}
+
+// out[3 s + a] = sum_b M_ab psi[3 s + b] for the four spins, psi packed words.
+template <class S>
+__device__ inline void colour_mul16(const uint32_t (&cr)[9], const uint32_t (&ci)[9], const uint32_t (&v)[12],
+                                    cx<float> (&out)[12]) {
+#pragma unroll
+  for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      float re = dot2_first<S>(cr[3 * a], v[3 * s4]);
+      re = dot2<S>(cr[3 * a + 1], v[3 * s4 + 1], re);
+      re = dot2<S>(cr[3 * a + 2], v[3 * s4 + 2], re);
+      float im = dot2_first<S>(ci[3 * a], v[3 * s4]);
+      im = dot2<S>(ci[3 * a + 1], v[3 * s4 + 1], im);
+      im = dot2<S>(ci[3 * a + 2], v[3 * s4 + 2], im);
+      out[3 * s4 + a] = mk<float>(re, im);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // spinor loads / stores: base points at chunk 0 of one (rhs, parity) half
 // field; stride is Vh (chunks between consecutive chunk rows).
 // ---------------------------------------------------------------------------

@@ -45,7 +45,10 @@ __device__ constexpr int up_a(int k) { return k < 3 ? 0 : (k < 5 ? 1 : 2); }
 __device__ constexpr int up_b(int k) { return k < 3 ? k + 1 : (k < 5 ? k - 1 : 3); }
 
 // acc: the block's first component (uniform), lane: this lane's site offset.
-template <class A>
+// DERIV: the derivative sums are kept without their constant factors in the
+// source loop (1/2 on the s-s diagonal, 1/4 elsewhere, powers of two, so the
+// scaling is exact) and scaled here.
+template <bool DERIV, class A>
 __device__ inline void flush(double* acc, long long V, int lane, A (&a)[48]) {
   // keep the 48 addresses from being computed once and held across the
   // source loop (that alone would take 96 registers)
@@ -53,7 +56,8 @@ __device__ inline void flush(double* acc, long long V, int lane, A (&a)[48]) {
 #pragma unroll
   for (int q = 0; q < 48; ++q) {
     double* p = acc + q * V;
-    p[lane] += (double)a[q];
+    const double f = DERIV ? (q < 4 ? 0.5 : 0.25) : 1.0;
+    p[lane] += f * (double)a[q];
     a[q] = (A)0;
   }
 }
@@ -114,30 +118,39 @@ __global__ __launch_bounds__(256) void k_contract_local(const SlotDesc* slots, i
         a[17 + 2 * (4 * i + j)] += (A)t.im;
       }
     if (++inblk == AccT<S>::KB) {
-      flush(acc, V, lane_off, a);
+      flush<false>(acc, V, lane_off, a);
       inblk = 0;
     }
   }
-  if (inblk) flush(acc, V, lane_off, a);
+  if (inblk) flush<false>(acc, V, lane_off, a);
 }
 
-// Forward transport of one rhs field along nu: out = b U_nu(x) psi(x+nu),
-// b the time-boundary factor of the link.
+// Forward transport of one rhs field along nu: out = M psi(x+nu), M = b U_nu(x)
+// with the link's boundary factor b already folded in.  16-bit fields use the
+// packed colour products (coefficients cr / ci prepared once per unit).
 template <class S>
-__device__ inline void transport_fwd(const void* f_other, long vp, int sp, typename Traits<S>::R b,
-                                     const cx<typename Traits<S>::R> (&u)[9], cx<typename Traits<S>::R> (&out)[12]) {
+__device__ inline void transport_fwd(const void* f_other, long vp, int sp, const cx<typename Traits<S>::R> (&u)[9],
+                                     const uint32_t (&cr)[9], const uint32_t (&ci)[9],
+                                     cx<typename Traits<S>::R> (&out)[12]) {
   using R = typename Traits<S>::R;
-  cx<R> v[12];
-  load_spinor<S>(f_other, vp, sp, v);
+  if constexpr (Traits<S>::NC == 3) {
+    const uint4* q = (const uint4*)f_other;
+    const uint4 q0 = q[sp], q1 = q[vp + sp], q2 = q[2 * vp + sp];
+    const uint32_t v[12] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w};
+    colour_mul16<S>(cr, ci, v, out);
+  } else {
+    cx<R> v[12];
+    load_spinor<S>(f_other, vp, sp, v);
 #pragma unroll
-  for (int s4 = 0; s4 < 4; ++s4)
+    for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      cx<R> f = u[3 * a] * v[3 * s4];
-      cmac(f, u[3 * a + 1], v[3 * s4 + 1]);
-      cmac(f, u[3 * a + 2], v[3 * s4 + 2]);
-      out[3 * s4 + a] = b * f;
-    }
+      for (int a = 0; a < 3; ++a) {
+        cx<R> f = u[3 * a] * v[3 * s4];
+        cmac(f, u[3 * a + 1], v[3 * s4 + 1]);
+        cmac(f, u[3 * a + 2], v[3 * s4 + 2]);
+        out[3 * s4 + a] = f;
+      }
+  }
 }
 
 // One-derivative contractions in link-centred form.  With T_psi(x) =
@@ -173,7 +186,17 @@ __global__ __launch_bounds__(256) void k_contract_deriv(const SlotDesc* slots, i
   const int sp = eo_index(sd, xp[0], xp[1], xp[2], xp[3]);
   const void* gauge = sd.gauge[Traits<S>::prec];
   cx<R> up[9];
-  load_link<S>(gauge, vp, nu, par, s, up);
+  uint32_t cr[9], ci[9];
+  if constexpr (Traits<S>::NC == 3) {
+    const uint4* lp = (const uint4*)gauge + ((long)(nu * 2 + par) * vp + s) * 3;
+    const uint4 l0 = lp[0], l1 = lp[1], l2 = lp[2];
+    const uint32_t e[9] = {l0.x, l0.y, l0.z, l0.w, l1.x, l1.y, l1.z, l1.w, l2.x};
+    link_coef16<true>(e, b < (R)0, cr, ci);
+  } else {
+    load_link<S>(gauge, vp, nu, par, s, up);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) up[k] = b * up[k];
+  }
   const void* s_here = par ? s_o : s_e;
   const void* s_other = par ? s_e : s_o;
   const void* x_here = par ? xi_o : xi_e;
@@ -190,14 +213,18 @@ __global__ __launch_bounds__(256) void k_contract_deriv(const SlotDesc* slots, i
     const long long off = sd.fo + (long long)r * vp;
     cx<R> sv[12], t[12];
     load_spinor<S>(field_at<S>(s_here, off), vp, s, sv);
-    transport_fwd<S>(field_at<S>(s_other, off), vp, sp, b, up, t);   // t = T_s
-    // s-s block: F_ab = 1/4 sum_c [conj(s_a) T_b - conj(T_a) s_b]
+    transport_fwd<S>(field_at<S>(s_other, off), vp, sp, up, cr, ci, t);   // t = T_s
+    // s-s block: F_ab = 1/4 sum_c [conj(s_a) T_b - conj(T_a) s_b]; the sums
+    // below omit the constant factors, applied at the flush
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       R im = 0;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) im += sv[3 * i + k].re * t[3 * i + k].im - sv[3 * i + k].im * t[3 * i + k].re;
-      a[i] += (A)((R)0.5 * im);                  // F_aa = (i/2) Im sum_c conj(s_a) T_a
+      for (int k = 0; k < 3; ++k) {
+        im = fmadd(sv[3 * i + k].re, t[3 * i + k].im, im);
+        im = fmadd(-sv[3 * i + k].im, t[3 * i + k].re, im);
+      }
+      a[i] += (A)im;                             // F_aa = (i/2) Im sum_c conj(s_a) T_a
     }
 #pragma unroll
     for (int k6 = 0; k6 < 6; ++k6) {
@@ -207,8 +234,8 @@ __global__ __launch_bounds__(256) void k_contract_deriv(const SlotDesc* slots, i
         cjmac(t1, sv[3 * up_a(k6) + k], t[3 * up_b(k6) + k]);
         cjmac(t2, t[3 * up_a(k6) + k], sv[3 * up_b(k6) + k]);
       }
-      a[4 + 2 * k6] += (A)((R)0.25 * (t1.re - t2.re));
-      a[5 + 2 * k6] += (A)((R)0.25 * (t1.im - t2.im));
+      a[4 + 2 * k6] += (A)(t1.re - t2.re);
+      a[5 + 2 * k6] += (A)(t1.im - t2.im);
     }
     // xi-s block, first half: 1/4 conj(xi_a) T_s,b
     {
@@ -221,12 +248,12 @@ __global__ __launch_bounds__(256) void k_contract_deriv(const SlotDesc* slots, i
           cx<R> w = mk<R>(0, 0);
 #pragma unroll
           for (int k = 0; k < 3; ++k) cjmac(w, xv[3 * i + k], t[3 * j + k]);
-          a[16 + 2 * (4 * i + j)] += (A)((R)0.25 * w.re);
-          a[17 + 2 * (4 * i + j)] += (A)((R)0.25 * w.im);
+          a[16 + 2 * (4 * i + j)] += (A)w.re;
+          a[17 + 2 * (4 * i + j)] += (A)w.im;
         }
     }
     // second half: -1/4 conj(T_xi,a) s_b
-    transport_fwd<S>(field_at<S>(x_other, off), vp, sp, b, up, t);   // t = T_xi
+    transport_fwd<S>(field_at<S>(x_other, off), vp, sp, up, cr, ci, t);   // t = T_xi
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -234,15 +261,15 @@ __global__ __launch_bounds__(256) void k_contract_deriv(const SlotDesc* slots, i
         cx<R> w = mk<R>(0, 0);
 #pragma unroll
         for (int k = 0; k < 3; ++k) cjmac(w, t[3 * i + k], sv[3 * j + k]);
-        a[16 + 2 * (4 * i + j)] -= (A)((R)0.25 * w.re);
-        a[17 + 2 * (4 * i + j)] -= (A)((R)0.25 * w.im);
+        a[16 + 2 * (4 * i + j)] -= (A)w.re;
+        a[17 + 2 * (4 * i + j)] -= (A)w.im;
       }
     if (++inblk == AccT<S>::KB) {
-      flush(acc, V, lane_off, a);
+      flush<true>(acc, V, lane_off, a);
       inblk = 0;
     }
   }
-  if (inblk) flush(acc, V, lane_off, a);
+  if (inblk) flush<true>(acc, V, lane_off, a);
 }
 
 #define DISPATCH_PREC(prec, KERNEL, ...)                                                     \

@@ -22,7 +22,8 @@
 //
 // Epilogue (per-spin complex factors, set per slot):
 //   res = e (.) H(d (.) in) + f (.) y,   out = g (.) res
-// optionally followed by the CG update x += alpha p, r -= alpha res.
+// optionally followed by the CG residual update r -= alpha res (x takes its
+// step alpha p in update_p).
 #include <stdexcept>
 
 #include "kernels.h"
@@ -118,31 +119,6 @@ __device__ inline void reconstruct(cx<R> (&acc)[12], const cx<R> (&w0)[3], const
   }
 }
 
-// 16-bit storage: FP32 dot product of two packed (re, im) pairs, c + a.lo b.lo
-// + a.hi b.hi.  The products of 16-bit values are exact in FP32, so this is
-// FP32 arithmetic on the stored values without unpacking them.
-template <class S> __device__ inline float dot2(uint32_t a, uint32_t b, float c);
-template <> __device__ inline float dot2<bf16s>(uint32_t a, uint32_t b, float c) {
-  return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a), __builtin_bit_cast(bf16x2_t, b), c, false);
-}
-template <> __device__ inline float dot2<f16s>(uint32_t a, uint32_t b, float c) {
-  return __builtin_amdgcn_fdot2(__builtin_bit_cast(f16x2_t, a), __builtin_bit_cast(f16x2_t, b), c, false);
-}
-// First product of a chain: the three-operand form with an inline zero
-// accumulator (the two-operand form accumulates into its destination and
-// would need the register cleared first).
-template <class S> __device__ inline float dot2_first(uint32_t a, uint32_t b);
-template <> __device__ inline float dot2_first<bf16s>(uint32_t a, uint32_t b) {
-  float r;
-  asm("v_dot2_f32_bf16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
-  return r;
-}
-template <> __device__ inline float dot2_first<f16s>(uint32_t a, uint32_t b) {
-  float r;
-  asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
-  return r;
-}
-__device__ inline uint32_t swap16(uint32_t w) { return (w >> 16) | (w << 16); }
 
 // One hop (direction MU, forward or backward) for every right-hand side of
 // the group: the link is loaded once.
@@ -165,20 +141,7 @@ __device__ inline void hop(const void* gauge, long vp, int link_par, int link_si
     const uint4 l0 = lp[0], l1 = lp[1], l2 = lp[2];
     const uint32_t e[9] = {l0.x, l0.y, l0.z, l0.w, l1.x, l1.y, l1.z, l1.w, l2.x};
     uint32_t cr[9], ci[9];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        if (FWD) {
-          const uint32_t w = e[3 * a + b];
-          cr[3 * a + b] = w ^ 0x80000000u;
-          ci[3 * a + b] = swap16(w);
-        } else {
-          const uint32_t w = e[3 * b + a];
-          cr[3 * a + b] = w;
-          ci[3 * a + b] = swap16(w) ^ 0x00008000u;
-        }
-      }
+    link_coef16<FWD>(e, false, cr, ci);
 #pragma unroll
     for (int i = 0; i < G; ++i) {
       if (i >= nr || !act[i]) continue;
@@ -186,18 +149,7 @@ __device__ inline void hop(const void* gauge, long vp, int link_par, int link_si
       const uint4 q0 = q[nb], q1 = q[vp + nb], q2 = q[2 * vp + nb];
       const uint32_t v[12] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w};
       cx<float> chi[12];
-#pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          float re = dot2_first<S>(cr[3 * a], v[3 * s4]);
-          re = dot2<S>(cr[3 * a + 1], v[3 * s4 + 1], re);
-          re = dot2<S>(cr[3 * a + 2], v[3 * s4 + 2], re);
-          float im = dot2_first<S>(ci[3 * a], v[3 * s4]);
-          im = dot2<S>(ci[3 * a + 1], v[3 * s4 + 1], im);
-          im = dot2<S>(ci[3 * a + 2], v[3 * s4 + 2], im);
-          chi[3 * s4 + a] = mk<float>(re, im);
-        }
+      colour_mul16<S>(cr, ci, v, chi);
       cx<float> w0[3], w1[3];
       project<MU, FWD>(chi, w0, w1);
       reconstruct<MU, FWD, INIT>(acc[i], w0, w1, sign);
@@ -324,16 +276,10 @@ __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
       }
       if (F & F_XR) {
         const R al = (R)a.alpha[sd.rhs_begin + r0 + i];
-        cx<R> xv[12], rv[12], pv[12];
-        load_spinor<S>(field_at<S>(a.x, off[i]), vp, s, xv);
+        cx<R> rv[12];
         load_spinor<S>(field_at<S>(a.r, off[i]), vp, s, rv);
-        load_spinor<S>(field_at<S>(a.p, off[i]), vp, s, pv);
 #pragma unroll
-        for (int k = 0; k < 12; ++k) {
-          xv[k] = xv[k] + al * pv[k];
-          rv[k] = rv[k] - al * res[k];
-        }
-        store_spinor<S>(field_at<S>(a.x, off[i]), vp, s, xv);
+        for (int k = 0; k < 12; ++k) rv[k] = rv[k] - al * res[k];
         quantize<S>(rv);                       // the norm is that of the stored residual
         store_spinor<S>(field_at<S>(a.r, off[i]), vp, s, rv);
         if (F & F_NORM) nrm[i] = norm2(rv);

@@ -10,7 +10,7 @@ enum DslashFlags : int {
   F_D = 1,      // multiply the input by the per-spin factor d on load
   F_Y = 2,      // add f (.) y
   F_NORM = 4,   // per-unit partial of ||result||^2 (or ||r||^2 with F_XR)
-  F_XR = 8,     // CG update: x += alpha p, r -= alpha result (result not stored)
+  F_XR = 8,     // CG update r -= alpha result (result not stored; x moves in update_p)
   F_OUT2 = 16,  // also store the result to a second field
   F_POST = 32,  // store g (.) result (the norm is taken before the factor)
 };
@@ -49,14 +49,17 @@ struct CgScalars {
   int* iters;
   int* maxiter;
   int* status;
+  int* upd;        // 1: x += alpha p of this iteration still to be applied
 };
 
 void launch_finalize(int kind, const SlotDesc* slots, int nslots, int nrhs_total,
                      const double* partial, const CgScalars& cs, hipStream_t st);
 
-// p = r + beta p for active right-hand sides
+// x += alpha p where upd is set (every rhs that took this iteration's step),
+// then p = r + beta p for the right-hand sides still active
 void launch_update_p(int prec, const SlotDesc* slots, int nslots, int total_units, void* p,
-                     const void* r, const double* beta, const int* active, hipStream_t st);
+                     const void* r, void* x, const double* alpha, const double* beta, const int* active,
+                     const int* upd, hipStream_t st);
 
 // set a batch field to zero on parity-free half fields
 void launch_zero(int prec, const SlotDesc* slots, int nslots, int total_units, void* f,

@@ -269,14 +269,15 @@ struct Batch {
     HIPCHECK(hipMemcpyAsync(dcoef.p, coefs.data(), sizeof(Coef) * coefs.size(), hipMemcpyHostToDevice, ctx->st));
     partial = DevBuf(ctx, sizeof(double) * std::max(u_rhs, 1));
     partial2 = DevBuf(ctx, sizeof(double) * std::max(u_rhs, 1));
-    // scalars: 6 double arrays + 4 int arrays
-    const size_t nd = 6 * (size_t)nrhs, ni = 4 * (size_t)nrhs;
+    // scalars: 6 double arrays + 5 int arrays
+    const size_t nd = 6 * (size_t)nrhs, ni = 5 * (size_t)nrhs;
     scal = DevBuf(ctx, sizeof(double) * nd + sizeof(int) * ni + 16);
     double* db = scal.as<double>();
     cs.rr = db; cs.cc = db + nrhs; cs.alpha = db + 2 * nrhs; cs.beta = db + 3 * nrhs;
     cs.tol2 = db + 4 * nrhs; cs.out = db + 5 * nrhs;
     int* ib = (int*)(db + nd);
     cs.active = ib; cs.iters = ib + nrhs; cs.maxiter = ib + 2 * nrhs; cs.status = ib + 3 * nrhs;
+    cs.upd = ib + 4 * nrhs;
     HIPCHECK(hipHostMalloc((void**)&h_int, sizeof(int) * 4 * std::max(nrhs, 1), hipHostMallocDefault));
     HIPCHECK(hipHostMalloc((void**)&h_dbl, sizeof(double) * 6 * std::max(nrhs, 1), hipHostMallocDefault));
   }
@@ -341,9 +342,10 @@ static void cg_iteration(Batch& b, int P, const CgFields& f, hipEvent_t t0 = nul
   b.dslash(P, F_Y | F_NORM | F_POST, CK_MHAT2P, 1, f.u, f.t, f.p, act);   // t' = D t
   b.finalize(FK_ALPHA);
   b.dslash(P, 0, CK_MDAG1P, 0, f.t, f.u, nullptr, act);
-  b.dslash(P, F_Y | F_XR | F_NORM, CK_MDAG2P, 1, f.u, nullptr, f.t, act, f.x, f.r, f.p);
+  b.dslash(P, F_Y | F_XR | F_NORM, CK_MDAG2P, 1, f.u, nullptr, f.t, act, nullptr, f.r);
   b.finalize(FK_BETA);
-  launch_update_p(P, b.slots(), b.nslots, b.u_rhs, f.p, f.r, b.cs.beta, act, b.ctx->st);
+  launch_update_p(P, b.slots(), b.nslots, b.u_rhs, f.p, f.r, f.x, b.cs.alpha, b.cs.beta, act, b.cs.upd,
+                  b.ctx->st);
 }
 
 // c = Mhat^dag bhat with bhat from eta; r = p = c, x = 0, scalars initialised.
