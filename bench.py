@@ -225,8 +225,10 @@ def main() -> int:
     dl.dl_gauge_set(lat, U_dev, 1)
     dl.dl_set_params(lat, kappa, mu)
     acc = dl.dl_accum_create(lat, dl.DL_OPS_LOCAL | dl.DL_OPS_DERIV)
-    blocks = {"bf16": a.rhs_block or dl.dl_autotune(ctx, lat, dl.DL_TIER_LP_BF16),
-              "fp32": a.rhs_block or dl.dl_autotune(ctx, lat, dl.DL_TIER_HP_FP32)}
+    blocks = {"bf16": list(dl.dl_autotune(ctx, lat, dl.DL_TIER_LP_BF16, n_lp)),
+              "fp32": list(dl.dl_autotune(ctx, lat, dl.DL_TIER_HP_FP32, n_hp))}
+    if a.rhs_block:
+        blocks = {k: [a.rhs_block, 4] for k in blocks}
     log(f"rhs blocks: {blocks}")
     nmom = len(dl.dl_momenta(dims, p2))
     out = torch.zeros((2, 5, 16, T, nmom), dtype=torch.complex128, device="cuda")

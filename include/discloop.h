@@ -218,17 +218,20 @@ int dl_set_option(dl_ctx* ctx, const char* name, double value);
  * spinor once per active right-hand side), out[3] total active rhs. */
 int dl_profile_read(dl_ctx* ctx, int tier, double out[4]);
 
-/* Right-hand-side block (sources per batch slot) that dl_solve_batch uses for
- * jobs of `tier` on `lat` when job->rhs_block is 0.  The first call per
- * (lattice shape, storage precision) runs the autotuner: it times the
- * hopping kernel on 128 scratch right-hand sides split into slots of
- * 1, 2, 4, ..., 128 and keeps the fastest (a larger block only when it is
- * more than 2% faster).  Results are cached in the context and in the JSON
- * file named by the environment variable DL_TUNE_CACHE (default
- * ~/.cache/discloop/tune-gfx950.json); an unwritable file only costs a
- * re-tune.  Synchronises the context stream.  Errors: DL_EINVAL (NULL
- * argument, unknown tier), DL_EHIP. */
-int dl_autotune(dl_ctx* ctx, dl_lattice* lat, int tier, int* block_out);
+/* Slot shape that dl_solve_batch uses for a job of `nsrc` sources of `tier`
+ * on `lat` when job->rhs_block is 0: *block_out right-hand sides per batch
+ * slot and, if tblk_out is not NULL, *tblk_out time slices per block of the
+ * hopping kernel's tile order.  The first call per (lattice shape, storage
+ * precision, size class = next power of two of nsrc in [16, 128]) runs the
+ * autotuner: it times the hopping kernel on size-class many scratch
+ * right-hand sides for blocks 1, 2, 4, ... and tile-order depths 1, 2, 4, 8
+ * and keeps the fastest (a later candidate only when more than 2% faster).
+ * Results are cached in the context and in the JSON file named by the
+ * environment variable DL_TUNE_CACHE (default ~/.cache/discloop/
+ * tune-gfx950.json); an unwritable file only costs a re-tune.  The choice
+ * never changes results, only speed.  Synchronises the context stream.
+ * Errors: DL_EINVAL (NULL argument, nsrc < 1, unknown tier), DL_EHIP. */
+int dl_autotune(dl_ctx* ctx, dl_lattice* lat, int tier, int nsrc, int* block_out, int* tblk_out);
 
 /* ---- single operators, for verification -------------------------------- */
 

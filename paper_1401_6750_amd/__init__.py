@@ -86,7 +86,7 @@ _SIGS = {
     "dl_loops_backward": ([_P, ctypes.POINTER(dl_job), _I, _P, _P, _P], _I),
     "dl_set_option": ([_P, ctypes.c_char_p, _D], _I),
     "dl_profile_read": ([_P, _I, ctypes.POINTER(_D)], _I),
-    "dl_autotune": ([_P, _P, _I, ctypes.POINTER(_I)], _I),
+    "dl_autotune": ([_P, _P, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_I)], _I),
     "dl_apply_op": ([_P, _I, _I, _P, _P, _I], _I),
     "dl_fill_noise": ([_P, _I, ctypes.c_uint64, ctypes.c_int64, _P], _I),
 }
@@ -234,11 +234,11 @@ def dl_profile_read(ctx, tier: int):
     return tuple(out)
 
 
-def dl_autotune(ctx, lat, tier: int) -> int:
-    """Right-hand-side block the solver uses for `tier` on `lat` (tunes on first use)."""
-    out = _I(0)
-    _check(lib().dl_autotune(ctx, lat, tier, ctypes.byref(out)))
-    return out.value
+def dl_autotune(ctx, lat, tier: int, nsrc: int = 128):
+    """(rhs block, tile-order time block) the solver uses for a job of nsrc sources (tunes on first use)."""
+    blk, tb = _I(0), _I(0)
+    _check(lib().dl_autotune(ctx, lat, tier, nsrc, ctypes.byref(blk), ctypes.byref(tb)))
+    return blk.value, tb.value
 
 
 def dl_apply_op(lat, op: int, tier: int, inp, out, nrhs: int) -> None:

@@ -421,14 +421,17 @@ int dl_profile_read(dl_ctx* ctx, int tier, double out[4]) {
   });
 }
 
-int dl_autotune(dl_ctx* ctx, dl_lattice* lat, int tier, int* block_out) {
+int dl_autotune(dl_ctx* ctx, dl_lattice* lat, int tier, int nsrc, int* block_out, int* tblk_out) {
   return guarded([&] {
     require(ctx && lat && block_out, "dl_autotune: NULL argument");
     require(lat->ctx == ctx, "dl_autotune: lattice belongs to another context");
+    require(nsrc >= 1, "dl_autotune: nsrc must be >= 1");
     const int P = tier_prec(tier);
     stream_enter(ctx);
-    *block_out = autotune_block(ctx, lat, P, 1 << 30);
+    const TuneChoice tc = autotune_block(ctx, lat, P, nsrc);
     stream_exit(ctx);
+    *block_out = tc.block;
+    if (tblk_out) *tblk_out = tc.tblk;
     return 0;
   });
 }

@@ -371,7 +371,7 @@ struct SlotDesc {
   int X, Y, Z, T;
   int Xh, Vh, ntile, nrhs;
   int Vp;                  // pad_half(Vh): row stride of fields, links, accumulators
-  int pad0;
+  int tblk;                // time slices per block of the hopping kernel's tile order
   int ubeg[4];             // first unit of this slot per UnitKind
   int rhs_begin;           // global index of this slot's rhs 0
   long long fo;            // site offset of rhs 0 in every batch field
@@ -408,22 +408,25 @@ __device__ inline int wave_unit() {
 }
 
 // Order in which the hopping kernel visits the tiles of a slot.  Tiles are
-// taken in blocks of TBLK time slices; inside a block the TBLK tiles at the
-// same place of successive slices are consecutive.  A tile's -t / +t
+// taken in blocks of tb = sd.tblk time slices; inside a block the tb tiles at
+// the same place of successive slices are consecutive.  A tile's -t / +t
 // neighbours are then a few tiles away instead of a whole time slice
 // (Xh*Y*Z/64 tiles), so they are still in L2 when read, while the z
-// neighbours move only TBLK times further.  The order needs whole tiles per
-// time slice; other lattices keep the lexicographic order.
-constexpr int TBLK = 4;
+// neighbours move only tb times further.  tb is tuned with the slot size;
+// tb <= 1, or a lattice without whole tiles per time slice, keeps the
+// lexicographic order.  The reductions index the physical tile, so the order
+// never changes results.
+constexpr int TBLK_DEFAULT = 4;
 __device__ inline int tile_of(const SlotDesc& sd, int lt) {
+  const int tb = sd.tblk;
   const int slice = sd.Xh * sd.Y * sd.Z;
-  if (slice % TILE != 0) return lt;
+  if (tb <= 1 || slice % TILE != 0) return lt;
   const int ts = slice / TILE;
-  const int b = lt / (TBLK * ts);
-  const int rem = lt - b * (TBLK * ts);
-  const int bt = min(TBLK, sd.T - b * TBLK);
+  const int b = lt / (tb * ts);
+  const int rem = lt - b * (tb * ts);
+  const int bt = min(tb, sd.T - b * tb);
   const int k = rem / bt;
-  return (b * TBLK + (rem - k * bt)) * ts + k;
+  return (b * tb + (rem - k * bt)) * ts + k;
 }
 
 __device__ inline int find_slot(const SlotDesc* slots, int nslots, int kind, int u) {

@@ -36,7 +36,7 @@ struct dl_ctx {
   hipStream_t st = nullptr;      // internal stream all work runs on
   hipEvent_t ev = nullptr;
   dl::Pool pool;
-  std::map<std::string, int> tune;   // autotuned rhs block per (dims, precision)
+  std::map<std::string, int> tune;   // autotuned rhs block / tile-order block per (dims, precision, size)
   std::string tune_path;
   bool tune_loaded = false;
   int last_tune_block = 0;
@@ -112,6 +112,7 @@ struct SlotPlan {
   const double* src_user;
   double* sol_user;
   double* acc;
+  int tblk;                // tile-order time block (0: default)
 };
 
 struct SolveReport {
@@ -129,7 +130,10 @@ void apply_op(dl_lattice* lat, int op, int tier, const double* in, double* out, 
 void set_gamma_table(const int col[16][4], const double ph[16][4][2]);
 void init_gamma_table();
 
-int autotune_block(dl_ctx* ctx, dl_lattice* lat, int prec, int nsrc_hint);
+// Slot shape of the hopping kernel: right-hand sides per slot and the
+// time-block depth of the tile order.
+struct TuneChoice { int block, tblk; };
+TuneChoice autotune_block(dl_ctx* ctx, dl_lattice* lat, int prec, int nsrc_hint);
 
 // Plan validated jobs into slots (autotuned block sizes) and memory-bounded
 // batches per precision class, run them, fill stats (job order) and the

@@ -226,6 +226,7 @@ struct Batch {
       d.Vh = (int)L->Vh;
       d.ntile = (d.Vh + TILE - 1) / TILE;
       d.Vp = (int)pad_half(d.Vh);
+      d.tblk = sp.tblk > 0 ? sp.tblk : TBLK_DEFAULT;
       d.nrhs = sp.nrhs;
       d.ubeg[UK_RHS] = ur; d.ubeg[UK_SITE] = us; d.ubeg[UK_DERIV] = ud; d.ubeg[UK_GRP] = ug;
       d.rhs_begin = rb;
@@ -829,15 +830,16 @@ void fill_noise_fields(dl_ctx* ctx, const std::vector<SlotPlan>& plan, const std
 }
 
 // ---------------------------------------------------------------------------
-// autotuner: right-hand sides interleaved per slot
+// autotuner: slot shape of the hopping kernel
 // ---------------------------------------------------------------------------
 // Within a slot the hopping kernel walks tile-major over its right-hand
 // sides, so one tile's links are fetched once for all of them; but the larger
-// the block, the longer a neighbour tile (+-t is Xh*Y*Z/64 tiles away) has to
-// survive in L2.  The best block size depends on lattice and precision and is
-// measured: the hopping launch is timed on a scratch batch for each candidate
-// and the fastest per right-hand side kept, in memory and in a JSON cache
-// (DL_TUNE_CACHE, default ~/.cache/discloop/tune-gfx950.json).
+// the block, the more data the neighbour tiles (z: ~4.5 tb tiles away, t:
+// next block) need L2 to hold.  The time-block depth tb of the tile order
+// trades t- against z-neighbour distance.  Both depend on lattice, precision
+// and batch size and are measured: the hopping launch is timed on a scratch
+// batch for every (block, tb) candidate and the fastest kept, in memory and in
+// a JSON cache (DL_TUNE_CACHE, default ~/.cache/discloop/tune-gfx950.json).
 static std::string tune_file() {
   const char* e = getenv("DL_TUNE_CACHE");
   if (e && *e) return e;
@@ -882,52 +884,66 @@ static void tune_save(dl_ctx* ctx) {
   fclose(f);
 }
 
-int autotune_block(dl_ctx* ctx, dl_lattice* lat, int prec, int nsrc_hint) {
-  if (nsrc_hint <= 1) return 1;
+TuneChoice autotune_block(dl_ctx* ctx, dl_lattice* lat, int prec, int nsrc_hint) {
+  if (nsrc_hint <= 1) return {1, TBLK_DEFAULT};
   tune_load(ctx);
+  // batch size class of the measurement: the next power of two of the job's
+  // sources, between 16 and 128
+  int total = 16;
+  while (total < nsrc_hint && total < 128) total *= 2;
   static const char* pname[4] = {"fp64", "fp32", "bf16", "fp16"};
-  char key[96];
-  snprintf(key, sizeof(key), "%dx%dx%dx%d:%s", lat->dims[0], lat->dims[1], lat->dims[2], lat->dims[3], pname[prec]);
+  char key[96], tkey[100];
+  snprintf(key, sizeof(key), "%dx%dx%dx%d:%s:%d", lat->dims[0], lat->dims[1], lat->dims[2], lat->dims[3],
+           pname[prec], total);
+  snprintf(tkey, sizeof(tkey), "%s:t", key);
   auto it = ctx->tune.find(key);
-  if (it == ctx->tune.end()) {
+  auto jt = ctx->tune.find(tkey);
+  if (it == ctx->tune.end() || jt == ctx->tune.end()) {
     const int cands[] = {1, 2, 4, 8, 16, 32, 64, 128};
-    const int total = 128;
+    const int tbs[] = {1, 2, 4, 8};
     double best_t = 1e300;
-    int best = 16;
+    int best = 16, best_tb = TBLK_DEFAULT;
     hipEvent_t e0, e1;
     HIPCHECK(hipEventCreate(&e0));
     HIPCHECK(hipEventCreate(&e1));
     for (int N : cands) {
-      std::vector<SlotPlan> plan;
-      for (int k = 0; k < total; k += N) {
-        SlotPlan sp{};
-        sp.lat = lat;
-        sp.nrhs = std::min(N, total - k);
-        plan.push_back(sp);
-      }
-      Batch b(ctx, prec, plan, nullptr);
-      DevBuf in = b.field(prec), out = b.field(prec);
-      HIPCHECK(hipMemsetAsync(in.p, 0, b.field_bytes(prec), ctx->st));
-      b.dslash(prec, 0, CK_MHAT1, 0, in.p, out.p, nullptr, nullptr);
-      HIPCHECK(hipEventRecord(e0, ctx->st));
-      for (int rep = 0; rep < 3; ++rep) b.dslash(prec, 0, CK_MHAT1, 0, in.p, out.p, nullptr, nullptr);
-      HIPCHECK(hipEventRecord(e1, ctx->st));
-      HIPCHECK(hipEventSynchronize(e1));
-      float ms = 0;
-      HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
-      if (ms < best_t * 0.98) {   // prefer the smaller block unless the larger one is clearly faster
-        best_t = ms;
-        best = N;
+      if (N > total) break;
+      for (int tb : tbs) {
+        std::vector<SlotPlan> plan;
+        for (int k = 0; k < total; k += N) {
+          SlotPlan sp{};
+          sp.lat = lat;
+          sp.nrhs = std::min(N, total - k);
+          sp.tblk = tb;
+          plan.push_back(sp);
+        }
+        Batch b(ctx, prec, plan, nullptr);
+        DevBuf in = b.field(prec), out = b.field(prec);
+        HIPCHECK(hipMemsetAsync(in.p, 0, b.field_bytes(prec), ctx->st));
+        b.dslash(prec, 0, CK_MHAT1, 0, in.p, out.p, nullptr, nullptr);
+        HIPCHECK(hipEventRecord(e0, ctx->st));
+        for (int rep = 0; rep < 3; ++rep) b.dslash(prec, 0, CK_MHAT1, 0, in.p, out.p, nullptr, nullptr);
+        HIPCHECK(hipEventRecord(e1, ctx->st));
+        HIPCHECK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_t * 0.98) {   // prefer the earlier candidate unless a later one is clearly faster
+          best_t = ms;
+          best = N;
+          best_tb = tb;
+        }
       }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     ctx->tune[key] = best;
+    ctx->tune[tkey] = best_tb;
     tune_save(ctx);
     it = ctx->tune.find(key);
+    jt = ctx->tune.find(tkey);
   }
   ctx->last_tune_block = it->second;
-  return std::max(1, std::min(nsrc_hint, it->second));
+  return {std::max(1, std::min(nsrc_hint, it->second)), jt->second};
 }
 
 bool solve_jobs(dl_ctx* ctx, const std::vector<dl_job>& J, dl_src_stats* stats) {
@@ -944,7 +960,9 @@ bool solve_jobs(dl_ctx* ctx, const std::vector<dl_job>& J, dl_src_stats* stats) 
     for (int j = 0; j < njobs; ++j) {
       const dl_job& q = J[j];
       if (q.tier != tier || q.nsrc == 0) continue;
-      const int N = q.rhs_block > 0 ? q.rhs_block : autotune_block(ctx, q.lat, P, q.nsrc);
+      const TuneChoice tc =
+          q.rhs_block > 0 ? TuneChoice{q.rhs_block, TBLK_DEFAULT} : autotune_block(ctx, q.lat, P, q.nsrc);
+      const int N = tc.block;
       const long long V = q.lat->V;
       for (int k = 0; k < q.nsrc; k += N) {
         SlotPlan sp{};
@@ -956,6 +974,7 @@ bool solve_jobs(dl_ctx* ctx, const std::vector<dl_job>& J, dl_src_stats* stats) 
         sp.src_user = q.src_in ? q.src_in + (size_t)k * V * 24 : nullptr;
         sp.sol_user = q.sol_out ? q.sol_out + (size_t)k * V * 24 : nullptr;
         sp.acc = q.accum ? q.accum->acc[q.accum_set] : nullptr;
+        sp.tblk = tc.tblk;
         all.push_back(sp);
       }
     }
