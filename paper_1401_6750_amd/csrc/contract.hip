@@ -36,8 +36,13 @@ namespace dl {
 
 int acc_components(int ops) { return (ops & 2) ? 240 : 48; }
 
-// register sums in the compute precision, KB sources per flush
-template <class S> struct AccT { using A = float; static constexpr int KB = 16; };
+// Register sums in the compute precision, KB sources per flush into FP64.
+// The flush is a read-modify-write of every component of the site (the
+// dominant HBM traffic of these kernels), so KB is as large as accuracy
+// allows: an FP32 sum of KB products carries < KB * 2^-24 relative rounding,
+// 4e-6 for KB = 64, far below the 2^-8 / 2^-11 storage rounding of 16-bit
+// fields; FP32 fields (the high-precision tier) keep KB = 16 (1e-6).
+template <class S> struct AccT { using A = float; static constexpr int KB = Traits<S>::NC == 3 ? 64 : 16; };
 template <> struct AccT<double> { using A = double; static constexpr int KB = 1 << 30; };
 
 // upper-triangle pair k = 0..5 -> (a, b): (0,1) (0,2) (0,3) (1,2) (1,3) (2,3)
