@@ -268,8 +268,8 @@ __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
       cx<R> res[12];
 #pragma unroll
       for (int k = 0; k < 12; ++k) res[k] = e[k / 3] * acc[i][k];
+      cx<R> yv[12];
       if (F & F_Y) {
-        cx<R> yv[12];
         load_spinor<S>(field_at<S>(a.y, off[i]), vp, s, yv);
 #pragma unroll
         for (int k = 0; k < 12; ++k) res[k] = res[k] + f[k / 3] * yv[k];
@@ -294,6 +294,13 @@ __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
         }
         store_spinor<S>(field_at<S>(a.out, off[i]), vp, s, res);
         if (F & F_OUT2) store_spinor<S>(field_at<S>(a.out2, off[i]), vp, s, res);
+        if (F & F_DUAL) {
+          // second epilogue on the same hop: g (.) H + f (.) y  (y is in yv)
+          cx<R> res2[12];
+#pragma unroll
+          for (int k = 0; k < 12; ++k) res2[k] = g[k / 3] * acc[i][k] + f[k / 3] * yv[k];
+          store_spinor<S>(field_at<S>(a.out2, off[i]), vp, s, res2);
+        }
       }
     }
   }
@@ -326,6 +333,7 @@ static void launch_dslash_t(int flags, const DslashArgs& a, hipStream_t st) {
     case F_Y | F_XR | F_NORM:
       hipLaunchKernelGGL((k_dslash<S, F_Y | F_XR | F_NORM>), grid, block, 0, st, a); break;
     case F_Y | F_POST: hipLaunchKernelGGL((k_dslash<S, F_Y | F_POST>), grid, block, 0, st, a); break;
+    case F_Y | F_DUAL: hipLaunchKernelGGL((k_dslash<S, F_Y | F_DUAL>), grid, block, 0, st, a); break;
     default: throw std::runtime_error("unsupported dslash flag combination");
   }
 }

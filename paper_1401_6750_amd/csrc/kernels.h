@@ -13,6 +13,7 @@ enum DslashFlags : int {
   F_XR = 8,     // CG update r -= alpha result (result not stored; x moves in update_p)
   F_OUT2 = 16,  // also store the result to a second field
   F_POST = 32,  // store g (.) result (the norm is taken before the factor)
+  F_DUAL = 64,  // with F_Y: also out2 = g (.) H(d (.) in) + f (.) y from the same hop
 };
 
 struct DslashArgs {

@@ -128,6 +128,7 @@ enum CoefKind : int {
   CK_PREP,        // bhat_o = A^-1(eta_o + kappa H_oe A^-1 eta_e)
   CK_RECON,       // s_e = A^-1(eta_e + kappa H_eo s_o)
   CK_XI,          // xi_p = s_p - kappa H s
+  CK_RECON_XI,    // s_e as CK_RECON and (g) xi_e = s_e - kappa H_eo s_o from one hop
   CK_MFULL,       // (M psi)_p = A psi_p - kappa H psi
   CK_MDAGFULL,    // (M^dag psi)_p = A(-mu) psi_p - kappa gamma5 H gamma5 psi
   CK_HOP,         // H psi
@@ -184,6 +185,7 @@ static Coef make_coef(int kind, double kappa, double mu) {
       case CK_PREP: d[s] = Ai[s]; e[s] = kappa * Ai[s]; f[s] = Ai[s]; break;
       case CK_RECON: e[s] = kappa * Ai[s]; f[s] = Ai[s]; break;
       case CK_XI: e[s] = -kappa; f[s] = 1.0; break;
+      case CK_RECON_XI: e[s] = kappa * Ai[s]; f[s] = Ai[s]; g[s] = kappa * Ai[s] - kappa; break;
       case CK_MFULL: e[s] = -kappa; f[s] = A[s]; break;
       case CK_MDAGFULL: d[s] = G5[s]; e[s] = -kappa * G5[s]; f[s] = Am[s]; break;
       case CK_HOP: break;
@@ -684,18 +686,23 @@ void run_batch(dl_ctx* ctx, int tier, const std::vector<SlotPlan>& plan, const s
 
   // ---- solution, xi fields, contractions ---------------------------------
   // fields: s_o = x, s_e = r, xi_e = p, xi_o = t
-  if (tier == DL_TIER_HP_FP32) {
-    launch_convert(P64, P32, b.slots(), b.nslots, b.u_rhs, s64_e.p, r.p, 0, nullptr, st);
-  } else {
-    b.dslash(P, F_Y, CK_RECON, 0, x.p, r.p, eta_e.p, nullptr);
-  }
   bool any_acc = false, any_sol = false;
   for (const SlotPlan& sp : plan) {
     any_acc = any_acc || sp.acc;
     any_sol = any_sol || sp.sol_user;
   }
+  bool xi_e_done = false;
+  if (tier == DL_TIER_HP_FP32) {
+    launch_convert(P64, P32, b.slots(), b.nslots, b.u_rhs, s64_e.p, r.p, 0, nullptr, st);
+  } else if (any_acc && PC == P) {
+    // s_e and xi_e = s_e - kappa H_eo s_o share the hop H_eo s_o
+    b.dslash(P, F_Y | F_DUAL, CK_RECON_XI, 0, x.p, r.p, eta_e.p, nullptr, nullptr, nullptr, nullptr, p.p);
+    xi_e_done = true;
+  } else {
+    b.dslash(P, F_Y, CK_RECON, 0, x.p, r.p, eta_e.p, nullptr);
+  }
   if (any_acc) {
-    b.dslash(PC, F_Y, CK_XI, 0, x.p, p.p, r.p, nullptr);
+    if (!xi_e_done) b.dslash(PC, F_Y, CK_XI, 0, x.p, p.p, r.p, nullptr);
     b.dslash(PC, F_Y, CK_XI, 1, r.p, t.p, x.p, nullptr);
     contract_passes(b, PC, r.p, x.p, p.p, t.p);
   }
