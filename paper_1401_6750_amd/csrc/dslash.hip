@@ -120,6 +120,55 @@ __device__ inline void reconstruct(cx<R> (&acc)[12], const cx<R> (&w0)[3], const
 }
 
 
+// Spin projection of one hop as (h0, h1) = (psi_0 + c0 psi_B0, psi_1 + c1 psi_B1),
+// c in {+1, -1, +i, -i} coded 0..3 (the same combinations as project()).
+template <int MU, bool FWD> struct ProjSpec;
+template <> struct ProjSpec<0, true> { static constexpr int b0 = 3, c0 = 2, b1 = 2, c1 = 2; };
+template <> struct ProjSpec<0, false> { static constexpr int b0 = 3, c0 = 3, b1 = 2, c1 = 3; };
+template <> struct ProjSpec<1, true> { static constexpr int b0 = 3, c0 = 0, b1 = 2, c1 = 1; };
+template <> struct ProjSpec<1, false> { static constexpr int b0 = 3, c0 = 1, b1 = 2, c1 = 0; };
+template <> struct ProjSpec<2, true> { static constexpr int b0 = 2, c0 = 2, b1 = 3, c1 = 3; };
+template <> struct ProjSpec<2, false> { static constexpr int b0 = 2, c0 = 3, b1 = 3, c1 = 2; };
+template <> struct ProjSpec<3, true> { static constexpr int b0 = 2, c0 = 1, b1 = 3, c1 = 1; };
+template <> struct ProjSpec<3, false> { static constexpr int b0 = 2, c0 = 0, b1 = 3, c1 = 0; };
+
+// Packed path: w = M h with the projection folded into the dot2 chains.  For
+// the term c psi_B: Re(M c psi) and Im(M c psi) are dot2 products of psi_B
+// with (cr, ci) for c = +1, (-cr, -ci) for -1, (-ci, cr) for +i and (ci, -cr)
+// for -i; -x of a packed pair flips both sign bits.
+template <class S, int C>
+__device__ inline void proj_coef(const uint32_t (&cr)[9], const uint32_t (&ci)[9], uint32_t (&pr)[9],
+                                 uint32_t (&pi)[9]) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const uint32_t ncr = cr[k] ^ 0x80008000u, nci = ci[k] ^ 0x80008000u;
+    pr[k] = C == 0 ? cr[k] : (C == 1 ? ncr : (C == 2 ? nci : ci[k]));
+    pi[k] = C == 0 ? ci[k] : (C == 1 ? nci : (C == 2 ? cr[k] : ncr));
+  }
+}
+
+template <class S>
+__device__ inline void proj_mul16(const uint32_t (&cr)[9], const uint32_t (&ci)[9], const uint32_t (&pr)[9],
+                                  const uint32_t (&pi)[9], const uint32_t (&v)[12], int sa, int sb,
+                                  cx<float> (&w)[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float re = dot2_first<S>(cr[3 * a], v[3 * sa]);
+    re = dot2<S>(cr[3 * a + 1], v[3 * sa + 1], re);
+    re = dot2<S>(cr[3 * a + 2], v[3 * sa + 2], re);
+    re = dot2<S>(pr[3 * a], v[3 * sb], re);
+    re = dot2<S>(pr[3 * a + 1], v[3 * sb + 1], re);
+    re = dot2<S>(pr[3 * a + 2], v[3 * sb + 2], re);
+    float im = dot2_first<S>(ci[3 * a], v[3 * sa]);
+    im = dot2<S>(ci[3 * a + 1], v[3 * sa + 1], im);
+    im = dot2<S>(ci[3 * a + 2], v[3 * sa + 2], im);
+    im = dot2<S>(pi[3 * a], v[3 * sb], im);
+    im = dot2<S>(pi[3 * a + 1], v[3 * sb + 1], im);
+    im = dot2<S>(pi[3 * a + 2], v[3 * sb + 2], im);
+    w[a] = mk<float>(re, im);
+  }
+}
+
 // One hop (direction MU, forward or backward) for every right-hand side of
 // the group: the link is loaded once.
 //
@@ -142,16 +191,19 @@ __device__ inline void hop(const void* gauge, long vp, int link_par, int link_si
     const uint32_t e[9] = {l0.x, l0.y, l0.z, l0.w, l1.x, l1.y, l1.z, l1.w, l2.x};
     uint32_t cr[9], ci[9];
     link_coef16<FWD>(e, false, cr, ci);
+    using PS = ProjSpec<MU, FWD>;
+    uint32_t pr0[9], pi0[9], pr1[9], pi1[9];
+    proj_coef<S, PS::c0>(cr, ci, pr0, pi0);
+    proj_coef<S, PS::c1>(cr, ci, pr1, pi1);
 #pragma unroll
     for (int i = 0; i < G; ++i) {
       if (i >= nr || !act[i]) continue;
       const uint4* q = (const uint4*)inb[i];
       const uint4 q0 = q[nb], q1 = q[vp + nb], q2 = q[2 * vp + nb];
       const uint32_t v[12] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w};
-      cx<float> chi[12];
-      colour_mul16<S>(cr, ci, v, chi);
       cx<float> w0[3], w1[3];
-      project<MU, FWD>(chi, w0, w1);
+      proj_mul16<S>(cr, ci, pr0, pi0, v, 0, PS::b0, w0);
+      proj_mul16<S>(cr, ci, pr1, pi1, v, 1, PS::b1, w1);
       reconstruct<MU, FWD, INIT>(acc[i], w0, w1, sign);
     }
   } else {
