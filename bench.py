@@ -238,8 +238,10 @@ def main() -> int:
         return [
             dl.make_job(lat, noise=noise_kind, tier=dl.DL_TIER_LP_BF16, seed=seed, first_src=0, nsrc=n_lp,
                         tol=1e-2, maxiter=500, rhs_block=a.rhs_block, accum=acc, accum_set=dl.DL_SET_LP),
+            # HP correction solves start from the LPC solutions of the same sources (job 2)
             dl.make_job(lat, noise=noise_kind, tier=dl.DL_TIER_HP_FP32, seed=seed, first_src=n_lp, nsrc=n_hp,
-                        tol=1e-8, maxiter=2000, rhs_block=a.rhs_block, accum=acc, accum_set=dl.DL_SET_HP),
+                        tol=1e-8, maxiter=2000, rhs_block=a.rhs_block, accum=acc, accum_set=dl.DL_SET_HP,
+                        guess_from=3),
             dl.make_job(lat, noise=noise_kind, tier=dl.DL_TIER_LP_BF16, seed=seed, first_src=n_lp, nsrc=n_hp,
                         tol=1e-2, maxiter=500, rhs_block=a.rhs_block, accum=acc, accum_set=dl.DL_SET_LPC),
         ]

@@ -113,6 +113,13 @@ typedef struct dl_job {
   double* sol_out;       /* optional device complex128 [nsrc][V][12]: s_r */
   dl_accum* accum;       /* optional: add the loops of every source here */
   int accum_set;         /* DL_SET_* */
+  int guess_from;        /* 0: CG starts from zero.  j + 1 (HP tier only): start
+                            from the solutions of job j of the same call, which
+                            must be a lower tier (FP64, LP_BF16 or LP_FP16) over
+                            the same lattice and sources (noise, seed,
+                            first_src, nsrc, src_in).  The final accuracy is
+                            unchanged; the truncated-solver correction solves
+                            then start at the low-precision residual. */
 } dl_job;
 
 typedef struct dl_src_stats {

@@ -48,6 +48,7 @@ class dl_job(ctypes.Structure):
         ("sol_out", ctypes.c_void_p),
         ("accum", ctypes.c_void_p),
         ("accum_set", ctypes.c_int),
+        ("guess_from", ctypes.c_int),
     ]
 
 
@@ -196,9 +197,10 @@ def dl_momenta(dims, p2max: int):
 
 def make_job(lat, *, noise=DL_NOISE_Z2, tier=DL_TIER_FP64, seed=0, first_src=0, nsrc=1, maxiter=1000,
              tol=1e-10, rhs_block=0, report_true_resid=0, src_in=None, sol_out=None, accum=None,
-             accum_set=DL_SET_HP) -> dl_job:
+             accum_set=DL_SET_HP, guess_from=0) -> dl_job:
+    """One job; guess_from = j + 1 starts an HP job from the solutions of job j of the same call."""
     return dl_job(lat, noise, tier, seed, first_src, nsrc, maxiter, tol, rhs_block, report_true_resid,
-                  _ptr(src_in), _ptr(sol_out), accum, accum_set)
+                  _ptr(src_in), _ptr(sol_out), accum, accum_set, guess_from)
 
 
 def dl_solve_batch(ctx, jobs):

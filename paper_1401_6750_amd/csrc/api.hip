@@ -280,6 +280,18 @@ int dl_solve_batch(dl_ctx* ctx, const dl_job* jobs, int njobs, dl_src_stats* sta
       }
       first_stat[j + 1] = first_stat[j] + q.nsrc;
     }
+    for (int j = 0; j < njobs; ++j) {
+      const dl_job& q = J[j];
+      if (q.guess_from == 0) continue;
+      const int g = q.guess_from - 1;
+      require(g >= 0 && g < njobs && g != j, "dl_solve_batch: guess_from out of range");
+      const dl_job& h = J[g];
+      require(q.tier == DL_TIER_HP_FP32, "dl_solve_batch: guess_from is for HP jobs");
+      require(h.tier != DL_TIER_HP_FP32, "dl_solve_batch: guess_from must name a lower-tier job");
+      require(h.lat == q.lat && h.noise == q.noise && h.seed == q.seed && h.first_src == q.first_src &&
+                  h.nsrc == q.nsrc && h.src_in == q.src_in,
+              "dl_solve_batch: guess_from job must solve the same sources on the same lattice");
+    }
     stream_enter(ctx);
     const bool all_ok = solve_jobs(ctx, J, stats);
     HIPCHECK(hipGetLastError());

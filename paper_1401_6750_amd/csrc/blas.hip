@@ -200,7 +200,10 @@ __global__ __launch_bounds__(256) void k_sources(const SlotDesc* slots, int nslo
   const long long lex = c.x + (long long)sd.X * (c.y + (long long)sd.Y * (c.z + (long long)sd.Z * c.t));
   const long long V = 2ll * sd.Vh;
   cx<R> v[12];
-  if (sd.noise == 2) {                 // caller sources, complex128 [rhs][V][12]
+  if (sd.noise == 2 && !sd.src_user) {  // no caller field for this slot: zeros
+#pragma unroll
+    for (int k = 0; k < 12; ++k) v[k] = mk<R>(0, 0);
+  } else if (sd.noise == 2) {          // caller sources, complex128 [rhs][V][12]
     const double2* src = (const double2*)sd.src_user + ((long long)w.r * V + lex) * 12;
 #pragma unroll
     for (int k = 0; k < 12; ++k) {

@@ -299,11 +299,9 @@ __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
     const void* inb[G];
 #pragma unroll
     for (int i = 0; i < G; ++i) inb[i] = field_at<S>(a.in, off[i]);
+    // set by the first hop of every active member; an inactive member skips
+    // every hop and its accumulator is never read
     cx<R> acc[G][12];
-#pragma unroll
-    for (int i = 0; i < G; ++i)
-#pragma unroll
-      for (int k = 0; k < 12; ++k) acc[i][k] = mk<R>(0, 0);   // inactive groups keep zeros
     constexpr bool HD = (F & F_D) != 0;
     const int q = 1 - p_out;
     hop<S, 0, true, HD, true>(gauge, vp, p_out, s, nxp, (R)1, inb, nr, act, d, acc);

@@ -113,6 +113,7 @@ struct SlotPlan {
   double* sol_user;
   double* acc;
   int tblk;                // tile-order time block (0: default)
+  const double* x0_user;   // initial guess of rhs 0 (complex128 [V][12] per rhs), or null
 };
 
 struct SolveReport {

@@ -601,6 +601,51 @@ void run_batch(dl_ctx* ctx, int tier, const std::vector<SlotPlan>& plan, const s
         }
     }
     const double delta2 = 1e-5;   // reliable update when ||r|| fell by ~300x since the last one
+    // FP64 reliable update of the flagged right-hand sides: fold the FP32
+    // correction into the FP64 solution, recompute the normal-equation
+    // residual c - Mhat^dag Mhat xhi in FP64 and restart the FP32 residual
+    // from it; leaves <r, r> of the flagged ones in cs.rr
+    auto reliable_update = [&](const int* fl) {
+      launch_convert(P32, P64, b.slots(), b.nslots, b.u_rhs, x.p, xhi.p, 1, fl, st);
+      launch_zero(P32, b.slots(), b.nslots, b.u_rhs, x.p, fl, st);
+      b.dslash(P64, 0, CK_MHAT1, 0, xhi.p, u64.p, nullptr, fl);
+      b.dslash(P64, F_Y, CK_MHAT2, 1, u64.p, t64.p, xhi.p, fl);
+      b.dslash(P64, F_D, CK_MDAG1, 0, t64.p, u64.p, nullptr, fl);
+      b.dslash(P64, F_Y, CK_MDAG2, 1, u64.p, ap64.p, t64.p, fl);
+      launch_residual_replace(b.slots(), b.nslots, b.u_rhs, c64.p, ap64.p, u64.p, r.p, b.partial.as<double>(), fl,
+                              st);
+      b.finalize_store(b.cs.rr, fl, b.partial.as<double>());
+    };
+    bool any_x0 = false;
+    for (const SlotPlan& sp : plan) any_x0 = any_x0 || sp.x0_user;
+    if (any_x0) {
+      // initial guesses (odd sites) into the FP64 solution, then one reliable
+      // update gives the starting residual, and p = r
+      std::vector<SlotDesc> g0 = b.hs;
+      for (size_t i = 0; i < g0.size(); ++i) {
+        g0[i].noise = DL_NOISE_USER;
+        g0[i].src_user = plan[i].x0_user;
+      }
+      DevBuf dg0(ctx, sizeof(SlotDesc) * g0.size());
+      HIPCHECK(hipMemcpyAsync(dg0.p, g0.data(), sizeof(SlotDesc) * g0.size(), hipMemcpyHostToDevice, st));
+      launch_sources(P64, dg0.as<SlotDesc>(), b.nslots, b.u_rhs, 1, xhi.p, st);
+      std::vector<int> ones(b.nrhs, 1);
+      HIPCHECK(hipMemcpyAsync(flag.p, ones.data(), sizeof(int) * b.nrhs, hipMemcpyHostToDevice, st));
+      reliable_update(flag.as<int>());
+      launch_convert(P32, P32, b.slots(), b.nslots, b.u_rhs, r.p, p.p, 0, nullptr, st);
+      b.to_host_dbl(b.cs.rr, b.h_dbl);
+      b.sync();
+      const int zero = 0;
+      for (int g = 0; g < b.nrhs; ++g) {
+        rr_ru[g] = b.h_dbl[g];
+        if (cc[g] > 0 && b.h_dbl[g] <= tolv[g] * tolv[g] * cc[g]) {   // the guess already converged
+          verified[g] = 1;
+          HIPCHECK(hipMemcpyAsync(b.cs.active + g, &zero, sizeof(int), hipMemcpyHostToDevice, st));
+          HIPCHECK(hipMemcpyAsync(b.cs.status + g, &zero, sizeof(int), hipMemcpyHostToDevice, st));
+        }
+      }
+      b.sync();
+    }
     int guard = 0;
     while (true) {
       // state after the previous step
@@ -617,7 +662,9 @@ void run_batch(dl_ctx* ctx, int tier, const std::vector<SlotPlan>& plan, const s
         hflag[g] = 0;
         if (act[g]) {
           any_active = true;
-          if (b.h_dbl[g] < delta2 * rr_ru[g]) hflag[g] = 1;
+          // no update within 100x (in |r|^2) of the target: the convergence
+          // check's own FP64 residual follows shortly
+          if (b.h_dbl[g] < delta2 * rr_ru[g] && b.h_dbl[g] > 1e2 * tolv[g] * tolv[g] * cc[g]) hflag[g] = 1;
         } else if (status[g] == 0 && !verified[g] && cc[g] > 0) {
           hflag[g] = 2;   // iterated residual converged: verify with the true residual
         }
@@ -629,16 +676,7 @@ void run_batch(dl_ctx* ctx, int tier, const std::vector<SlotPlan>& plan, const s
         std::vector<int> f01(b.nrhs);
         for (int g = 0; g < b.nrhs; ++g) f01[g] = hflag[g] != 0;
         HIPCHECK(hipMemcpyAsync(flag.p, f01.data(), sizeof(int) * b.nrhs, hipMemcpyHostToDevice, st));
-        const int* fl = flag.as<int>();
-        launch_convert(P32, P64, b.slots(), b.nslots, b.u_rhs, x.p, xhi.p, 1, fl, st);
-        launch_zero(P32, b.slots(), b.nslots, b.u_rhs, x.p, fl, st);
-        b.dslash(P64, 0, CK_MHAT1, 0, xhi.p, u64.p, nullptr, fl);
-        b.dslash(P64, F_Y, CK_MHAT2, 1, u64.p, t64.p, xhi.p, fl);
-        b.dslash(P64, F_D, CK_MDAG1, 0, t64.p, u64.p, nullptr, fl);
-        b.dslash(P64, F_Y, CK_MDAG2, 1, u64.p, ap64.p, t64.p, fl);
-        launch_residual_replace(b.slots(), b.nslots, b.u_rhs, c64.p, ap64.p, u64.p, r.p, b.partial.as<double>(),
-                                fl, st);
-        b.finalize_store(b.cs.rr, fl, b.partial.as<double>());
+        reliable_update(flag.as<int>());
         b.to_host_dbl(b.cs.rr, b.h_dbl);
         b.sync();
         std::vector<int> react;
@@ -959,6 +997,17 @@ bool solve_jobs(dl_ctx* ctx, const std::vector<dl_job>& J, dl_src_stats* stats) 
   for (int j = 0; j < njobs; ++j) first_stat[j + 1] = first_stat[j] + J[j].nsrc;
   bool all_ok = true;
   const double budget = ctx->inflight_mb * 1048576.0;
+  // solutions that HP jobs start from: the caller's sol_out, or a library
+  // buffer kept for this call (the lower tiers run first)
+  std::vector<double*> sol_ptr(njobs, nullptr);
+  std::vector<DevBuf> keep;
+  for (int j = 0; j < njobs; ++j) sol_ptr[j] = J[j].sol_out;
+  for (int j = 0; j < njobs; ++j) {
+    const int g = J[j].guess_from - 1;
+    if (g < 0 || sol_ptr[g] || J[g].nsrc == 0) continue;
+    keep.emplace_back(ctx, (size_t)J[g].nsrc * J[g].lat->V * 192);
+    sol_ptr[g] = keep.back().as<double>();
+  }
   const int max_rhs = ctx->inflight_rhs;
   const int tiers[4] = {DL_TIER_FP64, DL_TIER_LP_BF16, DL_TIER_LP_FP16, DL_TIER_HP_FP32};
   for (int tier : tiers) {
@@ -979,7 +1028,8 @@ bool solve_jobs(dl_ctx* ctx, const std::vector<dl_job>& J, dl_src_stats* stats) 
         sp.nrhs = std::min(N, q.nsrc - k);
         sp.src0 = q.first_src + k;
         sp.src_user = q.src_in ? q.src_in + (size_t)k * V * 24 : nullptr;
-        sp.sol_user = q.sol_out ? q.sol_out + (size_t)k * V * 24 : nullptr;
+        sp.sol_user = sol_ptr[j] ? sol_ptr[j] + (size_t)k * V * 24 : nullptr;
+        sp.x0_user = q.guess_from ? sol_ptr[q.guess_from - 1] + (size_t)k * V * 24 : nullptr;
         sp.acc = q.accum ? q.accum->acc[q.accum_set] : nullptr;
         sp.tblk = tc.tblk;
         all.push_back(sp);

@@ -257,6 +257,47 @@ def _solve(ctx, lat, tier, nsrc, block, seed=5, first=0):
     return host(sol), [s.iters for s in stats]
 
 
+@pytest.mark.parametrize("lp_sol", [False, True])
+def test_hp_started_from_lp_solutions(ctx, lp_sol):
+    """HP solves started from the LP solutions of the same sources (guess_from) reach the same
+    accuracy against the exact solution in fewer iterations; the LP solutions come from the
+    caller's sol_out when given, else from a library buffer."""
+    dims = (8, 8, 8, 8)
+    lat = make_lattice(ctx, dims, 1405, 0.2, 0.1615, 0.004)
+    n, tol = 4, 1e-8
+    sol0 = zeros_dev((n,) + lat.field_shape)
+    base = dl.make_job(lat.h, noise=dl.DL_NOISE_Z2, tier=dl.DL_TIER_HP_FP32, seed=3, nsrc=n, tol=tol, maxiter=2000,
+                       report_true_resid=1, sol_out=sol0)
+    _, st0 = dl.dl_solve_batch(ctx, base)
+    sol = zeros_dev((n,) + lat.field_shape)
+    lp_out = zeros_dev((n,) + lat.field_shape) if lp_sol else None
+    jobs = [dl.make_job(lat.h, noise=dl.DL_NOISE_Z2, tier=dl.DL_TIER_LP_BF16, seed=3, nsrc=n, tol=1e-2,
+                        maxiter=500, sol_out=lp_out),
+            dl.make_job(lat.h, noise=dl.DL_NOISE_Z2, tier=dl.DL_TIER_HP_FP32, seed=3, nsrc=n, tol=tol, maxiter=2000,
+                        report_true_resid=1, sol_out=sol, guess_from=1)]
+    rc, st = dl.dl_solve_batch(ctx, jobs)
+    assert rc == dl.DL_OK
+    got = host(sol)
+    for r in range(n):
+        hs = st[n + r]
+        eta = noise.source(dims, 3, r, noise.Z2)
+        exact, _ = solver.cgnr_eo(lat.U, eta, lat.kappa, lat.mu, lat.bc, dims, 1e-13)
+        err = rel(got[r], exact)
+        tr = solver.true_residual(lat.U, eta, got[r], lat.kappa, lat.mu, lat.bc)
+        log(f"guess: iters {hs.iters} (from zero {st0[r].iters}) RU {hs.reliable_updates} true {tr:.3e} err {err:.3e}")
+        assert hs.status == dl.DL_SRC_CONVERGED
+        assert tr < 20 * tol and err < 100 * tol
+        assert hs.iters < st0[r].iters
+    # invalid pairings are rejected before any work
+    bad = [dict(guess_from=2), dict(guess_from=5), dict(seed=4, guess_from=1)]
+    for kw in bad:
+        lp = dl.make_job(lat.h, noise=dl.DL_NOISE_Z2, tier=dl.DL_TIER_LP_BF16, seed=3, nsrc=n, tol=1e-2)
+        args = dict(noise=dl.DL_NOISE_Z2, tier=dl.DL_TIER_HP_FP32, seed=3, nsrc=n, tol=tol)
+        args.update(kw)
+        with pytest.raises(dl.DiscloopError):
+            dl.dl_solve_batch(ctx, [lp, dl.make_job(lat.h, **args)])
+
+
 @pytest.mark.parametrize("tier", [dl.DL_TIER_LP_BF16, dl.DL_TIER_LP_FP16])
 def test_lp_map_is_independent_of_blocking(ctx, tier):
     lat = make_lattice(ctx, (6, 6, 6, 8), 21, 0.2, 0.1615, 0.004)
