@@ -120,6 +120,44 @@ __device__ inline void reconstruct(cx<R> (&acc)[12], const cx<R> (&w0)[3], const
 }
 
 
+// reconstruct() for one colour row c.
+template <int MU, bool FWD, bool INIT, class R>
+__device__ inline void reconstruct_row(cx<R> (&acc)[12], int c, cx<R> w0, cx<R> w1, R sign) {
+  auto put = [&](int idx, cx<R> w) {
+    if (INIT) acc[idx] = w; else acc[idx] = acc[idx] + w;
+  };
+  auto put_s = [&](int idx, cx<R> w, R f) {
+    if (INIT) acc[idx] = f * w; else acc[idx] = mk<R>(fmadd(f, w.re, acc[idx].re), fmadd(f, w.im, acc[idx].im));
+  };
+  if (MU == 0) {
+    put(c, w0);
+    put(3 + c, w1);
+    put(6 + c, FWD ? times_mi(w1) : times_i(w1));
+    put(9 + c, FWD ? times_mi(w0) : times_i(w0));
+  } else if (MU == 1) {
+    put(c, w0);
+    put(3 + c, w1);
+    if (INIT) {
+      acc[6 + c] = FWD ? mk<R>(-w1.re, -w1.im) : w1;
+      acc[9 + c] = FWD ? w0 : mk<R>(-w0.re, -w0.im);
+    } else {
+      acc[6 + c] = FWD ? acc[6 + c] - w1 : acc[6 + c] + w1;
+      acc[9 + c] = FWD ? acc[9 + c] + w0 : acc[9 + c] - w0;
+    }
+  } else if (MU == 2) {
+    put(c, w0);
+    put(3 + c, w1);
+    put(6 + c, FWD ? times_mi(w0) : times_i(w0));
+    put(9 + c, FWD ? times_i(w1) : times_mi(w1));
+  } else {
+    const R ms = -sign;
+    put_s(c, w0, sign);
+    put_s(3 + c, w1, sign);
+    put_s(6 + c, w0, FWD ? ms : sign);
+    put_s(9 + c, w1, FWD ? ms : sign);
+  }
+}
+
 // Spin projection of one hop as (h0, h1) = (psi_0 + c0 psi_B0, psi_1 + c1 psi_B1),
 // c in {+1, -1, +i, -i} coded 0..3 (the same combinations as project()).
 template <int MU, bool FWD> struct ProjSpec;
@@ -232,6 +270,76 @@ __device__ inline void hop(const void* gauge, long vp, int link_par, int link_si
   }
 }
 
+// ---- software-pipelined 16-bit hops ---------------------------------------
+// The words one hop needs (link record, neighbour spinor of every group
+// member) are loaded one hop ahead of the arithmetic that uses them, so a
+// wave has the next hop's loads in flight while it computes the current one.
+template <int G>
+struct HopWords {
+  uint32_t e[9];
+  uint32_t v[G][12];
+};
+
+template <int MU, int G>
+__device__ inline void hop_load16(HopWords<G>& h, const void* gauge, long vp, int link_par, int link_site, int nb,
+                                  const void* const (&inb)[G]) {
+  const uint4* lp = (const uint4*)gauge + ((long)(MU * 2 + link_par) * vp + link_site) * 3;
+  const uint4 l0 = lp[0], l1 = lp[1], l2 = lp[2];
+  h.e[0] = l0.x; h.e[1] = l0.y; h.e[2] = l0.z; h.e[3] = l0.w;
+  h.e[4] = l1.x; h.e[5] = l1.y; h.e[6] = l1.z; h.e[7] = l1.w; h.e[8] = l2.x;
+#pragma unroll
+  for (int i = 0; i < G; ++i) {
+    const uint4* q = (const uint4*)inb[i];
+    const uint4 q0 = q[nb], q1 = q[vp + nb], q2 = q[2 * vp + nb];
+    h.v[i][0] = q0.x; h.v[i][1] = q0.y; h.v[i][2] = q0.z; h.v[i][3] = q0.w;
+    h.v[i][4] = q1.x; h.v[i][5] = q1.y; h.v[i][6] = q1.z; h.v[i][7] = q1.w;
+    h.v[i][8] = q2.x; h.v[i][9] = q2.y; h.v[i][10] = q2.z; h.v[i][11] = q2.w;
+  }
+}
+
+// The arithmetic of one hop, one colour row a at a time (only that row's
+// coefficient words are live).
+template <class S, int MU, bool FWD, bool INIT, int G>
+__device__ inline void hop_compute16(const HopWords<G>& h, float sign, const bool (&act)[G],
+                                     cx<float> (&acc)[G][12]) {
+  using PS = ProjSpec<MU, FWD>;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    uint32_t cr[3], ci[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const uint32_t w = FWD ? h.e[3 * a + b] : h.e[3 * b + a];
+      cr[b] = FWD ? (w ^ 0x80000000u) : w;
+      ci[b] = FWD ? swap16(w) : (swap16(w) ^ 0x00008000u);
+    }
+    uint32_t pr0[3], pi0[3], pr1[3], pi1[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const uint32_t ncr = cr[b] ^ 0x80008000u, nci = ci[b] ^ 0x80008000u;
+      pr0[b] = PS::c0 == 0 ? cr[b] : (PS::c0 == 1 ? ncr : (PS::c0 == 2 ? nci : ci[b]));
+      pi0[b] = PS::c0 == 0 ? ci[b] : (PS::c0 == 1 ? nci : (PS::c0 == 2 ? cr[b] : ncr));
+      pr1[b] = PS::c1 == 0 ? cr[b] : (PS::c1 == 1 ? ncr : (PS::c1 == 2 ? nci : ci[b]));
+      pi1[b] = PS::c1 == 0 ? ci[b] : (PS::c1 == 1 ? nci : (PS::c1 == 2 ? cr[b] : ncr));
+    }
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      if (!act[i]) continue;
+      const uint32_t (&v)[12] = h.v[i];
+      auto chain = [&](const uint32_t (&c)[3], int sa, const uint32_t (&p)[3], int sb) {
+        float x = dot2_first<S>(c[0], v[3 * sa]);
+        x = dot2<S>(c[1], v[3 * sa + 1], x);
+        x = dot2<S>(c[2], v[3 * sa + 2], x);
+        x = dot2<S>(p[0], v[3 * sb], x);
+        x = dot2<S>(p[1], v[3 * sb + 1], x);
+        return dot2<S>(p[2], v[3 * sb + 2], x);
+      };
+      const cx<float> w0 = mk<float>(chain(cr, 0, pr0, PS::b0), chain(ci, 0, pi0, PS::b0));
+      const cx<float> w1 = mk<float>(chain(cr, 1, pr1, PS::b1), chain(ci, 1, pi1, PS::b1));
+      reconstruct_row<MU, FWD, INIT>(acc[i], a, w0, w1, sign);
+    }
+  }
+}
+
 template <class R>
 __device__ inline void load_coef(const double (&c)[4][2], cx<R> (&out)[4]) {
 #pragma unroll
@@ -304,6 +412,33 @@ __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
     cx<R> acc[G][12];
     constexpr bool HD = (F & F_D) != 0;
     const int q = 1 - p_out;
+    if constexpr (Traits<S>::NC == 3 && !HD) {
+      // members that are inactive read the first active member's field
+      const void* fa = nullptr;
+#pragma unroll
+      for (int i = G - 1; i >= 0; --i)
+        if (act[i]) fa = inb[i];
+      const void* ld[G];
+#pragma unroll
+      for (int i = 0; i < G; ++i) ld[i] = act[i] ? inb[i] : fa;
+      HopWords<G> h0, h1;
+      hop_load16<0>(h0, gauge, vp, p_out, s, nxp, ld);
+      hop_load16<0>(h1, gauge, vp, q, nxm, nxm, ld);
+      hop_compute16<S, 0, true, true>(h0, 1.0f, act, acc);
+      hop_load16<1>(h0, gauge, vp, p_out, s, nyp, ld);
+      hop_compute16<S, 0, false, false>(h1, 1.0f, act, acc);
+      hop_load16<1>(h1, gauge, vp, q, nym, nym, ld);
+      hop_compute16<S, 1, true, false>(h0, 1.0f, act, acc);
+      hop_load16<2>(h0, gauge, vp, p_out, s, nzp, ld);
+      hop_compute16<S, 1, false, false>(h1, 1.0f, act, acc);
+      hop_load16<2>(h1, gauge, vp, q, nzm, nzm, ld);
+      hop_compute16<S, 2, true, false>(h0, 1.0f, act, acc);
+      hop_load16<3>(h0, gauge, vp, p_out, s, ntp, ld);
+      hop_compute16<S, 2, false, false>(h1, 1.0f, act, acc);
+      hop_load16<3>(h1, gauge, vp, q, ntm, ntm, ld);
+      hop_compute16<S, 3, true, false>(h0, (float)sp, act, acc);
+      hop_compute16<S, 3, false, false>(h1, (float)sm, act, acc);
+    } else {
     hop<S, 0, true, HD, true>(gauge, vp, p_out, s, nxp, (R)1, inb, nr, act, d, acc);
     hop<S, 0, false, HD, false>(gauge, vp, q, nxm, nxm, (R)1, inb, nr, act, d, acc);
     hop<S, 1, true, HD, false>(gauge, vp, p_out, s, nyp, (R)1, inb, nr, act, d, acc);
@@ -312,6 +447,7 @@ __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
     hop<S, 2, false, HD, false>(gauge, vp, q, nzm, nzm, (R)1, inb, nr, act, d, acc);
     hop<S, 3, true, HD, false>(gauge, vp, p_out, s, ntp, sp, inb, nr, act, d, acc);
     hop<S, 3, false, HD, false>(gauge, vp, q, ntm, ntm, sm, inb, nr, act, d, acc);
+    }
 #pragma unroll
     for (int i = 0; i < G; ++i) {
       if (!act[i]) continue;
