@@ -262,6 +262,69 @@ void launch_unpack(int prec, const SlotDesc* slots, int nslots, int total_units,
 }
 
 // ---------------------------------------------------------------------------
+// initial guesses kept between the solves of one call
+// ---------------------------------------------------------------------------
+template <class S>
+__global__ __launch_bounds__(256) void k_guess_store(const SlotDesc* slots, int nslots, int total_units,
+                                                     const void* f) {
+  UnitRhs w;
+  if (!decode_rhs_unit(slots, nslots, total_units, w)) return;
+  const SlotDesc& sd = slots[w.si];
+  if (!sd.gsave || !w.valid) return;
+  constexpr int NC = Traits<S>::NC;
+  const uint4* src = (const uint4*)field_at<S>(f, w.off);
+  uint4* dst = (uint4*)sd.gsave + (long long)w.r * NC * sd.Vp;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) dst[(long long)k * sd.Vp + w.s] = src[(long long)k * sd.Vp + w.s];
+}
+
+template <class SO, class SI>
+__device__ inline void guess_load_one(const SlotDesc& sd, const UnitRhs& w, void* f) {
+  using RI = typename Traits<SI>::R;
+  using RO = typename Traits<SO>::R;
+  cx<RI> a[12];
+  load_spinor<SI>((const char*)sd.gload + (long long)w.r * Traits<SI>::NC * sd.Vp * 16, sd.Vp, w.s, a);
+  cx<RO> b[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) b[k] = mk<RO>((RO)a[k].re, (RO)a[k].im);
+  store_spinor<SO>(field_at<SO>(f, w.off), sd.Vp, w.s, b);
+}
+
+template <class SO>
+__global__ __launch_bounds__(256) void k_guess_load(const SlotDesc* slots, int nslots, int total_units, void* f) {
+  using RO = typename Traits<SO>::R;
+  UnitRhs w;
+  if (!decode_rhs_unit(slots, nslots, total_units, w)) return;
+  const SlotDesc& sd = slots[w.si];
+  if (!w.valid) return;
+  switch (sd.gload ? sd.gprec : -1) {
+    case P64: guess_load_one<SO, double>(sd, w, f); break;
+    case P32: guess_load_one<SO, float>(sd, w, f); break;
+    case PB16: guess_load_one<SO, bf16s>(sd, w, f); break;
+    case PH16: guess_load_one<SO, f16s>(sd, w, f); break;
+    default: {
+      cx<RO> z[12];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) z[k] = mk<RO>(0, 0);
+      store_spinor<SO>(field_at<SO>(f, w.off), sd.Vp, w.s, z);
+    }
+  }
+}
+
+void launch_guess_store(int prec, const SlotDesc* slots, int nslots, int total_units, const void* f,
+                        hipStream_t st) {
+  if (!total_units) return;
+  DISPATCH_PREC(prec, k_guess_store, dim3(grid_for(total_units, 4)), dim3(256), 0, st, slots, nslots, total_units,
+                f);
+}
+
+void launch_guess_load(int prec, const SlotDesc* slots, int nslots, int total_units, void* f, hipStream_t st) {
+  if (!total_units) return;
+  DISPATCH_PREC(prec, k_guess_load, dim3(grid_for(total_units, 4)), dim3(256), 0, st, slots, nslots, total_units,
+                f);
+}
+
+// ---------------------------------------------------------------------------
 // precision conversion and reliable-update helpers
 // ---------------------------------------------------------------------------
 template <class SI, class SO>

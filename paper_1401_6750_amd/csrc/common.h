@@ -384,6 +384,10 @@ struct SlotDesc {
   int acc_ops;             // DL_OPS_* of the accumulator
   const double* src_user;  // caller sources of rhs 0 (complex128 [V][12] per rhs), or null
   double* sol_user;        // caller solution array of rhs 0, or null
+  void* gsave;             // guess buffer of rhs 0 to store the odd solution in, or null
+  const void* gload;       // guess buffer of rhs 0 to start the odd solution from, or null
+  int gprec;               // storage precision of gload
+  int pad1;
 };
 
 // Per-slot site-diagonal spin coefficients of one dslash-type launch:

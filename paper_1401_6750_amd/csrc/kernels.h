@@ -57,6 +57,13 @@ void launch_finalize(int kind, const SlotDesc* slots, int nslots, int nrhs_total
                      const double* partial, const CgScalars& cs, hipStream_t st);
 
 // x += alpha p where upd is set (every rhs that took this iteration's step),
+// Initial guesses: copy the odd solution field of every slot with gsave to
+// its guess buffer (raw words, the field's precision), and load slots with
+// gload (precision gprec) into a field of precision `prec` (zeros elsewhere).
+void launch_guess_store(int prec, const SlotDesc* slots, int nslots, int total_units, const void* f,
+                        hipStream_t st);
+void launch_guess_load(int prec, const SlotDesc* slots, int nslots, int total_units, void* f, hipStream_t st);
+
 // then p = r + beta p for the right-hand sides still active
 void launch_update_p(int prec, const SlotDesc* slots, int nslots, int total_units, void* p,
                      const void* r, void* x, const double* alpha, const double* beta, const int* active,

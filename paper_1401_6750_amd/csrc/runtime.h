@@ -113,7 +113,11 @@ struct SlotPlan {
   double* sol_user;
   double* acc;
   int tblk;                // tile-order time block (0: default)
-  const double* x0_user;   // initial guess of rhs 0 (complex128 [V][12] per rhs), or null
+  // initial guesses: per job rhs a [chunk][Vp] half field (odd sites) in the
+  // storage precision of the job that produced it
+  void* gsave;             // store this slot's odd solutions here (rhs 0), or null
+  const void* gload;       // start this slot's CG from here (rhs 0), or null
+  int gprec;               // precision of gload
 };
 
 struct SolveReport {

@@ -248,6 +248,9 @@ struct Batch {
       d.src0 = sp.src0;
       d.src_user = sp.src_user;
       d.sol_user = sp.sol_user;
+      d.gsave = sp.gsave;
+      d.gload = sp.gload;
+      d.gprec = sp.gprec;
       ur += d.ntile * d.nrhs;
       us += 2 * d.ntile;
       ud += 8 * d.ntile;
@@ -566,6 +569,9 @@ void run_batch(dl_ctx* ctx, int tier, const std::vector<SlotPlan>& plan, const s
   if (tier != DL_TIER_HP_FP32) {
     cg_start(b, P, eta_e.p, eta_o.p, f);
     run_cg_plain(b, P, f, maxiter_all, first_burst);
+    bool any_gsave = false;
+    for (const SlotPlan& sp : plan) any_gsave = any_gsave || sp.gsave;
+    if (any_gsave) launch_guess_store(P, b.slots(), b.nslots, b.u_rhs, x.p, st);
   } else {
     // High precision: FP32 CG with FP64 reliable updates (true residual of
     // the normal equations recomputed in FP64, solution accumulated in FP64).
@@ -617,18 +623,11 @@ void run_batch(dl_ctx* ctx, int tier, const std::vector<SlotPlan>& plan, const s
       b.finalize_store(b.cs.rr, fl, b.partial.as<double>());
     };
     bool any_x0 = false;
-    for (const SlotPlan& sp : plan) any_x0 = any_x0 || sp.x0_user;
+    for (const SlotPlan& sp : plan) any_x0 = any_x0 || sp.gload;
     if (any_x0) {
       // initial guesses (odd sites) into the FP64 solution, then one reliable
       // update gives the starting residual, and p = r
-      std::vector<SlotDesc> g0 = b.hs;
-      for (size_t i = 0; i < g0.size(); ++i) {
-        g0[i].noise = DL_NOISE_USER;
-        g0[i].src_user = plan[i].x0_user;
-      }
-      DevBuf dg0(ctx, sizeof(SlotDesc) * g0.size());
-      HIPCHECK(hipMemcpyAsync(dg0.p, g0.data(), sizeof(SlotDesc) * g0.size(), hipMemcpyHostToDevice, st));
-      launch_sources(P64, dg0.as<SlotDesc>(), b.nslots, b.u_rhs, 1, xhi.p, st);
+      launch_guess_load(P64, b.slots(), b.nslots, b.u_rhs, xhi.p, st);
       std::vector<int> ones(b.nrhs, 1);
       HIPCHECK(hipMemcpyAsync(flag.p, ones.data(), sizeof(int) * b.nrhs, hipMemcpyHostToDevice, st));
       reliable_update(flag.as<int>());
@@ -999,14 +998,14 @@ bool solve_jobs(dl_ctx* ctx, const std::vector<dl_job>& J, dl_src_stats* stats) 
   const double budget = ctx->inflight_mb * 1048576.0;
   // solutions that HP jobs start from: the caller's sol_out, or a library
   // buffer kept for this call (the lower tiers run first)
-  std::vector<double*> sol_ptr(njobs, nullptr);
+  std::vector<void*> gbuf(njobs, nullptr);
   std::vector<DevBuf> keep;
-  for (int j = 0; j < njobs; ++j) sol_ptr[j] = J[j].sol_out;
   for (int j = 0; j < njobs; ++j) {
     const int g = J[j].guess_from - 1;
-    if (g < 0 || sol_ptr[g] || J[g].nsrc == 0) continue;
-    keep.emplace_back(ctx, (size_t)J[g].nsrc * J[g].lat->V * 192);
-    sol_ptr[g] = keep.back().as<double>();
+    if (g < 0 || gbuf[g] || J[g].nsrc == 0) continue;
+    const size_t per = (size_t)chunks_of(tier_prec(J[g].tier)) * pad_half(J[g].lat->Vh) * 16;
+    keep.emplace_back(ctx, (size_t)J[g].nsrc * per);
+    gbuf[g] = keep.back().p;
   }
   const int max_rhs = ctx->inflight_rhs;
   const int tiers[4] = {DL_TIER_FP64, DL_TIER_LP_BF16, DL_TIER_LP_FP16, DL_TIER_HP_FP32};
@@ -1028,8 +1027,18 @@ bool solve_jobs(dl_ctx* ctx, const std::vector<dl_job>& J, dl_src_stats* stats) 
         sp.nrhs = std::min(N, q.nsrc - k);
         sp.src0 = q.first_src + k;
         sp.src_user = q.src_in ? q.src_in + (size_t)k * V * 24 : nullptr;
-        sp.sol_user = sol_ptr[j] ? sol_ptr[j] + (size_t)k * V * 24 : nullptr;
-        sp.x0_user = q.guess_from ? sol_ptr[q.guess_from - 1] + (size_t)k * V * 24 : nullptr;
+        sp.sol_user = q.sol_out ? q.sol_out + (size_t)k * V * 24 : nullptr;
+        if (gbuf[j]) {
+          const size_t per = (size_t)chunks_of(P) * pad_half(q.lat->Vh) * 16;
+          sp.gsave = (char*)gbuf[j] + (size_t)k * per;
+        }
+        if (q.guess_from) {
+          const dl_job& h = J[q.guess_from - 1];
+          const int PG = tier_prec(h.tier);
+          const size_t per = (size_t)chunks_of(PG) * pad_half(h.lat->Vh) * 16;
+          sp.gload = (const char*)gbuf[q.guess_from - 1] + (size_t)k * per;
+          sp.gprec = PG;
+        }
         sp.acc = q.accum ? q.accum->acc[q.accum_set] : nullptr;
         sp.tblk = tc.tblk;
         all.push_back(sp);
