@@ -335,26 +335,34 @@ __device__ inline void load_link<f16s>(const void* g, long vh, int mu, int par, 
 // batch slots
 // ---------------------------------------------------------------------------
 // Unit kinds: UK_RHS (one tile x one rhs), UK_SITE (one tile x one parity),
-// UK_DERIV (one tile x parity x direction), UK_GRP (one tile x RG rhs: the
-// hopping kernel runs RG right-hand sides per wavefront).
-enum UnitKind : int { UK_RHS = 0, UK_SITE = 1, UK_DERIV = 2, UK_GRP = 3 };
-// Right-hand sides per wavefront in the hopping kernel.  Sharing a wave
-// shares the link loads, the link-word preparation and the index arithmetic,
-// at the cost of registers.  Measured on gfx950 at 24^3x48: bf16 8.2 ms per
-// 525-rhs launch with two against 8.9 ms with one (the 16-bit kernels keep
-// spinors packed, so two fit in ~110 registers); FP32 HP solves +10 % and the
-// FP64 single-rhs path +27 % with two.  DL_RHS_PER_WAVE_WIDE sets FP32 / FP64
-// separately (1 or RG).  UK_GRP units are groups of RG right-hand sides.
-#ifndef DL_RHS_PER_WAVE
-#define DL_RHS_PER_WAVE 2
+// UK_DERIV (one tile x parity x direction), UK_GRP2 / UK_GRP4 (one tile x 2 / 4
+// rhs: the hopping kernel runs that many right-hand sides per wavefront).
+enum UnitKind : int { UK_RHS = 0, UK_SITE = 1, UK_DERIV = 2, UK_GRP2 = 3, UK_GRP4 = 4, UK_COUNT = 5 };
+// Right-hand sides per wavefront in the hopping kernel, per storage type
+// (1, 2 or 4).  Sharing a wave shares the link loads, the link-word
+// preparation and the index arithmetic, at the cost of registers.  Measured
+// on gfx950 at 24^3x48: bf16 8.2 ms per 525-rhs launch with two against 8.9 ms
+// with one (the 16-bit kernels keep spinors packed, so two fit in ~110
+// registers); FP32 HP solves +10 % and the FP64 single-rhs path +27 % with two.
+#ifndef DL_RPW16
+#define DL_RPW16 2
 #endif
-#ifndef DL_RHS_PER_WAVE_WIDE
-#define DL_RHS_PER_WAVE_WIDE 2
+#ifndef DL_RPW32
+#define DL_RPW32 2
 #endif
-constexpr int RG = DL_RHS_PER_WAVE;
-static_assert(DL_RHS_PER_WAVE_WIDE == 1 || DL_RHS_PER_WAVE_WIDE == RG, "wide types use 1 or RG rhs per wave");
-template <class S> constexpr int rhs_per_wave() { return Traits<S>::NC == 3 ? RG : DL_RHS_PER_WAVE_WIDE; }
-inline int rhs_per_wave_prec(int prec) { return (prec == PB16 || prec == PH16) ? RG : DL_RHS_PER_WAVE_WIDE; }
+#ifndef DL_RPW64
+#define DL_RPW64 2
+#endif
+template <class S> constexpr int rhs_per_wave() {
+  return Traits<S>::NC == 3 ? DL_RPW16 : (Traits<S>::NC == 6 ? DL_RPW32 : DL_RPW64);
+}
+inline int rhs_per_wave_prec(int prec) {
+  return (prec == PB16 || prec == PH16) ? DL_RPW16 : (prec == P32 ? DL_RPW32 : DL_RPW64);
+}
+constexpr int unit_kind_for_group(int g) { return g == 1 ? UK_RHS : (g == 2 ? UK_GRP2 : UK_GRP4); }
+static_assert((DL_RPW16 == 1 || DL_RPW16 == 2 || DL_RPW16 == 4) && (DL_RPW32 == 1 || DL_RPW32 == 2 || DL_RPW32 == 4) &&
+                  (DL_RPW64 == 1 || DL_RPW64 == 2 || DL_RPW64 == 4),
+              "right-hand sides per wave: 1, 2 or 4");
 
 // Site stride of every per-parity device array (spinor chunk rows, link
 // records, accumulator rows): Vh rounded up to an odd number of 64-site
@@ -372,7 +380,7 @@ struct SlotDesc {
   int Xh, Vh, ntile, nrhs;
   int Vp;                  // pad_half(Vh): row stride of fields, links, accumulators
   int tblk;                // time slices per block of the hopping kernel's tile order
-  int ubeg[4];             // first unit of this slot per UnitKind
+  int ubeg[UK_COUNT];      // first unit of this slot per UnitKind
   int rhs_begin;           // global index of this slot's rhs 0
   long long fo;            // site offset of rhs 0 in every batch field
   double bc;               // time-boundary factor

@@ -350,7 +350,7 @@ template <class S, int F>
 __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
   using R = typename Traits<S>::R;
   constexpr int G = rhs_per_wave<S>();
-  constexpr int UK = G == 1 ? UK_RHS : UK_GRP;
+  constexpr int UK = unit_kind_for_group(G);
   const int u = wave_unit();
   if (u >= a.total_units) return;
   const int lane = threadIdx.x & 63;

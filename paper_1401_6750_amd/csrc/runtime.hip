@@ -209,7 +209,7 @@ struct Batch {
   std::vector<SlotDesc> hs;
   std::vector<Coef> coefs;     // host copies stay alive while their uploads are in flight
   DevBuf dslots, dcoef;
-  int nslots = 0, nrhs = 0, u_rhs = 0, u_site = 0, u_deriv = 0, u_grp = 0;
+  int nslots = 0, nrhs = 0, u_rhs = 0, u_site = 0, u_deriv = 0, u_grp2 = 0, u_grp4 = 0;
   long long sites = 0;
   DevBuf partial, partial2, scal;
   CgScalars cs{};
@@ -218,7 +218,7 @@ struct Batch {
 
   Batch(dl_ctx* c, int prec_, const std::vector<SlotPlan>& plan, const std::vector<dl_job>* jobs)
       : ctx(c), prec(prec_) {
-    int ur = 0, us = 0, ud = 0, ug = 0, rb = 0;
+    int ur = 0, us = 0, ud = 0, ug2 = 0, ug4 = 0, rb = 0;
     long long fo = 0;
     for (const SlotPlan& sp : plan) {
       const dl_lattice* L = sp.lat;
@@ -230,7 +230,8 @@ struct Batch {
       d.Vp = (int)pad_half(d.Vh);
       d.tblk = sp.tblk > 0 ? sp.tblk : TBLK_DEFAULT;
       d.nrhs = sp.nrhs;
-      d.ubeg[UK_RHS] = ur; d.ubeg[UK_SITE] = us; d.ubeg[UK_DERIV] = ud; d.ubeg[UK_GRP] = ug;
+      d.ubeg[UK_RHS] = ur; d.ubeg[UK_SITE] = us; d.ubeg[UK_DERIV] = ud;
+      d.ubeg[UK_GRP2] = ug2; d.ubeg[UK_GRP4] = ug4;
       d.rhs_begin = rb;
       d.fo = fo;
       d.bc = (double)L->bc;
@@ -254,14 +255,15 @@ struct Batch {
       ur += d.ntile * d.nrhs;
       us += 2 * d.ntile;
       ud += 8 * d.ntile;
-      ug += d.ntile * ((d.nrhs + RG - 1) / RG);
+      ug2 += d.ntile * ((d.nrhs + 1) / 2);
+      ug4 += d.ntile * ((d.nrhs + 3) / 4);
       rb += d.nrhs;
       fo += (long long)d.nrhs * d.Vp;
       hs.push_back(d);
     }
     nslots = (int)hs.size();
     nrhs = rb;
-    u_rhs = ur; u_site = us; u_deriv = ud; u_grp = ug;
+    u_rhs = ur; u_site = us; u_deriv = ud; u_grp2 = ug2; u_grp4 = ug4;
     sites = fo;
     dslots = DevBuf(ctx, sizeof(SlotDesc) * nslots);
     HIPCHECK(hipMemcpyAsync(dslots.p, hs.data(), sizeof(SlotDesc) * nslots, hipMemcpyHostToDevice, ctx->st));
@@ -301,7 +303,8 @@ struct Batch {
               void* out2 = nullptr, double* part = nullptr) {
     DslashArgs a{};
     a.slots = slots(); a.nslots = nslots; a.coef = coef(ck); a.p_out = p_out;
-    a.total_units = rhs_per_wave_prec(p) == 1 ? u_rhs : u_grp;
+    const int g = rhs_per_wave_prec(p);
+    a.total_units = g == 1 ? u_rhs : (g == 2 ? u_grp2 : u_grp4);
     a.in = in; a.out = out; a.y = y; a.partial = part ? part : partial.as<double>(); a.active = gate;
     a.x = x; a.r = r; a.p = pp; a.alpha = cs.alpha; a.out2 = out2;
     launch_dslash(p, flags, a, ctx->st);
