@@ -170,103 +170,36 @@ template <> struct ProjSpec<2, false> { static constexpr int b0 = 2, c0 = 3, b1 
 template <> struct ProjSpec<3, true> { static constexpr int b0 = 2, c0 = 1, b1 = 3, c1 = 1; };
 template <> struct ProjSpec<3, false> { static constexpr int b0 = 2, c0 = 0, b1 = 3, c1 = 0; };
 
-// Packed path: w = M h with the projection folded into the dot2 chains.  For
-// the term c psi_B: Re(M c psi) and Im(M c psi) are dot2 products of psi_B
-// with (cr, ci) for c = +1, (-cr, -ci) for -1, (-ci, cr) for +i and (ci, -cr)
-// for -i; -x of a packed pair flips both sign bits.
-template <class S, int C>
-__device__ inline void proj_coef(const uint32_t (&cr)[9], const uint32_t (&ci)[9], uint32_t (&pr)[9],
-                                 uint32_t (&pi)[9]) {
-#pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    const uint32_t ncr = cr[k] ^ 0x80008000u, nci = ci[k] ^ 0x80008000u;
-    pr[k] = C == 0 ? cr[k] : (C == 1 ? ncr : (C == 2 ? nci : ci[k]));
-    pi[k] = C == 0 ? ci[k] : (C == 1 ? nci : (C == 2 ? cr[k] : ncr));
-  }
-}
-
-template <class S>
-__device__ inline void proj_mul16(const uint32_t (&cr)[9], const uint32_t (&ci)[9], const uint32_t (&pr)[9],
-                                  const uint32_t (&pi)[9], const uint32_t (&v)[12], int sa, int sb,
-                                  cx<float> (&w)[3]) {
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    float re = dot2_first<S>(cr[3 * a], v[3 * sa]);
-    re = dot2<S>(cr[3 * a + 1], v[3 * sa + 1], re);
-    re = dot2<S>(cr[3 * a + 2], v[3 * sa + 2], re);
-    re = dot2<S>(pr[3 * a], v[3 * sb], re);
-    re = dot2<S>(pr[3 * a + 1], v[3 * sb + 1], re);
-    re = dot2<S>(pr[3 * a + 2], v[3 * sb + 2], re);
-    float im = dot2_first<S>(ci[3 * a], v[3 * sa]);
-    im = dot2<S>(ci[3 * a + 1], v[3 * sa + 1], im);
-    im = dot2<S>(ci[3 * a + 2], v[3 * sa + 2], im);
-    im = dot2<S>(pi[3 * a], v[3 * sb], im);
-    im = dot2<S>(pi[3 * a + 1], v[3 * sb + 1], im);
-    im = dot2<S>(pi[3 * a + 2], v[3 * sb + 2], im);
-    w[a] = mk<float>(re, im);
-  }
-}
-
 // One hop (direction MU, forward or backward) for every right-hand side of
-// the group: the link is loaded once.
-//
-// 16-bit storage without the input factor d: the colour products are formed
-// on the packed words.  With M = U (forward) or U^dag (backward), each entry
-// M_ab contributes Re += dot2(cr_ab, psi_b), Im += dot2(ci_ab, psi_b) where
-//   forward:  cr = (Re U_ab, -Im U_ab), ci = (Im U_ab, Re U_ab)
-//   backward: cr = (Re U_ba,  Im U_ba), ci = (-Im U_ba, Re U_ba),
-// so every spin component is multiplied (4 colour vectors instead of the 2
-// projected ones, at half the instructions per product) and the spin
-// projection is taken on the products, M(1 -+ gamma) psi = (1 -+ gamma) M psi.
+// the group, unpacked arithmetic: FP32 / FP64 storage, and 16-bit storage with
+// the input factor d.  The link is loaded once; the spin projection comes
+// first and two colour vectors are multiplied.
 template <class S, int MU, bool FWD, bool HAS_D, bool INIT, int G>
 __device__ inline void hop(const void* gauge, long vp, int link_par, int link_site, int nb, typename Traits<S>::R sign,
                            const void* const (&inb)[G], int nr, const bool (&act)[G],
                            const cx<typename Traits<S>::R> (&d)[4], cx<typename Traits<S>::R> (&acc)[G][12]) {
   using R = typename Traits<S>::R;
-  if constexpr (Traits<S>::NC == 3 && !HAS_D) {
-    const uint4* lp = (const uint4*)gauge + ((long)(MU * 2 + link_par) * vp + link_site) * 3;
-    const uint4 l0 = lp[0], l1 = lp[1], l2 = lp[2];
-    const uint32_t e[9] = {l0.x, l0.y, l0.z, l0.w, l1.x, l1.y, l1.z, l1.w, l2.x};
-    uint32_t cr[9], ci[9];
-    link_coef16<FWD>(e, false, cr, ci);
-    using PS = ProjSpec<MU, FWD>;
-    uint32_t pr0[9], pi0[9], pr1[9], pi1[9];
-    proj_coef<S, PS::c0>(cr, ci, pr0, pi0);
-    proj_coef<S, PS::c1>(cr, ci, pr1, pi1);
+  cx<R> u[9];
+  load_link<S>(gauge, vp, MU, link_par, link_site, u);
 #pragma unroll
-    for (int i = 0; i < G; ++i) {
-      if (i >= nr || !act[i]) continue;
-      const uint4* q = (const uint4*)inb[i];
-      const uint4 q0 = q[nb], q1 = q[vp + nb], q2 = q[2 * vp + nb];
-      const uint32_t v[12] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w};
-      cx<float> w0[3], w1[3];
-      proj_mul16<S>(cr, ci, pr0, pi0, v, 0, PS::b0, w0);
-      proj_mul16<S>(cr, ci, pr1, pi1, v, 1, PS::b1, w1);
-      reconstruct<MU, FWD, INIT>(acc[i], w0, w1, sign);
+  for (int i = 0; i < G; ++i) {
+    if (i >= nr || !act[i]) continue;
+    cx<R> v[12];
+    load_spinor<S>(inb[i], vp, nb, v);
+    if (HAS_D) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) v[k] = d[k / 3] * v[k];
     }
-  } else {
-    cx<R> u[9];
-    load_link<S>(gauge, vp, MU, link_par, link_site, u);
-#pragma unroll
-    for (int i = 0; i < G; ++i) {
-      if (i >= nr || !act[i]) continue;
-      cx<R> v[12];
-      load_spinor<S>(inb[i], vp, nb, v);
-      if (HAS_D) {
-#pragma unroll
-        for (int k = 0; k < 12; ++k) v[k] = d[k / 3] * v[k];
-      }
-      cx<R> h0[3], h1[3], w0[3], w1[3];
-      project<MU, FWD>(v, h0, h1);
-      if (FWD) {
-        su3_mul(u, h0, w0);
-        su3_mul(u, h1, w1);
-      } else {
-        su3_dag_mul(u, h0, w0);
-        su3_dag_mul(u, h1, w1);
-      }
-      reconstruct<MU, FWD, INIT>(acc[i], w0, w1, sign);
+    cx<R> h0[3], h1[3], w0[3], w1[3];
+    project<MU, FWD>(v, h0, h1);
+    if (FWD) {
+      su3_mul(u, h0, w0);
+      su3_mul(u, h1, w1);
+    } else {
+      su3_dag_mul(u, h0, w0);
+      su3_dag_mul(u, h1, w1);
     }
+    reconstruct<MU, FWD, INIT>(acc[i], w0, w1, sign);
   }
 }
 
