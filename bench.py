@@ -33,9 +33,10 @@ WORKLOADS = {
     # lattice name -> TSM sizes
     "batched_24x24x24x48": dict(n_lp=1000, n_hp=50, p2max=4, noise="Z4"),
     "tsm_16x16x16x32": dict(n_lp=200, n_hp=10, p2max=4, noise="Z2"),
-    # not TSM steps of one lattice: see bench_uneven / bench_grad
+    # not TSM steps of one lattice: see bench_uneven / bench_grad / bench_sweep
     "uneven": None,
     "grad_16x16x16x32": None,
+    "dslash_sweep": None,
 }
 
 # serving-shaped mix of lattices: (dims, eps, LP sources); kappa 0.1615, mu 0.004
@@ -50,6 +51,62 @@ def _setup_lattice(dl, torch, synth, ctx, dims, seed, eps, kappa, mu):
     dl.dl_gauge_set(lat, torch.from_numpy(np.ascontiguousarray(U)).to("cuda"), 1)
     dl.dl_set_params(lat, kappa, mu)
     return lat, U
+
+
+def copy_gbs(torch, gib: int = 4, reps: int = 5) -> float:
+    """Achieved bandwidth of a plain device-to-device copy (read + write bytes / time)."""
+    x = torch.empty(gib << 28, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1)
+    del x, y
+    return 2.0 * (gib << 30) * reps / (ms * 1e-3) / 1e9
+
+
+def bench_sweep(a) -> int:
+    """Hopping-kernel bandwidth per storage precision and number of right-hand
+    sides on the 24^3x48 lattice: each configuration solves nsrc sources (LP
+    tiers and FP64 to rho = 1e-2, HP to 1e-8) with the kernel profiled; GB/s =
+    algorithmic bytes of the u_e = A^-1 H_eo p_o launches / their HIP-event
+    time.  One JSON line per configuration, then the plain-copy bandwidth."""
+    import torch
+
+    import paper_1401_6750_amd as dl
+    import synth
+
+    w = synth.WORKLOADS["batched_24x24x24x48"]
+    ctx = dl.dl_create(0, torch.cuda.current_stream().cuda_stream)
+    dl.dl_set_option(ctx, "inflight_mb", a.inflight_mb)
+    lat, _ = _setup_lattice(dl, torch, synth, ctx, w["dims"], w["gauge_seed"], w["eps"], w["kappa"], w["mu"])
+    tiers = [("bf16", dl.DL_TIER_LP_BF16, 1e-2, [1, 8, 64, 512]), ("fp16", dl.DL_TIER_LP_FP16, 1e-2, [1, 8, 64, 512]),
+             ("fp32", dl.DL_TIER_HP_FP32, 1e-8, [1, 8, 64]), ("fp64", dl.DL_TIER_FP64, 1e-2, [1, 8, 64])]
+    for name, tier, tol, ns in tiers:
+        for n in ns:
+            job = dl.make_job(lat, noise=dl.DL_NOISE_Z4, tier=tier, seed=w["source_seed"], nsrc=n, tol=tol,
+                              maxiter=2000)
+            dl.dl_solve_batch(ctx, job)               # tuning and warm-up
+            dl.dl_profile_read(ctx, tier)
+            dl.dl_set_option(ctx, "profile", 1)
+            dl.dl_solve_batch(ctx, job)
+            torch.cuda.synchronize()
+            dl.dl_set_option(ctx, "profile", 0)
+            launches, kms, kbytes, krhs = dl.dl_profile_read(ctx, tier)
+            blk = dl.dl_autotune(ctx, lat, tier, n)
+            print(json.dumps({"sweep": "dslash", "precision": name, "nsrc": n, "rhs_block": list(blk),
+                              "launches": int(launches), "avg_launch_us": round(kms * 1e3 / max(launches, 1), 1),
+                              "gbs": round(kbytes / (kms * 1e-3) / 1e9, 1) if kms > 0 else 0.0,
+                              "frac": round(kbytes / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if kms > 0 else 0.0}),
+                  flush=True)
+    print(json.dumps({"sweep": "copy", "gbs": round(copy_gbs(torch), 1)}), flush=True)
+    dl.dl_lattice_destroy(lat)
+    dl.dl_destroy(ctx)
+    return 0
 
 
 def bench_uneven(a) -> int:
@@ -121,15 +178,16 @@ def bench_grad(a) -> int:
 
     import paper_1401_6750_amd as dl
     import synth
-    from oracle import noise as onoise
-
     w = synth.WORKLOADS["tsm_16x16x16x32"]
     dims = w["dims"]
     ctx = dl.dl_create(0, torch.cuda.current_stream().cuda_stream)
     lat, _ = _setup_lattice(dl, torch, synth, ctx, dims, w["gauge_seed"], w["eps"], w["kappa"], w["mu"])
     nsrc, p2 = 64, 4
-    eta0 = torch.from_numpy(np.stack([onoise.source(dims, w["source_seed"], r, onoise.Z2)
-                                      for r in range(nsrc)])).to("cuda")
+    vol = dims[0] * dims[1] * dims[2] * dims[3]
+    eta0 = torch.zeros((nsrc, dims[3], dims[2], dims[1], dims[0], 4, 3), dtype=torch.complex128, device="cuda")
+    for r in range(nsrc):   # the library's own Z2 generator (the sources the forward pass would draw)
+        dl.dl_fill_noise(lat, dl.DL_NOISE_Z2, w["source_seed"], r, eta0[r])
+    assert eta0.numel() == nsrc * vol * 12
     np_ = len(dl.dl_momenta(dims, p2))
     rng = np.random.default_rng(0)
     gw = torch.from_numpy(rng.standard_normal((2, 5, 16, dims[3], np_))
@@ -208,6 +266,8 @@ def main() -> int:
         return bench_uneven(a)
     if a.workload == "grad_16x16x16x32":
         return bench_grad(a)
+    if a.workload == "dslash_sweep":
+        return bench_sweep(a)
     w = synth.WORKLOADS[a.workload]
     tw = WORKLOADS[a.workload]
     dims, kappa, mu = w["dims"], w["kappa"], w["mu"]
@@ -300,7 +360,8 @@ def main() -> int:
                 "kernel": "k_dslash<bf16s, 0> (u_e = A^-1 H_eo p_o, LP tier)",
                 "launches": int(launches), "avg_launch_us": round(kms * 1e3 / max(launches, 1), 2),
                 "alg_bytes_per_launch": round(kbytes / max(launches, 1)),
-                "avg_active_rhs": round(krhs / max(launches, 1), 1)}
+                "avg_active_rhs": round(krhs / max(launches, 1), 1),
+                "copy_gbs": round(copy_gbs(torch), 1)}
 
     # ---- per-tier breakdown and the plain FP64 comparator (untimed in value) --
     extra = {}

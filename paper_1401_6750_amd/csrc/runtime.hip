@@ -713,7 +713,30 @@ void run_batch(dl_ctx* ctx, int tier, const std::vector<SlotPlan>& plan, const s
         }
         continue;
       }
-      cg_iteration(b, P32, f);
+      if (ctx->profile) {
+        // time this iteration's hopping launch (u_e = A^-1 H_eo p_o) as the plain CG does
+        std::vector<int> act(b.nrhs);
+        b.to_host_int(b.cs.active, act.data());
+        b.sync();
+        hipEvent_t e0, e1;
+        HIPCHECK(hipEventCreate(&e0));
+        HIPCHECK(hipEventCreate(&e1));
+        cg_iteration(b, P32, f, e0, e1);
+        HIPCHECK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        double* pr = ctx->prof[P32];
+        int na = 0;
+        for (int g = 0; g < b.nrhs; ++g) na += act[g] != 0;
+        pr[0] += 1;
+        pr[1] += ms;
+        pr[2] += hop_launch_bytes(b, P32, act.data());
+        pr[3] += na;
+      } else {
+        cg_iteration(b, P32, f);
+      }
     }
     // fold the last FP32 correction; reconstruct in FP64
     launch_convert(P32, P64, b.slots(), b.nslots, b.u_rhs, x.p, xhi.p, 1, nullptr, st);
