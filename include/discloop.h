@@ -191,6 +191,16 @@ int dl_momenta(const int dims[4], int p2max, int* n_xyz, int cap, int* np_out);
 int dl_loops(dl_ctx* ctx, dl_accum* acc, int p2max, double* out, int out_on_device,
              int* np_out);
 
+/* The three TSM sets separately, without the division by their source counts:
+ * out[s] (s = DL_SET_LP, DL_SET_HP, DL_SET_LPC) is the sum over the set's
+ * sources of the loops that dl_loops normalises (same projection, Gamma
+ * rebuild and prefactors), layout complex128 [3][2][nops][16][T][Np].  A set
+ * without sources gives zeros.  With dl_accum_counts the TSM estimate is
+ * S_LP / N_LP + (S_HP - S_LPC) / N_HP; partial sums of disjoint source blocks
+ * add up, which is what base-2 storage of partial sums needs (Section 2.1.1,
+ * Fig. 2).  Errors as dl_loops. */
+int dl_loops_sets(dl_ctx* ctx, dl_accum* acc, int p2max, double* out, int out_on_device, int* np_out);
+
 /* Gradients of the loops of one job's sources with respect to the sources and
  * to mu, for a real loss F.  The loops are the plain estimator over the job's
  * nsrc sources (what dl_loops returns for an accumulator that holds only

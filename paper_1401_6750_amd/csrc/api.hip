@@ -300,6 +300,105 @@ int dl_solve_batch(dl_ctx* ctx, const dl_job* jobs, int njobs, dl_src_stats* sta
   });
 }
 
+// Projection, Gamma rebuild and prefactors of weighted combinations of the
+// accumulator's three sets: output k (complex128 [2][nops][16][T][Np], device)
+// is the loops of sum_s w[k][s] S_s.  Runs on the context stream.
+static int loops_device(dl_ctx* ctx, dl_accum* a, int p2max, const double (*w)[3], int nw, double* target) {
+  dl_lattice* L = a->lat;
+  auto moms = momentum_list(L->dims, p2max);
+  const int np = (int)moms.size();
+  const int X = L->dims[0], Y = L->dims[1], Z = L->dims[2], T = L->dims[3];
+  // tables of the separable projection: distinct kx, distinct (kx, ky)
+  std::vector<int> kxs, pair_ix, pj(np);
+  std::vector<std::array<int, 2>> pairs;
+  for (int p = 0; p < np; ++p) {
+    const int kx = moms[p][0], ky = moms[p][1];
+    int ix = (int)(std::find(kxs.begin(), kxs.end(), kx) - kxs.begin());
+    if (ix == (int)kxs.size()) kxs.push_back(kx);
+    const std::array<int, 2> pr{kx, ky};
+    int j = (int)(std::find(pairs.begin(), pairs.end(), pr) - pairs.begin());
+    if (j == (int)pairs.size()) {
+      pairs.push_back(pr);
+      pair_ix.push_back(ix);
+    }
+    pj[p] = j;
+  }
+  const int nkx = (int)kxs.size(), nkxy = (int)pairs.size();
+  auto phase = [](double n, int x, int ext, double* out) {
+    const double ang = -2.0 * M_PI * n * x / ext;
+    out[0] = std::cos(ang);
+    out[1] = std::sin(ang);
+  };
+  std::vector<double> tabs;   // px | py | pz | shift, complex
+  const size_t o_px = 0, o_py = o_px + 2ull * nkx * X, o_pz = o_py + 2ull * nkxy * Y,
+               o_sh = o_pz + 2ull * np * Z, n_tab = o_sh + 6ull * np;
+  tabs.resize(std::max<size_t>(n_tab, 2));
+  for (int k = 0; k < nkx; ++k)
+    for (int x = 0; x < X; ++x) phase(kxs[k], x, X, &tabs[o_px + 2 * ((size_t)k * X + x)]);
+  for (int k = 0; k < nkxy; ++k)
+    for (int y = 0; y < Y; ++y) phase(pairs[k][1], y, Y, &tabs[o_py + 2 * ((size_t)k * Y + y)]);
+  const int ext[3] = {X, Y, Z};
+  for (int p = 0; p < np; ++p) {
+    for (int z = 0; z < Z; ++z) phase(moms[p][2], z, Z, &tabs[o_pz + 2 * ((size_t)p * Z + z)]);
+    for (int nu = 0; nu < 3; ++nu) {
+      double* f = &tabs[o_sh + 2 * ((size_t)p * 3 + nu)];
+      phase(moms[p][nu], 1, ext[nu], f);
+      f[0] += 1.0;
+    }
+  }
+  std::vector<int> itab(pair_ix);
+  itab.insert(itab.end(), pj.begin(), pj.end());
+  DevBuf dtab(ctx, tabs.size() * sizeof(double)), ditab(ctx, std::max<size_t>(itab.size(), 1) * sizeof(int));
+  HIPCHECK(hipMemcpyAsync(dtab.p, tabs.data(), tabs.size() * sizeof(double), hipMemcpyHostToDevice, ctx->st));
+  if (!itab.empty())
+    HIPCHECK(hipMemcpyAsync(ditab.p, itab.data(), itab.size() * sizeof(int), hipMemcpyHostToDevice, ctx->st));
+  ProjTables tb{};
+  tb.np = np; tb.nkx = nkx; tb.nkxy = nkxy;
+  const double* dt = dtab.as<double>();
+  tb.px = dt + o_px; tb.py = dt + o_py; tb.pz = dt + o_pz; tb.shift = dt + o_sh;
+  tb.pair_ix = ditab.as<int>(); tb.pj = ditab.as<int>() + nkxy;
+  const int nops = (a->ops & DL_OPS_DERIV) ? 5 : 1;
+  const size_t per_out = (size_t)2 * 2 * nops * 16 * T * np;   // doubles
+  const size_t pbytes = std::max<size_t>(sizeof(double) * 2 * (size_t)a->nq * T * np, 16);
+  DevBuf proj(ctx, pbytes);
+  DevBuf r2(ctx, std::max<size_t>(sizeof(double) * 2 * (size_t)a->nq * T * Z * nkxy, 16));
+  for (int k = 0; k < nw; ++k) {
+    const double* sets[3];
+    for (int s = 0; s < 3; ++s) sets[s] = (w[k][s] != 0.0 && a->count[s] > 0) ? a->acc[s] : nullptr;
+    if (sets[0] || sets[1] || sets[2]) {
+      // derivative rows (q >= 48) hold link-centred sums
+      launch_project(sets, w[k], a->nq, 48, X, Y, Z, T, tb, r2.as<double>(), proj.as<double>(), ctx->st);
+    } else {
+      HIPCHECK(hipMemsetAsync(proj.p, 0, pbytes, ctx->st));
+    }
+    launch_loops_finalize(proj.as<double>(), nops, T, np, L->kappa, L->mu, target + k * per_out, ctx->st);
+  }
+  HIPCHECK(hipGetLastError());
+  return np;
+}
+
+static void loops_common(dl_ctx* ctx, dl_accum* a, int p2max, const double (*w)[3], int nw, double* out,
+                         int out_on_device, int* np_out) {
+  dl_lattice* L = a->lat;
+  const int np = (int)momentum_list(L->dims, p2max).size();
+  if (np_out) *np_out = np;
+  const int nops = (a->ops & DL_OPS_DERIV) ? 5 : 1;
+  const size_t obytes = sizeof(double) * 2 * 2 * nops * 16 * (size_t)L->dims[3] * np * nw;
+  stream_enter(ctx);
+  DevBuf dout;
+  double* target = out;
+  if (!out_on_device) {
+    dout = DevBuf(ctx, std::max<size_t>(obytes, 16));
+    target = dout.as<double>();
+  }
+  loops_device(ctx, a, p2max, w, nw, target);
+  if (!out_on_device) {
+    HIPCHECK(hipMemcpyAsync(out, target, obytes, hipMemcpyDeviceToHost, ctx->st));
+    HIPCHECK(hipStreamSynchronize(ctx->st));
+  }
+  stream_exit(ctx);
+}
+
 int dl_loops(dl_ctx* ctx, dl_accum* a, int p2max, double* out, int out_on_device, int* np_out) {
   return guarded([&] {
     require(ctx && a && out, "dl_loops: NULL argument");
@@ -309,91 +408,25 @@ int dl_loops(dl_ctx* ctx, dl_accum* a, int p2max, double* out, int out_on_device
     require(L->params_set, "dl_loops: kappa / mu not set");
     require(a->count[DL_SET_LPC] == 0 || a->count[DL_SET_LPC] == a->count[DL_SET_HP],
             "dl_loops: the LPC set must hold the same sources as the HP set");
-    auto moms = momentum_list(L->dims, p2max);
-    const int np = (int)moms.size();
-    if (np_out) *np_out = np;
-    const int X = L->dims[0], Y = L->dims[1], Z = L->dims[2], T = L->dims[3];
-    // tables of the separable projection: distinct kx, distinct (kx, ky)
-    std::vector<int> kxs, pair_ix, pj(np);
-    std::vector<std::array<int, 2>> pairs;
-    for (int p = 0; p < np; ++p) {
-      const int kx = moms[p][0], ky = moms[p][1];
-      int ix = (int)(std::find(kxs.begin(), kxs.end(), kx) - kxs.begin());
-      if (ix == (int)kxs.size()) kxs.push_back(kx);
-      const std::array<int, 2> pr{kx, ky};
-      int j = (int)(std::find(pairs.begin(), pairs.end(), pr) - pairs.begin());
-      if (j == (int)pairs.size()) {
-        pairs.push_back(pr);
-        pair_ix.push_back(ix);
-      }
-      pj[p] = j;
-    }
-    const int nkx = (int)kxs.size(), nkxy = (int)pairs.size();
-    auto phase = [](double n, int x, int ext, double* out) {
-      const double ang = -2.0 * M_PI * n * x / ext;
-      out[0] = std::cos(ang);
-      out[1] = std::sin(ang);
-    };
-    std::vector<double> tabs;   // px | py | pz | shift, complex
-    const size_t o_px = 0, o_py = o_px + 2ull * nkx * X, o_pz = o_py + 2ull * nkxy * Y,
-                 o_sh = o_pz + 2ull * np * Z, n_tab = o_sh + 6ull * np;
-    tabs.resize(std::max<size_t>(n_tab, 2));
-    for (int k = 0; k < nkx; ++k)
-      for (int x = 0; x < X; ++x) phase(kxs[k], x, X, &tabs[o_px + 2 * ((size_t)k * X + x)]);
-    for (int k = 0; k < nkxy; ++k)
-      for (int y = 0; y < Y; ++y) phase(pairs[k][1], y, Y, &tabs[o_py + 2 * ((size_t)k * Y + y)]);
-    const int ext[3] = {X, Y, Z};
-    for (int p = 0; p < np; ++p) {
-      for (int z = 0; z < Z; ++z) phase(moms[p][2], z, Z, &tabs[o_pz + 2 * ((size_t)p * Z + z)]);
-      for (int nu = 0; nu < 3; ++nu) {
-        double* f = &tabs[o_sh + 2 * ((size_t)p * 3 + nu)];
-        phase(moms[p][nu], 1, ext[nu], f);
-        f[0] += 1.0;
-      }
-    }
-    std::vector<int> itab(pair_ix);
-    itab.insert(itab.end(), pj.begin(), pj.end());
-    stream_enter(ctx);
-    DevBuf dtab(ctx, tabs.size() * sizeof(double)), ditab(ctx, std::max<size_t>(itab.size(), 1) * sizeof(int));
-    HIPCHECK(hipMemcpyAsync(dtab.p, tabs.data(), tabs.size() * sizeof(double), hipMemcpyHostToDevice, ctx->st));
-    if (!itab.empty())
-      HIPCHECK(hipMemcpyAsync(ditab.p, itab.data(), itab.size() * sizeof(int), hipMemcpyHostToDevice, ctx->st));
-    ProjTables tb{};
-    tb.np = np; tb.nkx = nkx; tb.nkxy = nkxy;
-    const double* dt = dtab.as<double>();
-    tb.px = dt + o_px; tb.py = dt + o_py; tb.pz = dt + o_pz; tb.shift = dt + o_sh;
-    tb.pair_ix = ditab.as<int>(); tb.pj = ditab.as<int>() + nkxy;
     // TSM combination L = S_LP / N_LP + (S_HP - S_LPC) / N_HP, taken on the
     // accumulators so one projection serves all three sets
     const double w_lp = a->count[DL_SET_LP] > 0 ? 1.0 / (double)a->count[DL_SET_LP] : 0.0;
     const double w_hp = a->count[DL_SET_HP] > 0 ? 1.0 / (double)a->count[DL_SET_HP] : 0.0;
-    const double* sets[3] = {w_lp != 0.0 ? a->acc[DL_SET_LP] : nullptr, w_hp != 0.0 ? a->acc[DL_SET_HP] : nullptr,
-                             (w_hp != 0.0 && a->count[DL_SET_LPC] > 0) ? a->acc[DL_SET_LPC] : nullptr};
-    const double wts[3] = {w_lp, w_hp, -w_hp};
-    const size_t pbytes = std::max<size_t>(sizeof(double) * 2 * (size_t)a->nq * T * np, 16);
-    DevBuf proj(ctx, pbytes);
-    if (sets[0] || sets[1] || sets[2]) {
-      DevBuf r2(ctx, std::max<size_t>(sizeof(double) * 2 * (size_t)a->nq * T * Z * nkxy, 16));
-      // derivative rows (q >= 48) hold link-centred sums
-      launch_project(sets, wts, a->nq, 48, X, Y, Z, T, tb, r2.as<double>(), proj.as<double>(), ctx->st);
-    } else {
-      HIPCHECK(hipMemsetAsync(proj.p, 0, pbytes, ctx->st));
-    }
-    const int nops = (a->ops & DL_OPS_DERIV) ? 5 : 1;
-    const size_t obytes = sizeof(double) * 2 * 2 * nops * 16 * (size_t)T * np;
-    DevBuf dout;
-    double* target = out;
-    if (!out_on_device) {
-      dout = DevBuf(ctx, std::max<size_t>(obytes, 16));
-      target = dout.as<double>();
-    }
-    launch_loops_finalize(proj.as<double>(), nops, T, np, L->kappa, L->mu, target, ctx->st);
-    HIPCHECK(hipGetLastError());
-    if (!out_on_device) {
-      HIPCHECK(hipMemcpyAsync(out, target, obytes, hipMemcpyDeviceToHost, ctx->st));
-      HIPCHECK(hipStreamSynchronize(ctx->st));
-    }
-    stream_exit(ctx);
+    const double w[1][3] = {{w_lp, w_hp, -w_hp}};
+    loops_common(ctx, a, p2max, w, 1, out, out_on_device, np_out);
+    return 0;
+  });
+}
+
+int dl_loops_sets(dl_ctx* ctx, dl_accum* a, int p2max, double* out, int out_on_device, int* np_out) {
+  return guarded([&] {
+    require(ctx && a && out, "dl_loops_sets: NULL argument");
+    require(p2max >= 0, "dl_loops_sets: p2max must be >= 0");
+    dl_lattice* L = a->lat;
+    require(L->ctx == ctx, "dl_loops_sets: accumulator of another context");
+    require(L->params_set, "dl_loops_sets: kappa / mu not set");
+    const double w[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
+    loops_common(ctx, a, p2max, w, 3, out, out_on_device, np_out);
     return 0;
   });
 }

@@ -7,6 +7,7 @@
 // right-hand side carries its own CG scalars and retires on its own
 // convergence, after which its units exit at once.
 #include <algorithm>
+#include <cctype>
 #include <array>
 #include <cmath>
 #include <complex>
@@ -923,14 +924,27 @@ static void tune_load(dl_ctx* ctx) {
   ctx->tune_path = tune_file();
   FILE* f = fopen(ctx->tune_path.c_str(), "r");
   if (!f) return;
-  char key[128];
-  int v;
-  // format: {"key": value, ...} one entry per line
-  char line[256];
-  while (fgets(line, sizeof(line), f)) {
-    if (sscanf(line, " \"%127[^\"]\" : %d", key, &v) == 2 && v >= 1) ctx->tune[key] = v;
-  }
+  // a flat JSON object {"key": value, ...}: every quoted key followed by ':'
+  // and a positive integer is taken, whatever the line breaks
+  std::string text;
+  char buf[4096];
+  size_t got;
+  while ((got = fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
   fclose(f);
+  size_t pos = 0;
+  while ((pos = text.find('"', pos)) != std::string::npos) {
+    const size_t end = text.find('"', pos + 1);
+    if (end == std::string::npos) break;
+    const std::string key = text.substr(pos + 1, end - pos - 1);
+    size_t q = end + 1;
+    while (q < text.size() && isspace((unsigned char)text[q])) ++q;
+    if (q < text.size() && text[q] == ':') {
+      char* stop = nullptr;
+      const long v = strtol(text.c_str() + q + 1, &stop, 10);
+      if (stop != text.c_str() + q + 1 && v >= 1 && v < (1 << 30)) ctx->tune[key] = (int)v;
+    }
+    pos = end + 1;
+  }
 }
 
 static void tune_save(dl_ctx* ctx) {

@@ -8,6 +8,8 @@ of their storage roundoff u (fp32 2^-24, fp16 2^-11, bf16 2^-8):
 """
 import sys
 
+import os
+
 import numpy as np
 import pytest
 
@@ -212,6 +214,55 @@ def test_tsm_combination_matches_oracle(ctx, plain):
     want = loops.tsm_combine(s_lp, n_lp, s_hp, s_lpc, n_hp, lat.kappa, lat.mu)
     assert rel(out, want) < 1e-9
     dl.dl_accum_destroy(acc)
+
+
+def test_loop_sets_and_base2_storage(ctx, plain, tmp_path):
+    """dl_loops_sets: the per-set sums recombine to dl_loops and match the oracle's summed
+    loops; base-2 storage (Fig. 2) rebuilds the estimate of any count from level files and
+    resumes a missing level with identical bits."""
+    from paper_1401_6750_amd import base2
+    lat, _ = plain
+    seed, p2 = 99, 3
+    acc = dl.dl_accum_create(lat.h, dl.DL_OPS_LOCAL | dl.DL_OPS_DERIV)
+    jobs = [
+        dl.make_job(lat.h, noise=dl.DL_NOISE_Z4, tier=dl.DL_TIER_FP64, seed=seed, first_src=0, nsrc=6, tol=1e-2,
+                    maxiter=200, accum=acc, accum_set=dl.DL_SET_LP),
+        dl.make_job(lat.h, noise=dl.DL_NOISE_Z4, tier=dl.DL_TIER_FP64, seed=seed, first_src=6, nsrc=3,
+                    tol=1e-10, maxiter=500, accum=acc, accum_set=dl.DL_SET_HP),
+        dl.make_job(lat.h, noise=dl.DL_NOISE_Z4, tier=dl.DL_TIER_FP64, seed=seed, first_src=6, nsrc=3,
+                    tol=1e-2, maxiter=200, accum=acc, accum_set=dl.DL_SET_LPC),
+    ]
+    dl.dl_solve_batch(ctx, jobs)
+    npm = len(loops.momenta(p2, lat.dims))
+    T = lat.dims[3]
+    est = np.zeros((2, 5, 16, T, npm), dtype=np.complex128)
+    sets = np.zeros((3, 2, 5, 16, T, npm), dtype=np.complex128)
+    dl.dl_loops(ctx, acc, p2, est, 0)
+    dl.dl_loops_sets(ctx, acc, p2, sets, 0)
+    assert rel(sets[0] / 6 + (sets[1] - sets[2]) / 3, est) < 1e-12
+    want_hp = loops.apply_prefactors(sum(
+        loops.source_loops(lat.U, solver.cgnr_eo(lat.U, noise.source(lat.dims, seed, r, noise.Z4), lat.kappa,
+                                                 lat.mu, lat.bc, lat.dims, 1e-10)[0], lat.kappa, lat.bc, p2, lat.dims)
+        for r in range(6, 9)), lat.kappa, lat.mu)
+    assert rel(sets[1], want_hp) < 1e-9
+    dl.dl_accum_destroy(acc)
+
+    # base-2 storage of a Z2 stream: 3 levels = 7 sources; n = 5 uses levels 0 and 2
+    meta = {"dims": list(lat.dims), "seed": 5, "tier": "fp64", "tol": 1e-10, "p2max": p2}
+    st = base2.Base2Store(str(tmp_path / "b2"), meta)
+    kw = dict(tier=dl.DL_TIER_FP64, noise=dl.DL_NOISE_Z2, seed=5, tol=1e-10, maxiter=500, p2max=p2,
+              ops=dl.DL_OPS_LOCAL | dl.DL_OPS_DERIV)
+    assert base2.solve_base2(ctx, lat.h, lat.dims, st, 3, **kw) == [0, 1, 2]
+    srcs = [0, 3, 4, 5, 6]
+    per = [loops.source_loops(lat.U, solver.cgnr_eo(lat.U, noise.source(lat.dims, 5, r, noise.Z2), lat.kappa,
+                                                    lat.mu, lat.bc, lat.dims, 1e-10)[0], lat.kappa, lat.bc, p2,
+                              lat.dims) for r in srcs]
+    assert rel(st.estimate(5), loops.estimate(np.stack(per), lat.kappa, lat.mu)) < 1e-9
+    lvl1 = st.load(1)
+    os.remove(os.path.join(st.dir, "level01.npy"))
+    assert st.resume_level() == 1
+    assert base2.solve_base2(ctx, lat.h, lat.dims, base2.Base2Store(st.dir, meta), 3, **kw) == [1]
+    assert np.array_equal(st.load(1), lvl1)
 
 
 # ---------------------------------------------------------------------------
