@@ -86,6 +86,17 @@ extern "C" {
  * one-derivative insertions (Section 2.1.1: 160 with both flavours). */
 #define DL_OPS_LOCAL 1
 #define DL_OPS_DERIV 2
+/* Hopping parameter expansion of the loops without tau_3 (one of the variance
+ * reductions of the interfaces, Section 2.4), order n = 1..4, or'ed into the
+ * ops of dl_accum_create.  With B = A^-1, A = 1 + 2 i kappa mu gamma_5 and
+ * M = A - kappa H, M^-1 = sum_{k<n} (kappa B H)^k B + (kappa B H)^n M^-1: the
+ * first sum is added exactly (its elements used here do not depend on the gauge
+ * field) and only the remainder is estimated, from phi = (kappa B H)^n s and the
+ * source eta, the d flavour by gamma_5-hermiticity from the same sample.
+ * Derivative insertions use order min(n, 3).  Requires every lattice extent
+ * >= 4.  The loops with tau_3 keep the one-end trick. */
+#define DL_OPS_HPE(n) ((n) << 4)
+#define DL_OPS_HPE_ORDER(ops) (((ops) >> 4) & 7)
 
 /* per-source status in dl_src_stats.status */
 #define DL_SRC_CONVERGED 0
@@ -168,7 +179,11 @@ int dl_set_params(dl_lattice* lat, double kappa, double mu);
  * Returns DL_NOT_CONVERGED if any source missed its tolerance. */
 int dl_solve_batch(dl_ctx* ctx, const dl_job* jobs, int njobs, dl_src_stats* stats);
 
-/* Per-site FP64 loop accumulators of one lattice (three TSM sets). */
+/* Per-site FP64 loop accumulators of one lattice (three TSM sets).  ops:
+ * DL_OPS_LOCAL or DL_OPS_LOCAL | DL_OPS_DERIV, optionally | DL_OPS_HPE(n).
+ * The jobs of one dl_solve_batch call that accumulate into HPE accumulators
+ * must all use the same order.  DL_EINVAL for other values, or for HPE on a
+ * lattice with an extent below 4. */
 int dl_accum_create(dl_lattice* lat, int ops, dl_accum** out);
 int dl_accum_reset(dl_accum* acc);
 int dl_accum_destroy(dl_accum* acc);
@@ -187,7 +202,8 @@ int dl_momenta(const int dims[4], int p2max, int* n_xyz, int cap, int* np_out);
  * one-end-trick prefactors.  out: complex128 [2][nops][16][T][Np], flavour 0
  * with tau_3, 1 without; op 0 local, 1..4 derivative along x, y, z, t
  * (nops = 1 or 5 by the accumulator's ops); host (out_on_device = 0) or
- * device pointer.  *np_out receives Np. */
+ * device pointer.  *np_out receives Np.  With DL_OPS_HPE the loops without
+ * tau_3 are the expansion's estimate: exact part plus estimated remainder. */
 int dl_loops(dl_ctx* ctx, dl_accum* acc, int p2max, double* out, int out_on_device,
              int* np_out);
 
@@ -213,7 +229,8 @@ int dl_loops_sets(dl_ctx* ctx, dl_accum* acc, int p2max, double* out, int out_on
  *   grad_mu     host double (optional): dF/dmu.
  * If job->sol_out is set it must hold the solutions of the forward call
  * (checkpoint) and is read; otherwise they are recomputed.  One adjoint solve
- * per source, M^dag = gamma_5 M(-mu) gamma_5, at job->tier and job->tol. */
+ * per source, M^dag = gamma_5 M(-mu) gamma_5, at job->tier and job->tol.
+ * DL_EINVAL if job->accum uses DL_OPS_HPE (not differentiated). */
 int dl_loops_backward(dl_ctx* ctx, const dl_job* job, int p2max, const double* grad_loops,
                       double* grad_eta, double* grad_mu);
 

@@ -22,6 +22,17 @@ DL_NOISE_Z2, DL_NOISE_Z4, DL_NOISE_USER = 0, 1, 2
 DL_TIER_FP64, DL_TIER_LP_BF16, DL_TIER_LP_FP16, DL_TIER_HP_FP32 = 0, 1, 2, 3
 DL_SET_LP, DL_SET_HP, DL_SET_LPC = 0, 1, 2
 DL_OPS_LOCAL, DL_OPS_DERIV = 1, 2
+
+
+def DL_OPS_HPE(n: int) -> int:
+    """Hopping parameter expansion of order n (1..4) for the loops without tau_3."""
+    return n << 4
+
+
+def DL_OPS_HPE_ORDER(ops: int) -> int:
+    return (ops >> 4) & 7
+
+
 DL_SRC_CONVERGED, DL_SRC_MAXITER, DL_SRC_BREAKDOWN = 0, 1, 2
 DL_OP_M, DL_OP_MDAG, DL_OP_MHAT, DL_OP_MHAT_DAG, DL_OP_HOP = 0, 1, 2, 3, 4
 

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -166,7 +167,13 @@ int dl_set_params(dl_lattice* lat, double kappa, double mu) {
 int dl_accum_create(dl_lattice* lat, int ops, dl_accum** out) {
   return guarded([&] {
     require(lat && out, "dl_accum_create: NULL argument");
-    require(ops == DL_OPS_LOCAL || ops == (DL_OPS_LOCAL | DL_OPS_DERIV), "dl_accum_create: ops must be LOCAL or LOCAL|DERIV");
+    const int base = ops & ~DL_OPS_HPE(7), hpe = DL_OPS_HPE_ORDER(ops);
+    require(base == DL_OPS_LOCAL || base == (DL_OPS_LOCAL | DL_OPS_DERIV),
+            "dl_accum_create: ops must be LOCAL or LOCAL|DERIV, optionally with DL_OPS_HPE(n)");
+    require(hpe <= 4, "dl_accum_create: HPE order must be 1..4");
+    if (hpe)
+      for (int d = 0; d < 4; ++d)
+        require(lat->dims[d] >= 4, "dl_accum_create: the hopping parameter expansion needs every extent >= 4");
     HIPCHECK(hipSetDevice(lat->ctx->device));
     auto* a = new dl_accum();
     a->lat = lat;
@@ -280,6 +287,15 @@ int dl_solve_batch(dl_ctx* ctx, const dl_job* jobs, int njobs, dl_src_stats* sta
       }
       first_stat[j + 1] = first_stat[j] + q.nsrc;
     }
+    int hpe_order = 0;
+    for (const dl_job& q : J) {
+      if (!q.accum || q.nsrc == 0) continue;
+      const int o = DL_OPS_HPE_ORDER(q.accum->ops);
+      if (!o) continue;
+      require(hpe_order == 0 || hpe_order == o,
+              "dl_solve_batch: jobs of one call must use one hopping parameter expansion order");
+      hpe_order = o;
+    }
     for (int j = 0; j < njobs; ++j) {
       const dl_job& q = J[j];
       if (q.guess_from == 0) continue;
@@ -303,6 +319,66 @@ int dl_solve_batch(dl_ctx* ctx, const dl_job* jobs, int njobs, dl_src_stats* sta
 // Projection, Gamma rebuild and prefactors of weighted combinations of the
 // accumulator's three sets: output k (complex128 [2][nops][16][T][Np], device)
 // is the loops of sum_s w[k][s] S_s.  Runs on the context stream.
+// Exact part of the hopping parameter expansion per site, before the
+// prefactor: half the sum over both flavours (mu_f = +mu, -mu, B = A(mu_f)^-1)
+// of the colour-traced orders k < n of M^-1 = sum_k (kappa B H)^k B, with the
+// insertion's Gamma.  Extents >= 4 leave, on the diagonal, B (k = 0) and the
+// hops forth and back, kappa^2 B Q B with Q = sum_nu [(1 - g_nu) B (1 + g_nu) +
+// (1 + g_nu) B (1 - g_nu)] (k = 2, used for n >= 3); odd k vanish there.  For
+// the derivative insertions (orders k < min(n, 3)) only the single hop k = 1
+// survives: its four terms combine to kappa B g_nu B (used for n >= 2).
+// Colour traces of the retraced links give 3.  out [nops][16].
+static std::vector<std::complex<double>> hpe_exact_table(double kappa, double mu, int n, int nops) {
+  using C = std::complex<double>;
+  C G[16][4][4];
+  gamma_basis(G);
+  std::vector<C> out((size_t)nops * 16, C(0, 0));
+  const double g5[4] = {1, 1, -1, -1};
+  auto trace_with = [&](int m, const C (&S)[4][4]) {
+    C t(0, 0);
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) t += G[m][a][b] * S[b][a];
+    return t;
+  };
+  for (const double muf : {mu, -mu}) {
+    C B[4];
+    for (int s = 0; s < 4; ++s) B[s] = 1.0 / C(1.0, 2.0 * kappa * muf * g5[s]);
+    // local: S = B + kappa^2 B Q B
+    C S[4][4] = {};
+    for (int a = 0; a < 4; ++a) S[a][a] = B[a];
+    if (n >= 3) {
+      C Q[4][4] = {};
+      for (int nu = 0; nu < 4; ++nu) {
+        const C (&g)[4][4] = G[1 << nu];
+        for (const double sg : {1.0, -1.0}) {
+          // (1 - sg g) B (1 + sg g)
+          C L[4][4], R[4][4];
+          for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) {
+              L[a][b] = (a == b ? 1.0 : 0.0) - sg * g[a][b];
+              R[a][b] = (a == b ? 1.0 : 0.0) + sg * g[a][b];
+            }
+          for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b)
+              for (int c = 0; c < 4; ++c) Q[a][b] += L[a][c] * B[c] * R[c][b];
+        }
+      }
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) S[a][b] += kappa * kappa * B[a] * Q[a][b] * B[b];
+    }
+    for (int m = 0; m < 16; ++m) out[m] += 1.5 * trace_with(m, S);
+    if (nops > 1 && n >= 2) {
+      for (int nu = 0; nu < 4; ++nu) {
+        C D[4][4];
+        for (int a = 0; a < 4; ++a)
+          for (int b = 0; b < 4; ++b) D[a][b] = kappa * B[a] * G[1 << nu][a][b] * B[b];
+        for (int m = 0; m < 16; ++m) out[(size_t)(1 + nu) * 16 + m] += 1.5 * trace_with(m, D);
+      }
+    }
+  }
+  return out;
+}
+
 static int loops_device(dl_ctx* ctx, dl_accum* a, int p2max, const double (*w)[3], int nw, double* target) {
   dl_lattice* L = a->lat;
   auto moms = momentum_list(L->dims, p2max);
@@ -362,6 +438,27 @@ static int loops_device(dl_ctx* ctx, dl_accum* a, int p2max, const double (*w)[3
   const size_t pbytes = std::max<size_t>(sizeof(double) * 2 * (size_t)a->nq * T * np, 16);
   DevBuf proj(ctx, pbytes);
   DevBuf r2(ctx, std::max<size_t>(sizeof(double) * 2 * (size_t)a->nq * T * Z * nkxy, 16));
+  // exact part of the hopping parameter expansion: per output, the spatial
+  // volume (momentum 0) times the weighted source count of the sets used
+  const int hpe = DL_OPS_HPE_ORDER(a->ops);
+  DevBuf dex;
+  if (hpe) {
+    const auto ex = hpe_exact_table(L->kappa, L->mu, hpe, nops);
+    std::vector<double> h((size_t)nw * nops * 16 * 2);
+    for (int k = 0; k < nw; ++k) {
+      double wsum = 0.0;
+      for (int s = 0; s < 3; ++s)
+        if (w[k][s] != 0.0 && a->count[s] > 0) wsum += w[k][s] * (double)a->count[s];
+      const double f = wsum * (double)X * Y * Z;
+      for (int i = 0; i < nops * 16; ++i) {
+        h[((size_t)k * nops * 16 + i) * 2] = f * ex[i].real();
+        h[((size_t)k * nops * 16 + i) * 2 + 1] = f * ex[i].imag();
+      }
+    }
+    dex = DevBuf(ctx, h.size() * sizeof(double));
+    HIPCHECK(hipMemcpyAsync(dex.p, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, ctx->st));
+    HIPCHECK(hipStreamSynchronize(ctx->st));   // h ends with this scope
+  }
   for (int k = 0; k < nw; ++k) {
     const double* sets[3];
     for (int s = 0; s < 3; ++s) sets[s] = (w[k][s] != 0.0 && a->count[s] > 0) ? a->acc[s] : nullptr;
@@ -371,7 +468,8 @@ static int loops_device(dl_ctx* ctx, dl_accum* a, int p2max, const double (*w)[3
     } else {
       HIPCHECK(hipMemsetAsync(proj.p, 0, pbytes, ctx->st));
     }
-    launch_loops_finalize(proj.as<double>(), nops, T, np, L->kappa, L->mu, target + k * per_out, ctx->st);
+    const double* exk = hpe ? dex.as<double>() + (size_t)k * nops * 16 * 2 : nullptr;
+    launch_loops_finalize(proj.as<double>(), nops, T, np, L->kappa, L->mu, exk, target + k * per_out, ctx->st);
   }
   HIPCHECK(hipGetLastError());
   return np;
@@ -525,6 +623,8 @@ int dl_loops_backward(dl_ctx* ctx, const dl_job* job, int p2max, const double* g
                       double* grad_mu) {
   return guarded([&] {
     require(ctx && job && grad_loops, "dl_loops_backward: NULL argument");
+    require(!job->accum || DL_OPS_HPE_ORDER(job->accum->ops) == 0,
+            "dl_loops_backward: loops with the hopping parameter expansion are not differentiated");
     loops_backward(ctx, *job, p2max, grad_loops, grad_eta, grad_mu);
     return 0;
   });

@@ -13,6 +13,15 @@
 // the tau_3 structure keeps 16 reals and the other 32 reals per operator; the
 // gamma_5 of the tau_3 structure is applied when the loops are assembled.
 //
+// Hopping parameter expansion (HPE variants): the structure without tau_3
+// takes the pair (xi = eta, phi = (kappa B H)^n s), whose outer product
+// estimates the remainder R_n of the u flavour; the d flavour's remainder is
+// gamma_5 R_n^dag gamma_5, so the flavour sum of a local insertion is
+// C -> (C + g5 C^dag g5) / 2 and of a derivative insertion E -> (E - g5 E^dag g5) / 2
+// (the Hermitian conjugate moves the derivative's forward hop to the other
+// side, which flips its sign).  The map is linear, so it is applied to the
+// register block sums when they are flushed.
+//
 // Work split: one wavefront = 64 sites of one parity (and, for the derivative,
 // one direction nu); a workgroup holds the four directions of one tile so the
 // site's own spinors are fetched once into L1.  Each lane runs over the
@@ -53,11 +62,29 @@ __device__ constexpr int up_b(int k) { return k < 3 ? k + 1 : (k < 5 ? k - 1 : 3
 // DERIV: the derivative sums are kept without their constant factors in the
 // source loop (1/2 on the s-s diagonal, 1/4 elsewhere, powers of two, so the
 // scaling is exact) and scaled here.
-template <bool DERIV, class A>
+template <bool DERIV, bool HPE, class A>
 __device__ inline void flush(double* acc, long long V, int lane, A (&a)[48]) {
   // keep the 48 addresses from being computed once and held across the
   // source loop (that alone would take 96 registers)
   asm volatile("" : "+v"(lane));
+  if constexpr (HPE) {
+    // xi-s block -> (C + sg g5 C^dag g5) / 2, sg = +1 local, -1 derivative:
+    // entry (i, j) takes sg g5_i g5_j conj(C_ji)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = i; j < 4; ++j) {
+        const int qij = 16 + 2 * (4 * i + j), qji = 16 + 2 * (4 * j + i);
+        const A gg = (((i < 2) == (j < 2)) == !DERIV) ? (A)1 : (A)-1;
+        const A re_ij = a[qij], im_ij = a[qij + 1], re_ji = a[qji], im_ji = a[qji + 1];
+        a[qij] = (A)0.5 * (re_ij + gg * re_ji);
+        a[qij + 1] = (A)0.5 * (im_ij - gg * im_ji);
+        if (j != i) {
+          a[qji] = (A)0.5 * (re_ji + gg * re_ij);
+          a[qji + 1] = (A)0.5 * (im_ji - gg * im_ij);
+        }
+      }
+  }
 #pragma unroll
   for (int q = 0; q < 48; ++q) {
     double* p = acc + q * V;
@@ -67,10 +94,10 @@ __device__ inline void flush(double* acc, long long V, int lane, A (&a)[48]) {
   }
 }
 
-template <class S>
+template <class S, bool HPE>
 __global__ __launch_bounds__(256) void k_contract_local(const SlotDesc* slots, int nslots, int total_units,
                                                         const void* s_e, const void* s_o, const void* xi_e,
-                                                        const void* xi_o) {
+                                                        const void* xi_o, const void* phi_e, const void* phi_o) {
   using R = typename Traits<S>::R;
   using A = typename AccT<S>::A;
   const int u = wave_unit();
@@ -87,6 +114,7 @@ __global__ __launch_bounds__(256) void k_contract_local(const SlotDesc* slots, i
   const int lane_off = par * (int)vp + s;
   const void* sf = par ? s_o : s_e;
   const void* xf = par ? xi_o : xi_e;
+  const void* pf = par ? phi_o : phi_e;
   A a[48];
 #pragma unroll
   for (int q = 0; q < 48; ++q) a[q] = (A)0;
@@ -112,6 +140,7 @@ __global__ __launch_bounds__(256) void k_contract_local(const SlotDesc* slots, i
       a[4 + 2 * k] += (A)t.re;
       a[5 + 2 * k] += (A)t.im;
     }
+    if constexpr (HPE) load_spinor<S>(field_at<S>(pf, off), vp, s, sv);   // sv = phi from here on
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -123,11 +152,11 @@ __global__ __launch_bounds__(256) void k_contract_local(const SlotDesc* slots, i
         a[17 + 2 * (4 * i + j)] += (A)t.im;
       }
     if (++inblk == AccT<S>::KB) {
-      flush<false>(acc, V, lane_off, a);
+      flush<false, HPE>(acc, V, lane_off, a);
       inblk = 0;
     }
   }
-  if (inblk) flush<false>(acc, V, lane_off, a);
+  if (inblk) flush<false, HPE>(acc, V, lane_off, a);
 }
 
 // Forward transport of one rhs field along nu: out = M psi(x+nu), M = b U_nu(x)
@@ -166,11 +195,12 @@ __device__ inline void transport_fwd(const void* f_other, long vp, int sp, const
 // (the backward half of D at x+nu reproduces the forward half at x).  So
 // each (site, nu) needs two transports instead of four, and the projection
 // adds F(x - nu) (a momentum phase for spatial nu, the previous time slice
-// for nu = t).  The s-s block (xi -> s) stays anti-Hermitian.
-template <class S>
+// for nu = t).  The s-s block (xi -> s) stays anti-Hermitian.  HPE: the
+// xi-s block pairs xi = eta with phi instead of s, one more transport (T_phi).
+template <class S, bool HPE>
 __global__ __launch_bounds__(256) void k_contract_deriv(const SlotDesc* slots, int nslots, int total_units,
                                                         const void* s_e, const void* s_o, const void* xi_e,
-                                                        const void* xi_o) {
+                                                        const void* xi_o, const void* phi_e, const void* phi_o) {
   using R = typename Traits<S>::R;
   using A = typename AccT<S>::A;
   const int u = wave_unit();
@@ -206,6 +236,8 @@ __global__ __launch_bounds__(256) void k_contract_deriv(const SlotDesc* slots, i
   const void* s_other = par ? s_e : s_o;
   const void* x_here = par ? xi_o : xi_e;
   const void* x_other = par ? xi_e : xi_o;
+  const void* f_here = par ? phi_o : phi_e;
+  const void* f_other = par ? phi_e : phi_o;
   const long long V = 2ll * vp;
   double* acc = sd.acc + (long long)(48 + 48 * nu) * V;
   const int lane_off = par * (int)vp + s;
@@ -242,10 +274,11 @@ __global__ __launch_bounds__(256) void k_contract_deriv(const SlotDesc* slots, i
       a[4 + 2 * k6] += (A)(t1.re - t2.re);
       a[5 + 2 * k6] += (A)(t1.im - t2.im);
     }
-    // xi-s block, first half: 1/4 conj(xi_a) T_s,b
+    // xi-s block, first half: 1/4 conj(xi_a) T_phi,b (phi = s unless HPE)
     {
       cx<R> xv[12];
       load_spinor<S>(field_at<S>(x_here, off), vp, s, xv);
+      if constexpr (HPE) transport_fwd<S>(field_at<S>(f_other, off), vp, sp, up, cr, ci, t);   // t = T_phi
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -257,7 +290,8 @@ __global__ __launch_bounds__(256) void k_contract_deriv(const SlotDesc* slots, i
           a[17 + 2 * (4 * i + j)] += (A)w.im;
         }
     }
-    // second half: -1/4 conj(T_xi,a) s_b
+    // second half: -1/4 conj(T_xi,a) phi_b
+    if constexpr (HPE) load_spinor<S>(field_at<S>(f_here, off), vp, s, sv);   // sv = phi
     transport_fwd<S>(field_at<S>(x_other, off), vp, sp, up, cr, ci, t);   // t = T_xi
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -270,34 +304,48 @@ __global__ __launch_bounds__(256) void k_contract_deriv(const SlotDesc* slots, i
         a[17 + 2 * (4 * i + j)] -= (A)w.im;
       }
     if (++inblk == AccT<S>::KB) {
-      flush<true>(acc, V, lane_off, a);
+      flush<true, HPE>(acc, V, lane_off, a);
       inblk = 0;
     }
   }
-  if (inblk) flush<true>(acc, V, lane_off, a);
+  if (inblk) flush<true, HPE>(acc, V, lane_off, a);
 }
 
-#define DISPATCH_PREC(prec, KERNEL, ...)                                                     \
+#define DISPATCH_PREC(prec, H, KERNEL, ...)                                                  \
   switch (prec) {                                                                            \
-    case P64: hipLaunchKernelGGL((KERNEL<double>), __VA_ARGS__); break;                      \
-    case P32: hipLaunchKernelGGL((KERNEL<float>), __VA_ARGS__); break;                       \
-    case PB16: hipLaunchKernelGGL((KERNEL<bf16s>), __VA_ARGS__); break;                      \
-    case PH16: hipLaunchKernelGGL((KERNEL<f16s>), __VA_ARGS__); break;                       \
+    case P64: hipLaunchKernelGGL((KERNEL<double, H>), __VA_ARGS__); break;                   \
+    case P32: hipLaunchKernelGGL((KERNEL<float, H>), __VA_ARGS__); break;                    \
+    case PB16: hipLaunchKernelGGL((KERNEL<bf16s, H>), __VA_ARGS__); break;                   \
+    case PH16: hipLaunchKernelGGL((KERNEL<f16s, H>), __VA_ARGS__); break;                    \
     default: throw std::runtime_error("bad precision");                                     \
   }
 
 void launch_contract_local(int prec, const SlotDesc* slots, int nslots, int total_units, const void* s_e,
-                           const void* s_o, const void* xi_e, const void* xi_o, hipStream_t st) {
+                           const void* s_o, const void* xi_e, const void* xi_o, const void* phi_e,
+                           const void* phi_o, hipStream_t st) {
   if (!total_units) return;
-  DISPATCH_PREC(prec, k_contract_local, dim3((total_units + 3) / 4), dim3(256), 0, st, slots, nslots,
-                total_units, s_e, s_o, xi_e, xi_o);
+  const dim3 grid((total_units + 3) / 4), block(256);
+  if (phi_e) {
+    DISPATCH_PREC(prec, true, k_contract_local, grid, block, 0, st, slots, nslots, total_units, s_e, s_o, xi_e,
+                  xi_o, phi_e, phi_o);
+  } else {
+    DISPATCH_PREC(prec, false, k_contract_local, grid, block, 0, st, slots, nslots, total_units, s_e, s_o, xi_e,
+                  xi_o, phi_e, phi_o);
+  }
 }
 
 void launch_contract_deriv(int prec, const SlotDesc* slots, int nslots, int total_units, const void* s_e,
-                           const void* s_o, const void* xi_e, const void* xi_o, hipStream_t st) {
+                           const void* s_o, const void* xi_e, const void* xi_o, const void* phi_e,
+                           const void* phi_o, hipStream_t st) {
   if (!total_units) return;
-  DISPATCH_PREC(prec, k_contract_deriv, dim3((total_units + 3) / 4), dim3(256), 0, st, slots, nslots,
-                total_units, s_e, s_o, xi_e, xi_o);
+  const dim3 grid((total_units + 3) / 4), block(256);
+  if (phi_e) {
+    DISPATCH_PREC(prec, true, k_contract_deriv, grid, block, 0, st, slots, nslots, total_units, s_e, s_o, xi_e,
+                  xi_o, phi_e, phi_o);
+  } else {
+    DISPATCH_PREC(prec, false, k_contract_deriv, grid, block, 0, st, slots, nslots, total_units, s_e, s_o, xi_e,
+                  xi_o, phi_e, phi_o);
+  }
 }
 
 }  // namespace dl

@@ -99,13 +99,17 @@ void launch_diff_norms(const SlotDesc* slots, int nslots, int total_units, const
 void launch_pack_gauge(const double* src, int X, int Y, int Z, int T, void* g64, void* g32,
                        void* gb16, void* gh16, hipStream_t st);
 
-// loop contractions of a block of solutions into FP64 accumulators
+// loop contractions of a block of solutions into FP64 accumulators.
+// Without phi (null): the one-end-trick structures, (xi, s) pairs with
+// xi = (1 - kappa H) s.  With phi: hopping-parameter-expanded loops without
+// tau_3, the pair (xi = eta, phi = (kappa B H)^n s), symmetrised into the flavour
+// sum (local C -> (C + g5 C^dag g5) / 2, derivative E -> (E - g5 E^dag g5) / 2).
 void launch_contract_local(int prec, const SlotDesc* slots, int nslots, int total_units,
                            const void* s_e, const void* s_o, const void* xi_e, const void* xi_o,
-                           hipStream_t st);
+                           const void* phi_e, const void* phi_o, hipStream_t st);
 void launch_contract_deriv(int prec, const SlotDesc* slots, int nslots, int total_units,
                            const void* s_e, const void* s_o, const void* xi_e, const void* xi_o,
-                           hipStream_t st);
+                           const void* phi_e, const void* phi_o, hipStream_t st);
 
 // Tables of the separable momentum projection (device pointers), built on the
 // host from the momentum list: distinct kx values, distinct (kx, ky) pairs.
@@ -124,9 +128,12 @@ struct ProjTables {
 void launch_project(const double* const acc[3], const double w[3], int nq, int q_link, int X, int Y, int Z, int T,
                     const ProjTables& tb, double* r2, double* proj, hipStream_t st);
 
-// Gamma rebuild and prefactors -> out [2][nops][16][T][Np] complex
-void launch_loops_finalize(const double* proj, int nops, int T, int np, double kappa, double mu, double* out,
-                           hipStream_t st);
+// Gamma rebuild and prefactors -> out [2][nops][16][T][Np] complex.
+// exact (device [nops][16] complex, or null): added to the loops without
+// tau_3 at momentum 0 before the prefactor (exact part of the hopping
+// parameter expansion, already multiplied by the spatial volume and weights).
+void launch_loops_finalize(const double* proj, int nops, int T, int np, double kappa, double mu,
+                           const double* exact, double* out, hipStream_t st);
 
 // Number of FP64 accumulator components per site for an ops mask.
 int acc_components(int ops);

@@ -153,7 +153,7 @@ __device__ inline double2 op_entry(const double2* blk, int hermitian_kind, int a
 }
 
 __global__ __launch_bounds__(256) void k_loops_finalize(const double2* pr, int nops, int T, int np, double2 pf_t3,
-                                                        double2 pf_1, double2* out) {
+                                                        double2 pf_1, const double2* exact, double2* out) {
   const long long n_out = 2ll * nops * 16 * T * np;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_out) return;
@@ -174,6 +174,10 @@ __global__ __launch_bounds__(256) void k_loops_finalize(const double2* pr, int n
     const double2 v = op_entry(pr + (long long)base * stride, kind, a, b, stride, tp);
     re += g5 * (gr * v.x - gi * v.y);
     im += g5 * (gr * v.y + gi * v.x);
+  }
+  if (exact && fl == 1 && tp % np == 0) {   // momentum 0 comes first
+    re += exact[op * 16 + n].x;
+    im += exact[op * 16 + n].y;
   }
   const double2 pf = fl == 0 ? pf_t3 : pf_1;
   out[i] = make_double2(pf.x * re - pf.y * im, pf.x * im + pf.y * re);
@@ -251,15 +255,15 @@ void launch_omega(const double* g, int nops, int X, int Y, int Z, int T, int np,
                      (double2*)omega);
 }
 
-void launch_loops_finalize(const double* proj, int nops, int T, int np, double kappa, double mu, double* out,
-                           hipStream_t st) {
+void launch_loops_finalize(const double* proj, int nops, int T, int np, double kappa, double mu,
+                           const double* exact, double* out, hipStream_t st) {
   const long long n_out = 2ll * nops * 16 * T * np;
   if (n_out == 0) return;
   // physical-normalisation prefactors: tau_3  -2 i mu (2 kappa)^2,  no tau_3  4 kappa
   const double2 pf_t3 = make_double2(0.0, -2.0 * mu * 4.0 * kappa * kappa);
   const double2 pf_1 = make_double2(4.0 * kappa, 0.0);
   hipLaunchKernelGGL(k_loops_finalize, dim3((unsigned)((n_out + 255) / 256)), dim3(256), 0, st,
-                     (const double2*)proj, nops, T, np, pf_t3, pf_1, (double2*)out);
+                     (const double2*)proj, nops, T, np, pf_t3, pf_1, (const double2*)exact, (double2*)out);
 }
 
 }  // namespace dl

@@ -1,6 +1,7 @@
 // Host runtime objects behind the C ABI.
 #pragma once
 
+#include <complex>
 #include <map>
 #include <stdexcept>
 #include <string>
@@ -133,6 +134,8 @@ void run_batch(dl_ctx* ctx, int tier, const std::vector<SlotPlan>& plan, const s
 void apply_op(dl_lattice* lat, int op, int tier, const double* in, double* out, int nrhs);
 
 void set_gamma_table(const int col[16][4], const double ph[16][4][2]);
+// Dense Gamma_n = g1^n0 g2^n1 g3^n2 g4^n3 of the chiral basis (gamma_nu = Gamma_{2^nu}).
+void gamma_basis(std::complex<double> (&G)[16][4][4]);
 void init_gamma_table();
 
 // Slot shape of the hopping kernel: right-hand sides per slot and the

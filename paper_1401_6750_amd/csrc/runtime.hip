@@ -80,7 +80,7 @@ int tier_prec(int tier) {
 // ---------------------------------------------------------------------------
 // gamma insertions: Gamma_n = g1^n0 g2^n1 g3^n2 g4^n3, chiral basis
 // ---------------------------------------------------------------------------
-void init_gamma_table() {
+void gamma_basis(std::complex<double> (&G)[16][4][4]) {
   using C = std::complex<double>;
   const C I(0, 1);
   C g[4][4][4] = {};
@@ -93,8 +93,6 @@ void init_gamma_table() {
         g[k][2 + a][b] = I * sig[k][a][b];
       }
   for (int a = 0; a < 2; ++a) g[3][a][2 + a] = g[3][2 + a][a] = 1;
-  int col[16][4];
-  double ph[16][4][2];
   for (int n = 0; n < 16; ++n) {
     C m[4][4] = {};
     for (int a = 0; a < 4; ++a) m[a][a] = 1;
@@ -106,6 +104,18 @@ void init_gamma_table() {
           for (int c = 0; c < 4; ++c) t[a][b] += m[a][c] * g[k][c][b];
       std::memcpy(m, t, sizeof(m));
     }
+    std::memcpy(G[n], m, sizeof(m));
+  }
+}
+
+void init_gamma_table() {
+  using C = std::complex<double>;
+  C G[16][4][4];
+  gamma_basis(G);
+  int col[16][4];
+  double ph[16][4][2];
+  for (int n = 0; n < 16; ++n) {
+    const C (&m)[4][4] = G[n];
     for (int a = 0; a < 4; ++a) {
       int found = -1;
       for (int b = 0; b < 4; ++b)
@@ -134,6 +144,7 @@ enum CoefKind : int {
   CK_MDAGFULL,    // (M^dag psi)_p = A(-mu) psi_p - kappa gamma5 H gamma5 psi
   CK_HOP,         // H psi
   CK_G5V,         // gamma5 C_p - kappa H gamma5 A  (backward pass)
+  CK_KBH,         // kappa A^-1(mu) H psi  (one order of the hopping parameter expansion)
   // CG-loop forms: the M-hat result is stored as t' = D t with
   // D = gamma5 A^-1(-mu), which is exactly the input M-hat^dag needs at every
   // neighbour, so its hop needs no per-neighbour factor; t = D^-1 t' is
@@ -191,6 +202,7 @@ static Coef make_coef(int kind, double kappa, double mu) {
       case CK_MDAGFULL: d[s] = G5[s]; e[s] = -kappa * G5[s]; f[s] = Am[s]; break;
       case CK_HOP: break;
       case CK_G5V: d[s] = G5[s]; e[s] = -kappa; f[s] = G5[s]; break;
+      case CK_KBH: e[s] = kappa * Ai[s]; break;
     }
   }
   Coef c;
@@ -373,7 +385,19 @@ static void cg_start(Batch& b, int P, const void* eta_e, const void* eta_o, cons
 // field and merge into one contraction slot (its right-hand sides are summed in
 // registers, in order); accumulators that still appear in several merged slots
 // are handled in successive launches.
-static void contract_passes(Batch& b, int P, const void* s_e, const void* s_o, const void* xi_e, const void* xi_o) {
+// Contractions of the batch's solutions into their accumulators.  Slots that
+// share an accumulator go to different launches (no two waves of one launch
+// add to the same site); slots whose accumulator uses the hopping parameter
+// expansion run the HPE kernels (xi = eta, phi_loc / phi_der the expanded
+// fields for local / derivative insertions).
+struct HpeFields {
+  const void* eta[2] = {nullptr, nullptr};
+  const void* loc[2] = {nullptr, nullptr};
+  const void* der[2] = {nullptr, nullptr};
+};
+
+static void contract_passes(Batch& b, int P, const void* s_e, const void* s_o, const void* xi_e, const void* xi_o,
+                            const HpeFields& h) {
   std::vector<SlotDesc> merged;
   for (const SlotDesc& d : b.hs) {
     if (!d.acc) continue;
@@ -387,13 +411,17 @@ static void contract_passes(Batch& b, int P, const void* s_e, const void* s_o, c
     merged.push_back(d);
   }
   std::vector<std::vector<SlotDesc>> passes;
-  std::map<double*, int> seen;
+  std::map<std::pair<double*, bool>, int> seen;
   for (const SlotDesc& d : merged) {
-    const int k = seen[d.acc]++;
-    if ((int)passes.size() <= k) passes.emplace_back();
+    const bool hpe = DL_OPS_HPE_ORDER(d.acc_ops) != 0;
+    const int k = 2 * seen[{d.acc, hpe}]++ + (hpe ? 1 : 0);
+    if ((int)passes.size() <= k) passes.resize(k + 1);
     passes[k].push_back(d);
   }
-  for (auto& pass : passes) {
+  for (size_t k = 0; k < passes.size(); ++k) {
+    auto& pass = passes[k];
+    if (pass.empty()) continue;
+    const bool hpe = k & 1;
     int us = 0, ud = 0;
     for (SlotDesc& d : pass) {
       d.ubeg[UK_SITE] = us;
@@ -404,8 +432,15 @@ static void contract_passes(Batch& b, int P, const void* s_e, const void* s_o, c
     DevBuf ds(b.ctx, sizeof(SlotDesc) * pass.size());
     HIPCHECK(hipMemcpyAsync(ds.p, pass.data(), sizeof(SlotDesc) * pass.size(), hipMemcpyHostToDevice, b.ctx->st));
     const SlotDesc* dptr = ds.as<SlotDesc>();
-    launch_contract_local(P, dptr, (int)pass.size(), us, s_e, s_o, xi_e, xi_o, b.ctx->st);
-    launch_contract_deriv(P, dptr, (int)pass.size(), ud, s_e, s_o, xi_e, xi_o, b.ctx->st);
+    if (hpe) {
+      launch_contract_local(P, dptr, (int)pass.size(), us, s_e, s_o, h.eta[0], h.eta[1], h.loc[0], h.loc[1],
+                            b.ctx->st);
+      launch_contract_deriv(P, dptr, (int)pass.size(), ud, s_e, s_o, h.eta[0], h.eta[1], h.der[0], h.der[1],
+                            b.ctx->st);
+    } else {
+      launch_contract_local(P, dptr, (int)pass.size(), us, s_e, s_o, xi_e, xi_o, nullptr, nullptr, b.ctx->st);
+      launch_contract_deriv(P, dptr, (int)pass.size(), ud, s_e, s_o, xi_e, xi_o, nullptr, nullptr, b.ctx->st);
+    }
     // the descriptor buffer returns to the pool only after the stream passed it
     HIPCHECK(hipStreamSynchronize(b.ctx->st));
   }
@@ -766,9 +801,40 @@ void run_batch(dl_ctx* ctx, int tier, const std::vector<SlotPlan>& plan, const s
     b.dslash(P, F_Y, CK_RECON, 0, x.p, r.p, eta_e.p, nullptr);
   }
   if (any_acc) {
-    if (!xi_e_done) b.dslash(PC, F_Y, CK_XI, 0, x.p, p.p, r.p, nullptr);
-    b.dslash(PC, F_Y, CK_XI, 1, r.p, t.p, x.p, nullptr);
-    contract_passes(b, PC, r.p, x.p, p.p, t.p);
+    int hpe = 0;
+    bool any_plain = false;
+    for (const SlotPlan& sp : plan) {
+      if (!sp.acc) continue;
+      const int o = DL_OPS_HPE_ORDER(jobs[sp.job].accum->ops);
+      if (o) hpe = o;
+      else any_plain = true;
+    }
+    if (any_plain) {
+      if (!xi_e_done) b.dslash(PC, F_Y, CK_XI, 0, x.p, p.p, r.p, nullptr);
+      b.dslash(PC, F_Y, CK_XI, 1, r.p, t.p, x.p, nullptr);
+    }
+    HpeFields h;
+    DevBuf fa_e, fa_o, fb_e, fb_o;
+    if (hpe) {
+      // phi_k = (kappa B H)^k s, k = 1..n, alternating between two fields;
+      // the source eta (eta_e / eta_o, still intact) is the other vector
+      fa_e = b.field(PC); fa_o = b.field(PC); fb_e = b.field(PC); fb_o = b.field(PC);
+      const void* in_e = r.p;
+      const void* in_o = x.p;
+      for (int k = 1; k <= hpe; ++k) {
+        void* oe = (k & 1) ? fa_e.p : fb_e.p;
+        void* oo = (k & 1) ? fa_o.p : fb_o.p;
+        b.dslash(PC, 0, CK_KBH, 0, in_o, oe, nullptr, nullptr);
+        b.dslash(PC, 0, CK_KBH, 1, in_e, oo, nullptr, nullptr);
+        in_e = oe;
+        in_o = oo;
+      }
+      const int nd = std::min(hpe, 3);
+      h.eta[0] = eta_e.p; h.eta[1] = eta_o.p;
+      h.loc[0] = (hpe & 1) ? fa_e.p : fb_e.p; h.loc[1] = (hpe & 1) ? fa_o.p : fb_o.p;
+      h.der[0] = (nd & 1) ? fa_e.p : fb_e.p; h.der[1] = (nd & 1) ? fa_o.p : fb_o.p;
+    }
+    contract_passes(b, PC, r.p, x.p, p.p, t.p, h);
   }
   if (any_sol) {
     if (tier == DL_TIER_HP_FP32) {
@@ -1096,6 +1162,7 @@ bool solve_jobs(dl_ctx* ctx, const std::vector<dl_job>& J, dl_src_stats* stats) 
         double per = vp * sp.nrhs * (7.0 * chunks_of(P) * 16);
         if (tier == DL_TIER_HP_FP32) per += vp * sp.nrhs * 9.0 * 192;
         if (J[sp.job].report_true_resid) per += vp * sp.nrhs * 6.0 * 192;
+        if (J[sp.job].accum && DL_OPS_HPE_ORDER(J[sp.job].accum->ops)) per += vp * sp.nrhs * (4.0 * chunks_of(P) * 16);
         if (!wave.empty() && (bytes + per > budget || nrhs + sp.nrhs > max_rhs)) break;
         wave.push_back(sp);
         bytes += per;
