@@ -244,6 +244,8 @@ def main() -> int:
     ap.add_argument("--workload", default="batched_24x24x24x48", choices=sorted(WORKLOADS))
     ap.add_argument("--rhs-block", type=int, default=0)
     ap.add_argument("--inflight-mb", type=float, default=65536.0)
+    ap.add_argument("--hpe", type=int, default=0,
+                    help="hopping parameter expansion order (1..4) for the loops without tau_3; 0: off")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparator", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
@@ -284,7 +286,7 @@ def main() -> int:
     lat = dl.dl_lattice_create(ctx, dims, -1)
     dl.dl_gauge_set(lat, U_dev, 1)
     dl.dl_set_params(lat, kappa, mu)
-    acc = dl.dl_accum_create(lat, dl.DL_OPS_LOCAL | dl.DL_OPS_DERIV)
+    acc = dl.dl_accum_create(lat, dl.DL_OPS_LOCAL | dl.DL_OPS_DERIV | dl.DL_OPS_HPE(a.hpe))
     blocks = {"bf16": list(dl.dl_autotune(ctx, lat, dl.DL_TIER_LP_BF16, n_lp)),
               "fp32": list(dl.dl_autotune(ctx, lat, dl.DL_TIER_HP_FP32, n_hp))}
     if a.rhs_block:
@@ -417,7 +419,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": a.workload, "lattice": "x".join(map(str, dims)), "n_lp": n_lp, "n_hp": n_hp,
                    "n_lpc": n_hp, "lp_storage": "bf16", "hp": "fp32+fp64 reliable updates",
-                   "noise": tw["noise"], "p2max": p2, "insertions": 160, "rhs_block": blocks},
+                   "noise": tw["noise"], "p2max": p2, "insertions": 160, "rhs_block": blocks,
+                   "hpe_order": a.hpe},
         "iters_lp_mean": round(float(np.mean(it_lp)), 2), "iters_hp_mean": round(float(np.mean(it_hp)), 2),
         "reliable_updates_hp_mean": round(float(np.mean(ru_hp)), 2),
         "roofline": roofline,
