@@ -246,6 +246,9 @@ def main() -> int:
     ap.add_argument("--inflight-mb", type=float, default=65536.0)
     ap.add_argument("--hpe", type=int, default=0,
                     help="hopping parameter expansion order (1..4) for the loops without tau_3; 0: off")
+    ap.add_argument("--tdil", type=int, default=0,
+                    help="time dilution: D components per noise vector (the noise-vector counts are "
+                         "divided by D so the number of solves stays the same); 0: off")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparator", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
@@ -276,6 +279,9 @@ def main() -> int:
     X, Y, Z, T = dims
     noise_kind = dl.DL_NOISE_Z4 if tw["noise"] == "Z4" else dl.DL_NOISE_Z2
     n_lp, n_hp, p2 = tw["n_lp"], tw["n_hp"], tw["p2max"]
+    ncomp = max(a.tdil, 1)
+    v_lp, v_hp = n_lp // ncomp, n_hp // ncomp      # noise vectors; n_lp, n_hp stay the solve counts
+    n_lp, n_hp = v_lp * ncomp, v_hp * ncomp
 
     log(f"setup: {a.workload} gauge field")
     U = synth.random_gauge(dims, w["gauge_seed"], w["eps"])
@@ -298,14 +304,16 @@ def main() -> int:
 
     def jobs():
         return [
-            dl.make_job(lat, noise=noise_kind, tier=dl.DL_TIER_LP_BF16, seed=seed, first_src=0, nsrc=n_lp,
-                        tol=1e-2, maxiter=500, rhs_block=a.rhs_block, accum=acc, accum_set=dl.DL_SET_LP),
+            dl.make_job(lat, noise=noise_kind, tier=dl.DL_TIER_LP_BF16, seed=seed, first_src=0, nsrc=v_lp,
+                        tol=1e-2, maxiter=500, rhs_block=a.rhs_block, accum=acc, accum_set=dl.DL_SET_LP,
+                        tdil=a.tdil),
             # HP correction solves start from the LPC solutions of the same sources (job 2)
-            dl.make_job(lat, noise=noise_kind, tier=dl.DL_TIER_HP_FP32, seed=seed, first_src=n_lp, nsrc=n_hp,
+            dl.make_job(lat, noise=noise_kind, tier=dl.DL_TIER_HP_FP32, seed=seed, first_src=v_lp, nsrc=v_hp,
                         tol=1e-8, maxiter=2000, rhs_block=a.rhs_block, accum=acc, accum_set=dl.DL_SET_HP,
-                        guess_from=3),
-            dl.make_job(lat, noise=noise_kind, tier=dl.DL_TIER_LP_BF16, seed=seed, first_src=n_lp, nsrc=n_hp,
-                        tol=1e-2, maxiter=500, rhs_block=a.rhs_block, accum=acc, accum_set=dl.DL_SET_LPC),
+                        guess_from=3, tdil=a.tdil),
+            dl.make_job(lat, noise=noise_kind, tier=dl.DL_TIER_LP_BF16, seed=seed, first_src=v_lp, nsrc=v_hp,
+                        tol=1e-2, maxiter=500, rhs_block=a.rhs_block, accum=acc, accum_set=dl.DL_SET_LPC,
+                        tdil=a.tdil),
         ]
 
     def step():
@@ -420,7 +428,7 @@ def main() -> int:
         "config": {"workload": a.workload, "lattice": "x".join(map(str, dims)), "n_lp": n_lp, "n_hp": n_hp,
                    "n_lpc": n_hp, "lp_storage": "bf16", "hp": "fp32+fp64 reliable updates",
                    "noise": tw["noise"], "p2max": p2, "insertions": 160, "rhs_block": blocks,
-                   "hpe_order": a.hpe},
+                   "hpe_order": a.hpe, "tdil": a.tdil},
         "iters_lp_mean": round(float(np.mean(it_lp)), 2), "iters_hp_mean": round(float(np.mean(it_hp)), 2),
         "reliable_updates_hp_mean": round(float(np.mean(ru_hp)), 2),
         "roofline": roofline,

@@ -131,6 +131,20 @@ typedef struct dl_job {
                             first_src, nsrc, src_in).  The final accuracy is
                             unchanged; the truncated-solver correction solves
                             then start at the low-precision residual. */
+  int tdil;              /* time dilution (Section 2.2 works with time-diluted
+                            sources): 0 or 1 = none; D >= 2 (at most T) splits every
+                            noise vector r into D sources eta_(r,c), c = 0..D-1, equal
+                            to eta_r on the time slices t with t mod D == c and zero
+                            elsewhere, each solved on its own.  nsrc still counts
+                            noise vectors; the job's stats and sol_out hold nsrc * D
+                            entries, component-major (entry c * nsrc + r - first_src);
+                            src_in (USER noise) holds the nsrc undiluted vectors.  The
+                            loops of one noise vector are the sum over its components,
+                            so the accumulator's source count grows by nsrc.  One-end-
+                            trick structures contract every component over the whole
+                            lattice; the hopping parameter expansion, which pairs eta
+                            with the solution, only next to the component's slices. */
+  int reserved;          /* set to 0 */
 } dl_job;
 
 typedef struct dl_src_stats {
@@ -175,7 +189,7 @@ int dl_set_params(dl_lattice* lat, double kappa, double mu);
  * the job's tier, then add the one-end-trick loops of each solution to the
  * job's accumulator set.  Jobs of the same precision class run together in
  * shared launches (different lattices and source blocks interleaved).
- * stats: optional host array of sum(nsrc) entries, in job order.
+ * stats: optional host array of sum(nsrc * max(tdil, 1)) entries, in job order.
  * Returns DL_NOT_CONVERGED if any source missed its tolerance. */
 int dl_solve_batch(dl_ctx* ctx, const dl_job* jobs, int njobs, dl_src_stats* stats);
 

@@ -60,6 +60,8 @@ class dl_job(ctypes.Structure):
         ("accum", ctypes.c_void_p),
         ("accum_set", ctypes.c_int),
         ("guess_from", ctypes.c_int),
+        ("tdil", ctypes.c_int),
+        ("reserved", ctypes.c_int),
     ]
 
 
@@ -209,10 +211,11 @@ def dl_momenta(dims, p2max: int):
 
 def make_job(lat, *, noise=DL_NOISE_Z2, tier=DL_TIER_FP64, seed=0, first_src=0, nsrc=1, maxiter=1000,
              tol=1e-10, rhs_block=0, report_true_resid=0, src_in=None, sol_out=None, accum=None,
-             accum_set=DL_SET_HP, guess_from=0) -> dl_job:
-    """One job; guess_from = j + 1 starts an HP job from the solutions of job j of the same call."""
+             accum_set=DL_SET_HP, guess_from=0, tdil=0) -> dl_job:
+    """One job; guess_from = j + 1 starts an HP job from the solutions of job j of the same call;
+    tdil = D >= 2 dilutes every noise vector into D time-slice components."""
     return dl_job(lat, noise, tier, seed, first_src, nsrc, maxiter, tol, rhs_block, report_true_resid,
-                  _ptr(src_in), _ptr(sol_out), accum, accum_set, guess_from)
+                  _ptr(src_in), _ptr(sol_out), accum, accum_set, guess_from, tdil, 0)
 
 
 def dl_solve_batch(ctx, jobs):
@@ -220,7 +223,7 @@ def dl_solve_batch(ctx, jobs):
     if isinstance(jobs, dl_job):
         jobs = [jobs]
     arr = (dl_job * len(jobs))(*jobs)
-    n = sum(j.nsrc for j in jobs)
+    n = sum(j.nsrc * max(j.tdil, 1) for j in jobs)
     stats = (dl_src_stats * max(n, 1))()
     rc = _check(lib().dl_solve_batch(ctx, arr, len(jobs), stats))
     return rc, list(stats)[:n]

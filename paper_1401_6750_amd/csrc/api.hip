@@ -281,11 +281,12 @@ int dl_solve_batch(dl_ctx* ctx, const dl_job* jobs, int njobs, dl_src_stats* sta
       require(q.first_src >= 0, "dl_solve_batch: first_src < 0");
       (void)tier_prec(q.tier);
       require(q.rhs_block >= 0, "dl_solve_batch: rhs_block < 0");
+      require(q.tdil >= 0 && q.tdil <= q.lat->dims[3], "dl_solve_batch: tdil must be 0..T");
       if (q.accum) {
         require(q.accum->lat == q.lat, "dl_solve_batch: accumulator of another lattice");
         require(q.accum_set >= 0 && q.accum_set < 3, "dl_solve_batch: bad accum_set");
       }
-      first_stat[j + 1] = first_stat[j] + q.nsrc;
+      first_stat[j + 1] = first_stat[j] + (long long)q.nsrc * std::max(q.tdil, 1);
     }
     int hpe_order = 0;
     for (const dl_job& q : J) {
@@ -305,7 +306,7 @@ int dl_solve_batch(dl_ctx* ctx, const dl_job* jobs, int njobs, dl_src_stats* sta
       require(q.tier == DL_TIER_HP_FP32, "dl_solve_batch: guess_from is for HP jobs");
       require(h.tier != DL_TIER_HP_FP32, "dl_solve_batch: guess_from must name a lower-tier job");
       require(h.lat == q.lat && h.noise == q.noise && h.seed == q.seed && h.first_src == q.first_src &&
-                  h.nsrc == q.nsrc && h.src_in == q.src_in,
+                  h.nsrc == q.nsrc && h.src_in == q.src_in && std::max(h.tdil, 1) == std::max(q.tdil, 1),
               "dl_solve_batch: guess_from job must solve the same sources on the same lattice");
     }
     stream_enter(ctx);
@@ -625,6 +626,7 @@ int dl_loops_backward(dl_ctx* ctx, const dl_job* job, int p2max, const double* g
     require(ctx && job && grad_loops, "dl_loops_backward: NULL argument");
     require(!job->accum || DL_OPS_HPE_ORDER(job->accum->ops) == 0,
             "dl_loops_backward: loops with the hopping parameter expansion are not differentiated");
+    require(job->tdil <= 1, "dl_loops_backward: time-diluted sources are not differentiated");
     loops_backward(ctx, *job, p2max, grad_loops, grad_eta, grad_mu);
     return 0;
   });

@@ -225,6 +225,10 @@ __global__ __launch_bounds__(256) void k_sources(const SlotDesc* slots, int nslo
       }
     }
   }
+  if (sd.tdil > 1 && c.t % sd.tdil != sd.tcomp) {   // time dilution: other component's slice
+#pragma unroll
+    for (int k = 0; k < 12; ++k) v[k] = mk<R>(0, 0);
+  }
   store_spinor<S>(field_at<S>(eta, w.off), sd.Vp, w.s, v);
 }
 

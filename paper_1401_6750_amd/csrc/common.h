@@ -395,6 +395,8 @@ struct SlotDesc {
   void* gsave;             // guess buffer of rhs 0 to store the odd solution in, or null
   const void* gload;       // guess buffer of rhs 0 to start the odd solution from, or null
   int gprec;               // storage precision of gload
+  int tdil;                // time dilution: components per noise vector (<= 1: none)
+  int tcomp;               // component of this slot's rhs: time slices t with t mod tdil == tcomp
   int pad1;
 };
 

@@ -63,7 +63,7 @@ __device__ constexpr int up_b(int k) { return k < 3 ? k + 1 : (k < 5 ? k - 1 : 3
 // source loop (1/2 on the s-s diagonal, 1/4 elsewhere, powers of two, so the
 // scaling is exact) and scaled here.
 template <bool DERIV, bool HPE, class A>
-__device__ inline void flush(double* acc, long long V, int lane, A (&a)[48]) {
+__device__ inline void flush(double* acc, long long V, int lane, A (&a)[48], bool xs = true) {
   // keep the 48 addresses from being computed once and held across the
   // source loop (that alone would take 96 registers)
   asm volatile("" : "+v"(lane));
@@ -87,11 +87,23 @@ __device__ inline void flush(double* acc, long long V, int lane, A (&a)[48]) {
   }
 #pragma unroll
   for (int q = 0; q < 48; ++q) {
+    if (q >= 16 && !xs) break;   // xi-s block not contracted at this site
     double* p = acc + q * V;
     const double f = DERIV ? (q < 4 ? 0.5 : 0.25) : 1.0;
     p[lane] += f * (double)a[q];
     a[q] = (A)0;
   }
+}
+
+// Time dilution with the expansion: eta of component c lives on the slices
+// t mod D == c, so the xi-s block (xi = eta) is non-zero only there -- and, for
+// the link-centred time derivative, on the slice before.  Elsewhere it is
+// skipped (the single-time-slice contraction); the s-s block is always summed.
+__device__ inline bool xs_sites(const SlotDesc& sd, int t, int nu) {
+  if (sd.tdil <= 1) return true;
+  if (t % sd.tdil == sd.tcomp) return true;
+  const int tn = t + 1 == sd.T ? 0 : t + 1;
+  return nu == 3 && tn % sd.tdil == sd.tcomp;
 }
 
 template <class S, bool HPE>
@@ -115,6 +127,8 @@ __global__ __launch_bounds__(256) void k_contract_local(const SlotDesc* slots, i
   const void* sf = par ? s_o : s_e;
   const void* xf = par ? xi_o : xi_e;
   const void* pf = par ? phi_o : phi_e;
+  bool xs = true;
+  if constexpr (HPE) xs = xs_sites(sd, eo_coords(sd, s, par).t, -1);
   A a[48];
 #pragma unroll
   for (int q = 0; q < 48; ++q) a[q] = (A)0;
@@ -122,9 +136,8 @@ __global__ __launch_bounds__(256) void k_contract_local(const SlotDesc* slots, i
 #pragma unroll 1
   for (int r = 0; r < sd.nrhs; ++r) {
     const long long off = sd.fo + (long long)r * vp;
-    cx<R> sv[12], xv[12];
+    cx<R> sv[12];
     load_spinor<S>(field_at<S>(sf, off), vp, s, sv);
-    load_spinor<S>(field_at<S>(xf, off), vp, s, xv);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       R d = 0;
@@ -140,23 +153,27 @@ __global__ __launch_bounds__(256) void k_contract_local(const SlotDesc* slots, i
       a[4 + 2 * k] += (A)t.re;
       a[5 + 2 * k] += (A)t.im;
     }
-    if constexpr (HPE) load_spinor<S>(field_at<S>(pf, off), vp, s, sv);   // sv = phi from here on
+    if (xs) {
+      cx<R> xv[12];
+      load_spinor<S>(field_at<S>(xf, off), vp, s, xv);
+      if constexpr (HPE) load_spinor<S>(field_at<S>(pf, off), vp, s, sv);   // sv = phi from here on
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        cx<R> t = mk<R>(0, 0);
+        for (int j = 0; j < 4; ++j) {
+          cx<R> t = mk<R>(0, 0);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) cjmac(t, xv[3 * i + c], sv[3 * j + c]);
-        a[16 + 2 * (4 * i + j)] += (A)t.re;
-        a[17 + 2 * (4 * i + j)] += (A)t.im;
-      }
+          for (int c = 0; c < 3; ++c) cjmac(t, xv[3 * i + c], sv[3 * j + c]);
+          a[16 + 2 * (4 * i + j)] += (A)t.re;
+          a[17 + 2 * (4 * i + j)] += (A)t.im;
+        }
+    }
     if (++inblk == AccT<S>::KB) {
-      flush<false, HPE>(acc, V, lane_off, a);
+      flush<false, HPE>(acc, V, lane_off, a, xs);
       inblk = 0;
     }
   }
-  if (inblk) flush<false, HPE>(acc, V, lane_off, a);
+  if (inblk) flush<false, HPE>(acc, V, lane_off, a, xs);
 }
 
 // Forward transport of one rhs field along nu: out = M psi(x+nu), M = b U_nu(x)
@@ -241,6 +258,8 @@ __global__ __launch_bounds__(256) void k_contract_deriv(const SlotDesc* slots, i
   const long long V = 2ll * vp;
   double* acc = sd.acc + (long long)(48 + 48 * nu) * V;
   const int lane_off = par * (int)vp + s;
+  bool xs = true;
+  if constexpr (HPE) xs = xs_sites(sd, c.t, nu);
   A a[48];
 #pragma unroll
   for (int q = 0; q < 48; ++q) a[q] = (A)0;
@@ -275,7 +294,7 @@ __global__ __launch_bounds__(256) void k_contract_deriv(const SlotDesc* slots, i
       a[5 + 2 * k6] += (A)(t1.im - t2.im);
     }
     // xi-s block, first half: 1/4 conj(xi_a) T_phi,b (phi = s unless HPE)
-    {
+    if (xs) {
       cx<R> xv[12];
       load_spinor<S>(field_at<S>(x_here, off), vp, s, xv);
       if constexpr (HPE) transport_fwd<S>(field_at<S>(f_other, off), vp, sp, up, cr, ci, t);   // t = T_phi
@@ -289,26 +308,26 @@ __global__ __launch_bounds__(256) void k_contract_deriv(const SlotDesc* slots, i
           a[16 + 2 * (4 * i + j)] += (A)w.re;
           a[17 + 2 * (4 * i + j)] += (A)w.im;
         }
+      // second half: -1/4 conj(T_xi,a) phi_b
+      if constexpr (HPE) load_spinor<S>(field_at<S>(f_here, off), vp, s, sv);   // sv = phi
+      transport_fwd<S>(field_at<S>(x_other, off), vp, sp, up, cr, ci, t);   // t = T_xi
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          cx<R> w = mk<R>(0, 0);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) cjmac(w, t[3 * i + k], sv[3 * j + k]);
+          a[16 + 2 * (4 * i + j)] -= (A)w.re;
+          a[17 + 2 * (4 * i + j)] -= (A)w.im;
+        }
     }
-    // second half: -1/4 conj(T_xi,a) phi_b
-    if constexpr (HPE) load_spinor<S>(field_at<S>(f_here, off), vp, s, sv);   // sv = phi
-    transport_fwd<S>(field_at<S>(x_other, off), vp, sp, up, cr, ci, t);   // t = T_xi
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        cx<R> w = mk<R>(0, 0);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) cjmac(w, t[3 * i + k], sv[3 * j + k]);
-        a[16 + 2 * (4 * i + j)] -= (A)w.re;
-        a[17 + 2 * (4 * i + j)] -= (A)w.im;
-      }
     if (++inblk == AccT<S>::KB) {
-      flush<true, HPE>(acc, V, lane_off, a);
+      flush<true, HPE>(acc, V, lane_off, a, xs);
       inblk = 0;
     }
   }
-  if (inblk) flush<true, HPE>(acc, V, lane_off, a);
+  if (inblk) flush<true, HPE>(acc, V, lane_off, a, xs);
 }
 
 #define DISPATCH_PREC(prec, H, KERNEL, ...)                                                  \

@@ -119,6 +119,8 @@ struct SlotPlan {
   void* gsave;             // store this slot's odd solutions here (rhs 0), or null
   const void* gload;       // start this slot's CG from here (rhs 0), or null
   int gprec;               // precision of gload
+  int tdil = 0;            // time dilution of the job (components per noise vector)
+  int tcomp = 0;           // component of this slot's sources
 };
 
 struct SolveReport {

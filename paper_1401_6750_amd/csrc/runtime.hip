@@ -260,6 +260,8 @@ struct Batch {
         d.noise = DL_NOISE_USER;
       }
       d.src0 = sp.src0;
+      d.tdil = sp.tdil;
+      d.tcomp = sp.tcomp;
       d.src_user = sp.src_user;
       d.sol_user = sp.sol_user;
       d.gsave = sp.gsave;
@@ -403,7 +405,10 @@ static void contract_passes(Batch& b, int P, const void* s_e, const void* s_o, c
     if (!d.acc) continue;
     if (!merged.empty()) {
       SlotDesc& m = merged.back();
-      if (m.acc == d.acc && m.gauge[0] == d.gauge[0] && m.fo + (long long)m.nrhs * m.Vp == d.fo) {
+      // contiguous slots of one accumulator and lattice contract as one; time-diluted
+      // slots only within one component (the expansion's contraction depends on it)
+      if (m.acc == d.acc && m.gauge[0] == d.gauge[0] && m.fo + (long long)m.nrhs * m.Vp == d.fo &&
+          m.tdil == d.tdil && m.tcomp == d.tcomp) {
         m.nrhs += d.nrhs;
         continue;
       }
@@ -1099,7 +1104,8 @@ TuneChoice autotune_block(dl_ctx* ctx, dl_lattice* lat, int prec, int nsrc_hint)
 bool solve_jobs(dl_ctx* ctx, const std::vector<dl_job>& J, dl_src_stats* stats) {
   const int njobs = (int)J.size();
   std::vector<long long> first_stat(njobs + 1, 0);
-  for (int j = 0; j < njobs; ++j) first_stat[j + 1] = first_stat[j] + J[j].nsrc;
+  auto ncomp = [](const dl_job& q) { return std::max(q.tdil, 1); };
+  for (int j = 0; j < njobs; ++j) first_stat[j + 1] = first_stat[j] + (long long)J[j].nsrc * ncomp(J[j]);
   bool all_ok = true;
   const double budget = ctx->inflight_mb * 1048576.0;
   // solutions that HP jobs start from: the caller's sol_out, or a library
@@ -1110,7 +1116,7 @@ bool solve_jobs(dl_ctx* ctx, const std::vector<dl_job>& J, dl_src_stats* stats) 
     const int g = J[j].guess_from - 1;
     if (g < 0 || gbuf[g] || J[g].nsrc == 0) continue;
     const size_t per = (size_t)chunks_of(tier_prec(J[g].tier)) * pad_half(J[g].lat->Vh) * 16;
-    keep.emplace_back(ctx, (size_t)J[g].nsrc * per);
+    keep.emplace_back(ctx, (size_t)J[g].nsrc * ncomp(J[g]) * per);
     gbuf[g] = keep.back().p;
   }
   const int max_rhs = ctx->inflight_rhs;
@@ -1122,33 +1128,38 @@ bool solve_jobs(dl_ctx* ctx, const std::vector<dl_job>& J, dl_src_stats* stats) 
       const dl_job& q = J[j];
       if (q.tier != tier || q.nsrc == 0) continue;
       const TuneChoice tc =
-          q.rhs_block > 0 ? TuneChoice{q.rhs_block, TBLK_DEFAULT} : autotune_block(ctx, q.lat, P, q.nsrc);
+          q.rhs_block > 0 ? TuneChoice{q.rhs_block, TBLK_DEFAULT} : autotune_block(ctx, q.lat, P, q.nsrc * ncomp(q));
       const int N = tc.block;
       const long long V = q.lat->V;
-      for (int k = 0; k < q.nsrc; k += N) {
-        SlotPlan sp{};
-        sp.lat = q.lat;
-        sp.job = j;
-        sp.job_first = k;
-        sp.nrhs = std::min(N, q.nsrc - k);
-        sp.src0 = q.first_src + k;
-        sp.src_user = q.src_in ? q.src_in + (size_t)k * V * 24 : nullptr;
-        sp.sol_user = q.sol_out ? q.sol_out + (size_t)k * V * 24 : nullptr;
-        if (gbuf[j]) {
-          const size_t per = (size_t)chunks_of(P) * pad_half(q.lat->Vh) * 16;
-          sp.gsave = (char*)gbuf[j] + (size_t)k * per;
+      // time dilution: one slot set per component; job entries component-major
+      for (int c = 0; c < ncomp(q); ++c)
+        for (int k = 0; k < q.nsrc; k += N) {
+          const long long e = (long long)c * q.nsrc + k;   // entry of rhs 0 in the job's stats / sol_out
+          SlotPlan sp{};
+          sp.lat = q.lat;
+          sp.job = j;
+          sp.job_first = (int)e;
+          sp.nrhs = std::min(N, q.nsrc - k);
+          sp.src0 = q.first_src + k;
+          sp.src_user = q.src_in ? q.src_in + (size_t)k * V * 24 : nullptr;
+          sp.sol_user = q.sol_out ? q.sol_out + (size_t)e * V * 24 : nullptr;
+          sp.tdil = q.tdil > 1 ? q.tdil : 0;
+          sp.tcomp = c;
+          if (gbuf[j]) {
+            const size_t per = (size_t)chunks_of(P) * pad_half(q.lat->Vh) * 16;
+            sp.gsave = (char*)gbuf[j] + (size_t)e * per;
+          }
+          if (q.guess_from) {
+            const dl_job& h = J[q.guess_from - 1];
+            const int PG = tier_prec(h.tier);
+            const size_t per = (size_t)chunks_of(PG) * pad_half(h.lat->Vh) * 16;
+            sp.gload = (const char*)gbuf[q.guess_from - 1] + (size_t)e * per;
+            sp.gprec = PG;
+          }
+          sp.acc = q.accum ? q.accum->acc[q.accum_set] : nullptr;
+          sp.tblk = tc.tblk;
+          all.push_back(sp);
         }
-        if (q.guess_from) {
-          const dl_job& h = J[q.guess_from - 1];
-          const int PG = tier_prec(h.tier);
-          const size_t per = (size_t)chunks_of(PG) * pad_half(h.lat->Vh) * 16;
-          sp.gload = (const char*)gbuf[q.guess_from - 1] + (size_t)k * per;
-          sp.gprec = PG;
-        }
-        sp.acc = q.accum ? q.accum->acc[q.accum_set] : nullptr;
-        sp.tblk = tc.tblk;
-        all.push_back(sp);
-      }
     }
     // batches bounded by device memory and right-hand-side count
     size_t i = 0;
@@ -1186,7 +1197,7 @@ bool solve_jobs(dl_ctx* ctx, const std::vector<dl_job>& J, dl_src_stats* stats) 
           }
         }
         const dl_job& q = J[sp.job];
-        if (q.accum) q.accum->count[q.accum_set] += sp.nrhs;
+        if (q.accum && sp.tcomp == 0) q.accum->count[q.accum_set] += sp.nrhs;   // noise vectors
       }
     }
   }

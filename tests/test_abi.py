@@ -3,6 +3,7 @@ logic and argument checks work without a GPU."""
 import ctypes
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -60,10 +61,26 @@ def test_argument_errors_without_gpu():
     assert e.value.code == dl.DL_EINVAL
 
 
-def test_struct_layouts_match_header():
-    # dl_job: pointer, 2 ints, u64, i64, 2 ints, double, 2 ints, 3 pointers, int (+ padding)
-    assert ctypes.sizeof(dl.dl_job) == 88
-    assert ctypes.sizeof(dl.dl_src_stats) == 32
+def test_struct_layouts_match_header(tmp_path):
+    """Sizes and field offsets of the binding's structs equal what a C compiler makes of
+    the header."""
+    structs = {"dl_job": dl.dl_job, "dl_src_stats": dl.dl_src_stats}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{name} {f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for name, cls in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert got[(name, f)] == getattr(cls, f).offset, (name, f)
 
 
 def test_binding_refuses_to_run_without_library(monkeypatch, tmp_path):
