@@ -204,14 +204,14 @@ __global__ __launch_bounds__(256) void k_sources(const SlotDesc* slots, int nslo
 #pragma unroll
     for (int k = 0; k < 12; ++k) v[k] = mk<R>(0, 0);
   } else if (sd.noise == 2) {          // caller sources, complex128 [rhs][V][12]
-    const double2* src = (const double2*)sd.src_user + ((long long)w.r * V + lex) * 12;
+    const double2* src = (const double2*)sd.src_user + ((long long)src_vector(sd, w.r) * V + lex) * 12;
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
       double2 q = src[k];
       v[k] = mk<R>((R)q.x, (R)q.y);
     }
   } else {
-    const uint64_t base = ((uint64_t)(sd.src0 + w.r) * (uint64_t)V + (uint64_t)lex) * 12ull;
+    const uint64_t base = ((uint64_t)(sd.src0 + src_vector(sd, w.r)) * (uint64_t)V + (uint64_t)lex) * 12ull;
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
       const uint64_t b = splitmix64_at(sd.seed, base + k);
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(256) void k_sources(const SlotDesc* slots, int nslo
       }
     }
   }
-  if (sd.tdil > 1 && c.t % sd.tdil != sd.tcomp) {   // time dilution: other component's slice
+  if (sd.tdil > 1 && c.t % sd.tdil != tdil_comp(sd, w.r)) {   // time dilution: other component's slice
 #pragma unroll
     for (int k = 0; k < 12; ++k) v[k] = mk<R>(0, 0);
   }

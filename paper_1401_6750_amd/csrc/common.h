@@ -387,18 +387,32 @@ struct SlotDesc {
   const void* gauge[4];    // gauge field per precision
   double* acc;             // accumulator set of this slot (contractions), or null
   uint64_t seed;           // noise
-  long long src0;          // source index of rhs 0
+  long long src0;          // source index of rhs 0 (time dilution: of the job's first vector)
   int noise;               // DL_NOISE_*
   int acc_ops;             // DL_OPS_* of the accumulator
-  const double* src_user;  // caller sources of rhs 0 (complex128 [V][12] per rhs), or null
+  const double* src_user;  // caller sources of rhs 0 (complex128 [V][12] per rhs; time dilution:
+                           // the job's first vector), or null
   double* sol_user;        // caller solution array of rhs 0, or null
   void* gsave;             // guess buffer of rhs 0 to store the odd solution in, or null
   const void* gload;       // guess buffer of rhs 0 to start the odd solution from, or null
   int gprec;               // storage precision of gload
   int tdil;                // time dilution: components per noise vector (<= 1: none)
-  int tcomp;               // component of this slot's rhs: time slices t with t mod tdil == tcomp
-  int pad1;
+  int tclen;               // time dilution: noise vectors of the job (entries per component)
+  int tentry;              // job entry of rhs 0 (entries component-major): rhs r belongs to
+                           // component (tentry + r) / tclen, the slices t mod tdil == component
+  int job;                 // index of the job in its call
 };
+
+// Time-dilution component of rhs r of a slot.
+__host__ __device__ inline int tdil_comp(const SlotDesc& sd, int r) {
+  return sd.tdil > 1 ? (sd.tentry + r) / sd.tclen : 0;
+}
+
+// Noise vector of rhs r, counted from src0 / src_user: a time-diluted slot
+// may span components, its rhs r is vector (tentry + r) mod tclen of the job.
+__host__ __device__ inline int src_vector(const SlotDesc& sd, int r) {
+  return sd.tdil > 1 ? (sd.tentry + r) % sd.tclen : r;
+}
 
 // Per-slot site-diagonal spin coefficients of one dslash-type launch:
 //   res = e (.) H(d (.) in) + f (.) y,  out = g (.) res   (per-spin complex factors)

@@ -86,27 +86,38 @@ __device__ inline void flush(double* acc, long long V, int lane, A (&a)[48], boo
       }
   }
 #pragma unroll
-  for (int q = 0; q < 48; ++q) {
-    if (q >= 16 && !xs) break;   // xi-s block not contracted at this site
+  for (int q = 0; q < 16; ++q) {
     double* p = acc + q * V;
     const double f = DERIV ? (q < 4 ? 0.5 : 0.25) : 1.0;
     p[lane] += f * (double)a[q];
     a[q] = (A)0;
   }
+  if (xs) {   // else the xi-s block was not contracted at this site in this block
+#pragma unroll
+    for (int q = 16; q < 48; ++q) {
+      double* p = acc + q * V;
+      p[lane] += (DERIV ? 0.25 : 1.0) * (double)a[q];
+      a[q] = (A)0;
+    }
+  }
 }
 
 // Time dilution with the expansion: eta of component c lives on the slices
-// t mod D == c, so the xi-s block (xi = eta) is non-zero only there -- and, for
-// the link-centred time derivative, on the slice before.  Elsewhere it is
-// skipped (the single-time-slice contraction); the s-s block is always summed.
-__device__ inline bool xs_sites(const SlotDesc& sd, int t, int nu) {
-  if (sd.tdil <= 1) return true;
-  if (t % sd.tdil == sd.tcomp) return true;
+// t mod D == c, so the xi-s block (xi = eta) of an rhs of component c is
+// non-zero only there -- and, for the link-centred time derivative, on the
+// slice before.  Elsewhere it is skipped (the single-time-slice contraction);
+// the s-s block is always summed.
+// The components whose xi-s terms reach a site: (t mod D, and for the time
+// derivative the next slice's, else -1); without dilution both are 0 = the
+// component of every rhs.
+struct XsComps { int c0, c1; };
+__device__ inline XsComps xs_comps(const SlotDesc& sd, int t, int nu) {
+  if (sd.tdil <= 1) return {0, 0};
   const int tn = t + 1 == sd.T ? 0 : t + 1;
-  return nu == 3 && tn % sd.tdil == sd.tcomp;
+  return {t % sd.tdil, nu == 3 ? tn % sd.tdil : -1};
 }
 
-template <class S, bool HPE>
+template <class S, bool HPE, bool DIL>
 __global__ __launch_bounds__(256) void k_contract_local(const SlotDesc* slots, int nslots, int total_units,
                                                         const void* s_e, const void* s_o, const void* xi_e,
                                                         const void* xi_o, const void* phi_e, const void* phi_o) {
@@ -127,8 +138,9 @@ __global__ __launch_bounds__(256) void k_contract_local(const SlotDesc* slots, i
   const void* sf = par ? s_o : s_e;
   const void* xf = par ? xi_o : xi_e;
   const void* pf = par ? phi_o : phi_e;
-  bool xs = true;
-  if constexpr (HPE) xs = xs_sites(sd, eo_coords(sd, s, par).t, -1);
+  XsComps xc{0, 0};
+  if constexpr (DIL) xc = xs_comps(sd, eo_coords(sd, s, par).t, -1);
+  bool any_xs = false;   // some rhs of the current register block had an xi-s term here
   A a[48];
 #pragma unroll
   for (int q = 0; q < 48; ++q) a[q] = (A)0;
@@ -136,6 +148,12 @@ __global__ __launch_bounds__(256) void k_contract_local(const SlotDesc* slots, i
 #pragma unroll 1
   for (int r = 0; r < sd.nrhs; ++r) {
     const long long off = sd.fo + (long long)r * vp;
+    bool xs = true;
+    if constexpr (DIL) {
+      const int comp = tdil_comp(sd, r);
+      xs = xc.c0 == comp || xc.c1 == comp;
+    }
+    any_xs = any_xs || xs;
     cx<R> sv[12];
     load_spinor<S>(field_at<S>(sf, off), vp, s, sv);
 #pragma unroll
@@ -169,11 +187,12 @@ __global__ __launch_bounds__(256) void k_contract_local(const SlotDesc* slots, i
         }
     }
     if (++inblk == AccT<S>::KB) {
-      flush<false, HPE>(acc, V, lane_off, a, xs);
+      flush<false, HPE>(acc, V, lane_off, a, any_xs);
       inblk = 0;
+      any_xs = false;
     }
   }
-  if (inblk) flush<false, HPE>(acc, V, lane_off, a, xs);
+  if (inblk) flush<false, HPE>(acc, V, lane_off, a, any_xs);
 }
 
 // Forward transport of one rhs field along nu: out = M psi(x+nu), M = b U_nu(x)
@@ -214,7 +233,7 @@ __device__ inline void transport_fwd(const void* f_other, long vp, int sp, const
 // adds F(x - nu) (a momentum phase for spatial nu, the previous time slice
 // for nu = t).  The s-s block (xi -> s) stays anti-Hermitian.  HPE: the
 // xi-s block pairs xi = eta with phi instead of s, one more transport (T_phi).
-template <class S, bool HPE>
+template <class S, bool HPE, bool DIL>
 __global__ __launch_bounds__(256) void k_contract_deriv(const SlotDesc* slots, int nslots, int total_units,
                                                         const void* s_e, const void* s_o, const void* xi_e,
                                                         const void* xi_o, const void* phi_e, const void* phi_o) {
@@ -258,8 +277,9 @@ __global__ __launch_bounds__(256) void k_contract_deriv(const SlotDesc* slots, i
   const long long V = 2ll * vp;
   double* acc = sd.acc + (long long)(48 + 48 * nu) * V;
   const int lane_off = par * (int)vp + s;
-  bool xs = true;
-  if constexpr (HPE) xs = xs_sites(sd, c.t, nu);
+  XsComps xc{0, 0};
+  if constexpr (DIL) xc = xs_comps(sd, c.t, nu);
+  bool any_xs = false;   // some rhs of the current register block had an xi-s term here
   A a[48];
 #pragma unroll
   for (int q = 0; q < 48; ++q) a[q] = (A)0;
@@ -267,6 +287,12 @@ __global__ __launch_bounds__(256) void k_contract_deriv(const SlotDesc* slots, i
 #pragma unroll 1
   for (int r = 0; r < sd.nrhs; ++r) {
     const long long off = sd.fo + (long long)r * vp;
+    bool xs = true;
+    if constexpr (DIL) {
+      const int comp = tdil_comp(sd, r);
+      xs = xc.c0 == comp || xc.c1 == comp;
+    }
+    any_xs = any_xs || xs;
     cx<R> sv[12], t[12];
     load_spinor<S>(field_at<S>(s_here, off), vp, s, sv);
     transport_fwd<S>(field_at<S>(s_other, off), vp, sp, up, cr, ci, t);   // t = T_s
@@ -323,47 +349,54 @@ __global__ __launch_bounds__(256) void k_contract_deriv(const SlotDesc* slots, i
         }
     }
     if (++inblk == AccT<S>::KB) {
-      flush<true, HPE>(acc, V, lane_off, a, xs);
+      flush<true, HPE>(acc, V, lane_off, a, any_xs);
       inblk = 0;
+      any_xs = false;
     }
   }
-  if (inblk) flush<true, HPE>(acc, V, lane_off, a, xs);
+  if (inblk) flush<true, HPE>(acc, V, lane_off, a, any_xs);
 }
 
-#define DISPATCH_PREC(prec, H, KERNEL, ...)                                                  \
+#define DISPATCH_PREC(prec, H, D, KERNEL, ...)                                               \
   switch (prec) {                                                                            \
-    case P64: hipLaunchKernelGGL((KERNEL<double, H>), __VA_ARGS__); break;                   \
-    case P32: hipLaunchKernelGGL((KERNEL<float, H>), __VA_ARGS__); break;                    \
-    case PB16: hipLaunchKernelGGL((KERNEL<bf16s, H>), __VA_ARGS__); break;                   \
-    case PH16: hipLaunchKernelGGL((KERNEL<f16s, H>), __VA_ARGS__); break;                    \
+    case P64: hipLaunchKernelGGL((KERNEL<double, H, D>), __VA_ARGS__); break;                \
+    case P32: hipLaunchKernelGGL((KERNEL<float, H, D>), __VA_ARGS__); break;                 \
+    case PB16: hipLaunchKernelGGL((KERNEL<bf16s, H, D>), __VA_ARGS__); break;                \
+    case PH16: hipLaunchKernelGGL((KERNEL<f16s, H, D>), __VA_ARGS__); break;                 \
     default: throw std::runtime_error("bad precision");                                     \
   }
 
 void launch_contract_local(int prec, const SlotDesc* slots, int nslots, int total_units, const void* s_e,
                            const void* s_o, const void* xi_e, const void* xi_o, const void* phi_e,
-                           const void* phi_o, hipStream_t st) {
+                           const void* phi_o, bool dil, hipStream_t st) {
   if (!total_units) return;
   const dim3 grid((total_units + 3) / 4), block(256);
-  if (phi_e) {
-    DISPATCH_PREC(prec, true, k_contract_local, grid, block, 0, st, slots, nslots, total_units, s_e, s_o, xi_e,
-                  xi_o, phi_e, phi_o);
+  if (phi_e && dil) {
+    DISPATCH_PREC(prec, true, true, k_contract_local, grid, block, 0, st, slots, nslots, total_units, s_e, s_o,
+                  xi_e, xi_o, phi_e, phi_o);
+  } else if (phi_e) {
+    DISPATCH_PREC(prec, true, false, k_contract_local, grid, block, 0, st, slots, nslots, total_units, s_e, s_o,
+                  xi_e, xi_o, phi_e, phi_o);
   } else {
-    DISPATCH_PREC(prec, false, k_contract_local, grid, block, 0, st, slots, nslots, total_units, s_e, s_o, xi_e,
-                  xi_o, phi_e, phi_o);
+    DISPATCH_PREC(prec, false, false, k_contract_local, grid, block, 0, st, slots, nslots, total_units, s_e, s_o,
+                  xi_e, xi_o, phi_e, phi_o);
   }
 }
 
 void launch_contract_deriv(int prec, const SlotDesc* slots, int nslots, int total_units, const void* s_e,
                            const void* s_o, const void* xi_e, const void* xi_o, const void* phi_e,
-                           const void* phi_o, hipStream_t st) {
+                           const void* phi_o, bool dil, hipStream_t st) {
   if (!total_units) return;
   const dim3 grid((total_units + 3) / 4), block(256);
-  if (phi_e) {
-    DISPATCH_PREC(prec, true, k_contract_deriv, grid, block, 0, st, slots, nslots, total_units, s_e, s_o, xi_e,
-                  xi_o, phi_e, phi_o);
+  if (phi_e && dil) {
+    DISPATCH_PREC(prec, true, true, k_contract_deriv, grid, block, 0, st, slots, nslots, total_units, s_e, s_o,
+                  xi_e, xi_o, phi_e, phi_o);
+  } else if (phi_e) {
+    DISPATCH_PREC(prec, true, false, k_contract_deriv, grid, block, 0, st, slots, nslots, total_units, s_e, s_o,
+                  xi_e, xi_o, phi_e, phi_o);
   } else {
-    DISPATCH_PREC(prec, false, k_contract_deriv, grid, block, 0, st, slots, nslots, total_units, s_e, s_o, xi_e,
-                  xi_o, phi_e, phi_o);
+    DISPATCH_PREC(prec, false, false, k_contract_deriv, grid, block, 0, st, slots, nslots, total_units, s_e, s_o,
+                  xi_e, xi_o, phi_e, phi_o);
   }
 }
 

@@ -104,12 +104,14 @@ void launch_pack_gauge(const double* src, int X, int Y, int Z, int T, void* g64,
 // xi = (1 - kappa H) s.  With phi: hopping-parameter-expanded loops without
 // tau_3, the pair (xi = eta, phi = (kappa B H)^n s), symmetrised into the flavour
 // sum (local C -> (C + g5 C^dag g5) / 2, derivative E -> (E - g5 E^dag g5) / 2).
+// dil: some slot is time-diluted (with phi: the xi-s block of an rhs is then
+// contracted only next to its component's time slices).
 void launch_contract_local(int prec, const SlotDesc* slots, int nslots, int total_units,
                            const void* s_e, const void* s_o, const void* xi_e, const void* xi_o,
-                           const void* phi_e, const void* phi_o, hipStream_t st);
+                           const void* phi_e, const void* phi_o, bool dil, hipStream_t st);
 void launch_contract_deriv(int prec, const SlotDesc* slots, int nslots, int total_units,
                            const void* s_e, const void* s_o, const void* xi_e, const void* xi_o,
-                           const void* phi_e, const void* phi_o, hipStream_t st);
+                           const void* phi_e, const void* phi_o, bool dil, hipStream_t st);
 
 // Tables of the separable momentum projection (device pointers), built on the
 // host from the momentum list: distinct kx values, distinct (kx, ky) pairs.

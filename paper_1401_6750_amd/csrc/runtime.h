@@ -120,7 +120,7 @@ struct SlotPlan {
   const void* gload;       // start this slot's CG from here (rhs 0), or null
   int gprec;               // precision of gload
   int tdil = 0;            // time dilution of the job (components per noise vector)
-  int tcomp = 0;           // component of this slot's sources
+  int tclen = 0;           // noise vectors of the job
 };
 
 struct SolveReport {

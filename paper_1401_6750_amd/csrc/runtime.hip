@@ -261,7 +261,9 @@ struct Batch {
       }
       d.src0 = sp.src0;
       d.tdil = sp.tdil;
-      d.tcomp = sp.tcomp;
+      d.tclen = sp.tclen;
+      d.tentry = sp.job_first;
+      d.job = sp.job;
       d.src_user = sp.src_user;
       d.sol_user = sp.sol_user;
       d.gsave = sp.gsave;
@@ -406,9 +408,11 @@ static void contract_passes(Batch& b, int P, const void* s_e, const void* s_o, c
     if (!merged.empty()) {
       SlotDesc& m = merged.back();
       // contiguous slots of one accumulator and lattice contract as one; time-diluted
-      // slots only within one component (the expansion's contraction depends on it)
-      if (m.acc == d.acc && m.gauge[0] == d.gauge[0] && m.fo + (long long)m.nrhs * m.Vp == d.fo &&
-          m.tdil == d.tdil && m.tcomp == d.tcomp) {
+      // slots only as consecutive entries of one job (the component of an rhs
+      // follows from its entry)
+      const bool dil_ok = (m.tdil <= 1 && d.tdil <= 1) ||
+                          (m.tdil == d.tdil && m.job == d.job && m.tentry + m.nrhs == d.tentry);
+      if (m.acc == d.acc && m.gauge[0] == d.gauge[0] && m.fo + (long long)m.nrhs * m.Vp == d.fo && dil_ok) {
         m.nrhs += d.nrhs;
         continue;
       }
@@ -427,8 +431,10 @@ static void contract_passes(Batch& b, int P, const void* s_e, const void* s_o, c
     auto& pass = passes[k];
     if (pass.empty()) continue;
     const bool hpe = k & 1;
+    bool dil = false;
     int us = 0, ud = 0;
     for (SlotDesc& d : pass) {
+      dil = dil || d.tdil > 1;
       d.ubeg[UK_SITE] = us;
       d.ubeg[UK_DERIV] = ud;
       us += 2 * d.ntile;
@@ -438,13 +444,13 @@ static void contract_passes(Batch& b, int P, const void* s_e, const void* s_o, c
     HIPCHECK(hipMemcpyAsync(ds.p, pass.data(), sizeof(SlotDesc) * pass.size(), hipMemcpyHostToDevice, b.ctx->st));
     const SlotDesc* dptr = ds.as<SlotDesc>();
     if (hpe) {
-      launch_contract_local(P, dptr, (int)pass.size(), us, s_e, s_o, h.eta[0], h.eta[1], h.loc[0], h.loc[1],
+      launch_contract_local(P, dptr, (int)pass.size(), us, s_e, s_o, h.eta[0], h.eta[1], h.loc[0], h.loc[1], dil,
                             b.ctx->st);
-      launch_contract_deriv(P, dptr, (int)pass.size(), ud, s_e, s_o, h.eta[0], h.eta[1], h.der[0], h.der[1],
+      launch_contract_deriv(P, dptr, (int)pass.size(), ud, s_e, s_o, h.eta[0], h.eta[1], h.der[0], h.der[1], dil,
                             b.ctx->st);
     } else {
-      launch_contract_local(P, dptr, (int)pass.size(), us, s_e, s_o, xi_e, xi_o, nullptr, nullptr, b.ctx->st);
-      launch_contract_deriv(P, dptr, (int)pass.size(), ud, s_e, s_o, xi_e, xi_o, nullptr, nullptr, b.ctx->st);
+      launch_contract_local(P, dptr, (int)pass.size(), us, s_e, s_o, xi_e, xi_o, nullptr, nullptr, false, b.ctx->st);
+      launch_contract_deriv(P, dptr, (int)pass.size(), ud, s_e, s_o, xi_e, xi_o, nullptr, nullptr, false, b.ctx->st);
     }
     // the descriptor buffer returns to the pool only after the stream passed it
     HIPCHECK(hipStreamSynchronize(b.ctx->st));
@@ -1131,35 +1137,37 @@ bool solve_jobs(dl_ctx* ctx, const std::vector<dl_job>& J, dl_src_stats* stats) 
           q.rhs_block > 0 ? TuneChoice{q.rhs_block, TBLK_DEFAULT} : autotune_block(ctx, q.lat, P, q.nsrc * ncomp(q));
       const int N = tc.block;
       const long long V = q.lat->V;
-      // time dilution: one slot set per component; job entries component-major
-      for (int c = 0; c < ncomp(q); ++c)
-        for (int k = 0; k < q.nsrc; k += N) {
-          const long long e = (long long)c * q.nsrc + k;   // entry of rhs 0 in the job's stats / sol_out
-          SlotPlan sp{};
-          sp.lat = q.lat;
-          sp.job = j;
-          sp.job_first = (int)e;
-          sp.nrhs = std::min(N, q.nsrc - k);
-          sp.src0 = q.first_src + k;
-          sp.src_user = q.src_in ? q.src_in + (size_t)k * V * 24 : nullptr;
-          sp.sol_user = q.sol_out ? q.sol_out + (size_t)e * V * 24 : nullptr;
-          sp.tdil = q.tdil > 1 ? q.tdil : 0;
-          sp.tcomp = c;
-          if (gbuf[j]) {
-            const size_t per = (size_t)chunks_of(P) * pad_half(q.lat->Vh) * 16;
-            sp.gsave = (char*)gbuf[j] + (size_t)e * per;
-          }
-          if (q.guess_from) {
-            const dl_job& h = J[q.guess_from - 1];
-            const int PG = tier_prec(h.tier);
-            const size_t per = (size_t)chunks_of(PG) * pad_half(h.lat->Vh) * 16;
-            sp.gload = (const char*)gbuf[q.guess_from - 1] + (size_t)e * per;
-            sp.gprec = PG;
-          }
-          sp.acc = q.accum ? q.accum->acc[q.accum_set] : nullptr;
-          sp.tblk = tc.tblk;
-          all.push_back(sp);
+      // job entries e (time dilution: component-major, e = c * nsrc + vector),
+      // N per slot; a diluted slot may span components (each rhs finds its
+      // component and noise vector from its entry)
+      const bool dil = q.tdil > 1;
+      const long long nent = (long long)q.nsrc * ncomp(q);
+      for (long long e = 0; e < nent; e += N) {
+        SlotPlan sp{};
+        sp.lat = q.lat;
+        sp.job = j;
+        sp.job_first = (int)e;
+        sp.nrhs = (int)std::min<long long>(N, nent - e);
+        sp.src0 = dil ? q.first_src : q.first_src + e;
+        sp.src_user = q.src_in ? q.src_in + (dil ? 0 : (size_t)e * V * 24) : nullptr;
+        sp.sol_user = q.sol_out ? q.sol_out + (size_t)e * V * 24 : nullptr;
+        sp.tdil = dil ? q.tdil : 0;
+        sp.tclen = q.nsrc;
+        if (gbuf[j]) {
+          const size_t per = (size_t)chunks_of(P) * pad_half(q.lat->Vh) * 16;
+          sp.gsave = (char*)gbuf[j] + (size_t)e * per;
         }
+        if (q.guess_from) {
+          const dl_job& h = J[q.guess_from - 1];
+          const int PG = tier_prec(h.tier);
+          const size_t per = (size_t)chunks_of(PG) * pad_half(h.lat->Vh) * 16;
+          sp.gload = (const char*)gbuf[q.guess_from - 1] + (size_t)e * per;
+          sp.gprec = PG;
+        }
+        sp.acc = q.accum ? q.accum->acc[q.accum_set] : nullptr;
+        sp.tblk = tc.tblk;
+        all.push_back(sp);
+      }
     }
     // batches bounded by device memory and right-hand-side count
     size_t i = 0;
@@ -1197,7 +1205,8 @@ bool solve_jobs(dl_ctx* ctx, const std::vector<dl_job>& J, dl_src_stats* stats) 
           }
         }
         const dl_job& q = J[sp.job];
-        if (q.accum && sp.tcomp == 0) q.accum->count[q.accum_set] += sp.nrhs;   // noise vectors
+        if (q.accum)   // noise vectors: the entries of component 0
+          q.accum->count[q.accum_set] += std::max(0, std::min(sp.job_first + sp.nrhs, q.nsrc) - sp.job_first);
       }
     }
   }

@@ -65,7 +65,7 @@ def test_fp64_diluted_solutions_match_oracle(ctx, lat):
     sol = zeros_dev((nsrc * D,) + lat.field_shape)
     rc, stats = dl.dl_solve_batch(ctx, dl.make_job(lat.h, noise=dl.DL_NOISE_Z2, tier=dl.DL_TIER_FP64, seed=seed,
                                                    first_src=5, nsrc=nsrc, tol=1e-10, maxiter=1000, tdil=D,
-                                                   report_true_resid=1, sol_out=sol))
+                                                   rhs_block=4, report_true_resid=1, sol_out=sol))
     assert rc == dl.DL_OK and len(stats) == nsrc * D
     got = host(sol)
     for c in range(D):
@@ -99,14 +99,16 @@ def test_fp64_diluted_one_end_loops_match_oracle(ctx, lat, D):
     dl.dl_accum_destroy(acc)
 
 
-@pytest.mark.parametrize("D", [3, 6])
-def test_fp64_diluted_hpe_loops_match_oracle(ctx, lat, D):
-    log("diluted hpe D", D)
+@pytest.mark.parametrize("D,block", [(3, 1), (3, 3), (6, 5)])
+def test_fp64_diluted_hpe_loops_match_oracle(ctx, lat, D, block):
+    """Slots of one component (block 1) and slots that span components (3, 5)."""
+    log("diluted hpe D", D, "block", block)
     seed, nsrc, p2, n = 43, 2, 2, 4
     acc = dl.dl_accum_create(lat.h, dl.DL_OPS_LOCAL | dl.DL_OPS_DERIV | dl.DL_OPS_HPE(n))
     rc, _ = dl.dl_solve_batch(ctx, dl.make_job(lat.h, noise=dl.DL_NOISE_Z4, tier=dl.DL_TIER_FP64, seed=seed,
-                                               nsrc=nsrc, tol=1e-11, maxiter=1000, tdil=D, rhs_block=1,
+                                               nsrc=nsrc, tol=1e-11, maxiter=1000, tdil=D, rhs_block=block,
                                                accum=acc, accum_set=dl.DL_SET_HP))
+    assert dl.dl_accum_counts(acc) == [0, nsrc, 0]
     assert rc == dl.DL_OK
     npm = len(loops.momenta(p2, lat.dims))
     sets = np.zeros((3, 2, 5, 16, lat.dims[3], npm), dtype=np.complex128)
@@ -119,7 +121,7 @@ def test_fp64_diluted_hpe_loops_match_oracle(ctx, lat, D):
 
 
 def test_user_sources_are_diluted_like_generated_ones(ctx, lat):
-    seed, nsrc, D, p2 = 44, 2, 2, 1
+    seed, nsrc, D, p2 = 44, 3, 2, 1
     src = dev(np.stack([noise.source(lat.dims, seed, r, noise.Z4) for r in range(nsrc)]))
     npm = len(loops.momenta(p2, lat.dims))
     outs = []
@@ -140,7 +142,7 @@ def test_diluted_lp_maps_and_hp_guesses(ctx, lat):
     seed, nsrc, D, p2 = 45, 4, 3, 2
     npm = len(loops.momenta(p2, lat.dims))
     outs = []
-    for block in (1, 4):
+    for block in (1, 4, 5):
         acc = dl.dl_accum_create(lat.h, dl.DL_OPS_LOCAL | dl.DL_OPS_DERIV | dl.DL_OPS_HPE(4))
         dl.dl_solve_batch(ctx, dl.make_job(lat.h, noise=dl.DL_NOISE_Z4, tier=dl.DL_TIER_LP_BF16, seed=seed,
                                            nsrc=nsrc, tol=1e-2, maxiter=500, rhs_block=block, tdil=D, accum=acc,
@@ -149,12 +151,12 @@ def test_diluted_lp_maps_and_hp_guesses(ctx, lat):
         dl.dl_loops_sets(ctx, acc, p2, out, 0)
         outs.append(out)
         dl.dl_accum_destroy(acc)
-    assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
     sol = zeros_dev((nsrc * D,) + lat.field_shape)
     jobs = [dl.make_job(lat.h, noise=dl.DL_NOISE_Z4, tier=dl.DL_TIER_HP_FP32, seed=seed, nsrc=nsrc, tol=1e-8,
-                        maxiter=2000, tdil=D, sol_out=sol, guess_from=2),
+                        maxiter=2000, tdil=D, sol_out=sol, guess_from=2, rhs_block=5),
             dl.make_job(lat.h, noise=dl.DL_NOISE_Z4, tier=dl.DL_TIER_LP_BF16, seed=seed, nsrc=nsrc, tol=1e-2,
-                        maxiter=500, tdil=D)]
+                        maxiter=500, tdil=D, rhs_block=3)]
     rc, stats = dl.dl_solve_batch(ctx, jobs)
     assert rc == dl.DL_OK and len(stats) == 2 * nsrc * D
     got = host(sol)
