@@ -249,6 +249,9 @@ def main() -> int:
     ap.add_argument("--tdil", type=int, default=0,
                     help="time dilution: D components per noise vector (the noise-vector counts are "
                          "divided by D so the number of solves stays the same); 0: off")
+    ap.add_argument("--p2max", type=int, default=-1,
+                    help="momentum cut |n|^2 <= p2max of the projection (default: the workload's; "
+                         "a cut >= 3 (L/2)^2 keeps every momentum)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparator", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
@@ -279,6 +282,8 @@ def main() -> int:
     X, Y, Z, T = dims
     noise_kind = dl.DL_NOISE_Z4 if tw["noise"] == "Z4" else dl.DL_NOISE_Z2
     n_lp, n_hp, p2 = tw["n_lp"], tw["n_hp"], tw["p2max"]
+    if a.p2max >= 0:
+        p2 = a.p2max
     ncomp = max(a.tdil, 1)
     v_lp, v_hp = n_lp // ncomp, n_hp // ncomp      # noise vectors; n_lp, n_hp stay the solve counts
     n_lp, n_hp = v_lp * ncomp, v_hp * ncomp
@@ -349,6 +354,13 @@ def main() -> int:
     ms = (t1 - t0) * 1e3 / a.steps
     log(f"timed {a.steps} steps: {ms:.1f} ms/step")
     assert rc == dl.DL_OK, f"solve status {rc}"
+    # projection + Gamma rebuild + TSM combination alone (part of every step above)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(3):
+        dl.dl_loops(ctx, acc, p2, out, 1)
+    torch.cuda.synchronize()
+    loops_ms = (time.perf_counter() - t) * 1e3 / 3
     it_lp = [s.iters for s in st[:n_lp]]
     it_hp = [s.iters for s in st[n_lp:n_lp + n_hp]]
     ru_hp = [s.reliable_updates for s in st[n_lp:n_lp + n_hp]]
@@ -431,6 +443,7 @@ def main() -> int:
                    "hpe_order": a.hpe, "tdil": a.tdil},
         "iters_lp_mean": round(float(np.mean(it_lp)), 2), "iters_hp_mean": round(float(np.mean(it_hp)), 2),
         "reliable_updates_hp_mean": round(float(np.mean(ru_hp)), 2),
+        "momenta": nmom, "projection_ms": round(loops_ms, 2),
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

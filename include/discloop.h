@@ -87,7 +87,7 @@ extern "C" {
 #define DL_OPS_LOCAL 1
 #define DL_OPS_DERIV 2
 /* Hopping parameter expansion of the loops without tau_3 (one of the variance
- * reductions of the interfaces, Section 2.4), order n = 1..4, or'ed into the
+ * reductions of the interfaces, Section 2.3), order n = 1..4, or'ed into the
  * ops of dl_accum_create.  With B = A^-1, A = 1 + 2 i kappa mu gamma_5 and
  * M = A - kappa H, M^-1 = sum_{k<n} (kappa B H)^k B + (kappa B H)^n M^-1: the
  * first sum is added exactly (its elements used here do not depend on the gauge
@@ -180,7 +180,10 @@ int dl_lattice_destroy(dl_lattice* lat);
  * The caller keeps ownership of `links`. */
 int dl_gauge_set(dl_lattice* lat, const double* links, int on_device);
 
-/* Set kappa and mu of the operator (mu != 0, kappa > 0). */
+/* Set kappa (> 0) and mu of the operator.  mu = 0 is the Wilson operator
+ * (Section 2.4 expects the code to carry over to Wilson-type fermions): u and
+ * d coincide, the loops with tau_3 vanish and those without it are the plain
+ * Wilson loops, tr Gamma 2 D_W^-1; dl_loops_backward then gives no dF/dmu. */
 int dl_set_params(dl_lattice* lat, double kappa, double mu);
 
 /* ---- solves and loops -------------------------------------------------- */

@@ -3,7 +3,7 @@
 Test infrastructure: a plain CPU reference, used only by the tests and the
 benchmark's CPU baseline; it shares no code with the HIP library.
 
-The paper lists the HPE (Section 2.4, the interfaces) among the variance
+The paper lists the HPE (Section 2.3, the interfaces) among the variance
 reduction methods it combines with the TSM, without printing a formula.  The
 reading used here:
 

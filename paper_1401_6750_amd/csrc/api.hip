@@ -156,7 +156,7 @@ int dl_set_params(dl_lattice* lat, double kappa, double mu) {
   return guarded([&] {
     require(lat != nullptr, "dl_set_params: NULL lattice");
     require(std::isfinite(kappa) && kappa > 0, "dl_set_params: kappa must be > 0");
-    require(std::isfinite(mu) && mu != 0, "dl_set_params: mu must be nonzero (one-end trick)");
+    require(std::isfinite(mu), "dl_set_params: mu must be finite");
     lat->kappa = kappa;
     lat->mu = mu;
     lat->params_set = true;

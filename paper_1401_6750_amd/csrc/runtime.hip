@@ -1227,6 +1227,8 @@ void loops_backward(dl_ctx* ctx, const dl_job& job, int p2max, const double* gra
   if (p2max < 0) throw Error(DL_EINVAL, "dl_loops_backward: p2max must be >= 0");
   if (!(job.tol > 0) || job.maxiter < 1) throw Error(DL_EINVAL, "dl_loops_backward: bad tol / maxiter");
   if (job.noise == DL_NOISE_USER && !job.src_in) throw Error(DL_EINVAL, "dl_loops_backward: USER noise needs src_in");
+  if (grad_mu && L->mu == 0)   // the tau_3 term of dF/dmu is taken as (1/mu) x its mu-weighted sum
+    throw Error(DL_EINVAL, "dl_loops_backward: dF/dmu needs mu != 0");
   (void)tier_prec(job.tier);
   hipStream_t st = ctx->st;
   const int nops = job.accum ? ((job.accum->ops & DL_OPS_DERIV) ? 5 : 1) : 5;

@@ -518,7 +518,7 @@ def test_edge_cases(ctx):
         dl.dl_lattice_create(ctx, (4, 4, 3, 4))
     assert e.value.code == dl.DL_EINVAL
     with pytest.raises(dl.DiscloopError):
-        dl.dl_set_params(lat.h, 0.16, 0.0)
+        dl.dl_set_params(lat.h, 0.16, float("nan"))
     with pytest.raises(dl.DiscloopError):
         dl.dl_solve_batch(ctx, dl.make_job(lat.h, nsrc=1, tol=-1))
     # LPC set must mirror the HP set
