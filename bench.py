@@ -37,6 +37,7 @@ WORKLOADS = {
     "uneven": None,
     "grad_16x16x16x32": None,
     "dslash_sweep": None,
+    "tsm_error_16x16x16x32": None,
 }
 
 # serving-shaped mix of lattices: (dims, eps, LP sources); kappa 0.1615, mu 0.004
@@ -225,6 +226,119 @@ def bench_grad(a) -> int:
     return 0
 
 
+def bench_error(a) -> int:
+    """Same final accuracy: the truncated solver method against plain FP64 solves at
+    equal standard error of one loop, on 16^3x32 (Z2 sources).
+
+    The observable is the tau_3 loop with Gamma_15 = gamma_5 at p = 0 summed over t.
+    TSM: 200 LP (bf16, rho 1e-2) + 10 HP (fp32 + RU, rho 1e-8, started from the LPC
+    solutions) + the 10 LPC solves; its standard error is the jackknife error of 10
+    bins (20 LP + 1 HP + 1 LPC each, every bin a complete TSM estimate).  Plain: FP64
+    solves to rho 1e-8; the per-source variance from 10 bins of 4 sources gives the
+    number of plain sources N_eq with the TSM's error, timed single-rhs (the
+    comparator path) and batched."""
+    import numpy as np
+    import torch
+
+    import paper_1401_6750_amd as dl
+    import synth
+    w = synth.WORKLOADS["tsm_16x16x16x32"]
+    dims = w["dims"]
+    ctx = dl.dl_create(0, torch.cuda.current_stream().cuda_stream)
+    lat, _ = _setup_lattice(dl, torch, synth, ctx, dims, w["gauge_seed"], w["eps"], w["kappa"], w["mu"])
+    seed, nb, n_lp, n_hp, p2 = w["source_seed"], 10, 200, 10, 0
+    ops = dl.DL_OPS_LOCAL
+    Z2 = dl.DL_NOISE_Z2
+
+    def tsm_jobs(acc, lp0, nlp, hp0, nhp):
+        return [dl.make_job(lat, noise=Z2, tier=dl.DL_TIER_LP_BF16, seed=seed, first_src=lp0, nsrc=nlp, tol=1e-2,
+                            maxiter=500, accum=acc, accum_set=dl.DL_SET_LP),
+                dl.make_job(lat, noise=Z2, tier=dl.DL_TIER_HP_FP32, seed=seed, first_src=hp0, nsrc=nhp, tol=1e-8,
+                            maxiter=2000, accum=acc, accum_set=dl.DL_SET_HP, guess_from=3),
+                dl.make_job(lat, noise=Z2, tier=dl.DL_TIER_LP_BF16, seed=seed, first_src=hp0, nsrc=nhp, tol=1e-2,
+                            maxiter=500, accum=acc, accum_set=dl.DL_SET_LPC)]
+
+    def observable(acc):
+        out = np.zeros((2, 1, 16, dims[3], 1), dtype=np.complex128)
+        dl.dl_loops(ctx, acc, p2, out, 0)
+        return out[0, 0, 15, :, 0].sum()
+
+    def timed(fn, reps=2):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps
+
+    # TSM: the production step (one accumulator), timed
+    acc = dl.dl_accum_create(lat, ops)
+
+    def tsm_step():
+        dl.dl_accum_reset(acc)
+        dl.dl_solve_batch(ctx, tsm_jobs(acc, 0, n_lp, n_lp, n_hp))
+        return observable(acc)
+
+    t_tsm = timed(tsm_step)
+    est_tsm = tsm_step()
+    # TSM errors from bins
+    accs = [dl.dl_accum_create(lat, ops) for _ in range(nb)]
+    jobs = []
+    for b in range(nb):
+        jobs += tsm_jobs(accs[b], b * (n_lp // nb), n_lp // nb, n_lp + b * (n_hp // nb), n_hp // nb)
+    for j, q in enumerate(jobs):
+        if q.guess_from:
+            q.guess_from = j + 2          # the LPC job right after it
+    rc, _ = dl.dl_solve_batch(ctx, jobs)
+    assert rc == dl.DL_OK
+    bins_tsm = np.array([observable(x) for x in accs])
+    for x in accs:
+        dl.dl_accum_destroy(x)
+    err_tsm = float(np.sqrt(np.mean(np.abs(bins_tsm - bins_tsm.mean()) ** 2) / (nb - 1)))
+    # plain FP64: per-source variance from bins of 4
+    per_bin = 4
+    accs = [dl.dl_accum_create(lat, ops) for _ in range(nb)]
+    rc, _ = dl.dl_solve_batch(ctx, [dl.make_job(lat, noise=Z2, tier=dl.DL_TIER_FP64, seed=seed,
+                                                first_src=10_000 + b * per_bin, nsrc=per_bin, tol=1e-8,
+                                                maxiter=2000, accum=accs[b], accum_set=dl.DL_SET_HP)
+                                    for b in range(nb)])
+    assert rc == dl.DL_OK
+    bins_plain = np.array([observable(x) for x in accs])
+    for x in accs:
+        dl.dl_accum_destroy(x)
+    var_plain = per_bin * float(np.sum(np.abs(bins_plain - bins_plain.mean()) ** 2) / (nb - 1))
+    n_eq = var_plain / err_tsm ** 2
+    # plain FP64 time per source: single-rhs without graph (the comparator), and batched
+    acc1 = dl.dl_accum_create(lat, ops)
+
+    def plain(n, single):
+        dl.dl_accum_reset(acc1)
+        if single:
+            dl.dl_set_option(ctx, "inflight_rhs", 1)
+            dl.dl_set_option(ctx, "use_graph", 0)
+        dl.dl_solve_batch(ctx, dl.make_job(lat, noise=Z2, tier=dl.DL_TIER_FP64, seed=seed, first_src=20_000,
+                                           nsrc=n, tol=1e-8, maxiter=2000, rhs_block=1 if single else 0,
+                                           accum=acc1, accum_set=dl.DL_SET_HP))
+        observable(acc1)
+        dl.dl_set_option(ctx, "inflight_rhs", 1024)
+        dl.dl_set_option(ctx, "use_graph", 1)
+
+    t_single = timed(lambda: plain(4, True), reps=1) / 4
+    t_batch = timed(lambda: plain(64, False), reps=1) / 64
+    res = {"metric": "TSM time to equal standard error vs plain FP64 (tau_3 gamma_5 loop, p=0)",
+           "value": round(n_eq * t_single / t_tsm, 2), "unit": "x (plain FP64 single-rhs time / TSM time)",
+           "higher_is_better": True, "tsm_ms": round(t_tsm * 1e3, 2), "tsm_estimate": [est_tsm.real, est_tsm.imag],
+           "tsm_error": err_tsm, "plain_per_source_sigma": var_plain ** 0.5, "plain_sources_for_equal_error":
+           round(n_eq, 1), "plain_fp64_single_rhs_ms_per_source": round(t_single * 1e3, 2),
+           "plain_fp64_batched_ms_per_source": round(t_batch * 1e3, 2),
+           "vs_plain_fp64_batched": round(n_eq * t_batch / t_tsm, 2),
+           "config": {"workload": "tsm_error_16x16x16x32", "n_lp": n_lp, "n_hp": n_hp, "bins": nb,
+                      "plain_bins": [nb, per_bin], "noise": "Z2", "insertions": "local", "p2max": p2}}
+    print(json.dumps(res), flush=True)
+    return 0
+
+
 def kernel_hash() -> str:
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
@@ -276,6 +390,8 @@ def main() -> int:
         return bench_grad(a)
     if a.workload == "dslash_sweep":
         return bench_sweep(a)
+    if a.workload == "tsm_error_16x16x16x32":
+        return bench_error(a)
     w = synth.WORKLOADS[a.workload]
     tw = WORKLOADS[a.workload]
     dims, kappa, mu = w["dims"], w["kappa"], w["mu"]
