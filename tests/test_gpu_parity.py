@@ -473,6 +473,41 @@ def test_full_size_hop_sampled(ctx, name):
     lat.close()
 
 
+def test_full_size_loops_from_gpu_solutions(ctx):
+    """24^3 x 48, the bench's LP tier (bf16) and contraction kernels with two slots
+    merged into one contraction launch (as the bench's slots are): the per-set loop sums at p = 0 equal the
+    oracle's loops of the solutions the GPU returned.  Local tau_3 structure (s only,
+    exact bf16 values, FP32 block sums): 1e-5; derivative insertions transport with
+    the tier's bf16 links, and the structure without tau_3 reads xi = (1 - kappa H) s
+    stored in bf16 (2^-9 rounding per element): 1.6e-2 and 2e-2."""
+    w = synth.WORKLOADS["batched_24x24x24x48"]
+    log("full size loops 24^3x48")
+    lat = make_lattice(ctx, w["dims"], w["gauge_seed"], w["eps"], w["kappa"], w["mu"])
+    nsrc, p2 = 2, 0                        # the oracle takes ~40 s per source here
+    acc = dl.dl_accum_create(lat.h, dl.DL_OPS_LOCAL | dl.DL_OPS_DERIV)
+    sol = zeros_dev((nsrc,) + lat.field_shape)
+    rc, _ = dl.dl_solve_batch(ctx, dl.make_job(lat.h, noise=dl.DL_NOISE_Z4, tier=dl.DL_TIER_LP_BF16,
+                                               seed=w["source_seed"], nsrc=nsrc, tol=1e-2, maxiter=500, rhs_block=1,
+                                               sol_out=sol, accum=acc, accum_set=dl.DL_SET_LP))
+    assert rc == dl.DL_OK
+    sets = np.zeros((3, 2, 5, 16, lat.dims[3], 1), dtype=np.complex128)
+    dl.dl_loops_sets(ctx, acc, p2, sets, 0)
+    dl.dl_accum_destroy(acc)
+    sols = host(sol)
+    del sol
+    want = 0
+    for r in range(nsrc):
+        want = want + loops.apply_prefactors(loops.source_loops(lat.U, sols[r], lat.kappa, lat.bc, p2, lat.dims),
+                                             lat.kappa, lat.mu)
+    for f in range(2):
+        for op in range(5):
+            tol = 2e-2 if f else (1e-5 if op == 0 else 1.6e-2)
+            e = rel(sets[dl.DL_SET_LP, f, op], want[f, op])
+            log("  flavour", f, "op", op, "rel err", e)
+            assert e < tol, (f, op, e)
+    lat.close()
+
+
 def test_full_size_fp64_solve_true_residual(ctx):
     """16^3 x 32 FP64 solve: the oracle's own operator confirms the residual."""
     w = synth.WORKLOADS["tsm_16x16x16x32"]
