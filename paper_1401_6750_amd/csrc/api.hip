@@ -401,22 +401,36 @@ static int loops_device(dl_ctx* ctx, dl_accum* a, int p2max, const double (*w)[3
     pj[p] = j;
   }
   const int nkx = (int)kxs.size(), nkxy = (int)pairs.size();
+  // distinct kz values, and the z-sum's thread order (kz, then pair)
+  std::vector<int> kzs, pk(np), order(np);
+  for (int p = 0; p < np; ++p) {
+    const int kz = moms[p][2];
+    int k = (int)(std::find(kzs.begin(), kzs.end(), kz) - kzs.begin());
+    if (k == (int)kzs.size()) kzs.push_back(kz);
+    pk[p] = k;
+    order[p] = p;
+  }
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return pk[a] != pk[b] ? pk[a] < pk[b] : pj[a] < pj[b]; });
+  const int nkz = (int)kzs.size();
   auto phase = [](double n, int x, int ext, double* out) {
     const double ang = -2.0 * M_PI * n * x / ext;
     out[0] = std::cos(ang);
     out[1] = std::sin(ang);
   };
-  std::vector<double> tabs;   // px | py | pz | shift, complex
-  const size_t o_px = 0, o_py = o_px + 2ull * nkx * X, o_pz = o_py + 2ull * nkxy * Y,
-               o_sh = o_pz + 2ull * np * Z, n_tab = o_sh + 6ull * np;
+  std::vector<double> tabs;   // roots x | roots y | pz | shift, complex
+  const size_t o_px = 0, o_py = o_px + 2ull * X, o_pz = o_py + 2ull * Y,
+               o_sh = o_pz + 2ull * nkz * Z, n_tab = o_sh + 6ull * np;
   tabs.resize(std::max<size_t>(n_tab, 2));
-  for (int k = 0; k < nkx; ++k)
-    for (int x = 0; x < X; ++x) phase(kxs[k], x, X, &tabs[o_px + 2 * ((size_t)k * X + x)]);
-  for (int k = 0; k < nkxy; ++k)
-    for (int y = 0; y < Y; ++y) phase(pairs[k][1], y, Y, &tabs[o_py + 2 * ((size_t)k * Y + y)]);
+  for (int x = 0; x < X; ++x) phase(1, x, X, &tabs[o_px + 2 * (size_t)x]);
+  for (int y = 0; y < Y; ++y) phase(1, y, Y, &tabs[o_py + 2 * (size_t)y]);
+  std::vector<int> kx_mod(nkx), ky_mod(nkxy);
+  for (int k = 0; k < nkx; ++k) kx_mod[k] = ((kxs[k] % X) + X) % X;
+  for (int k = 0; k < nkxy; ++k) ky_mod[k] = ((pairs[k][1] % Y) + Y) % Y;
   const int ext[3] = {X, Y, Z};
+  for (int k = 0; k < nkz; ++k)
+    for (int z = 0; z < Z; ++z) phase(kzs[k], z, Z, &tabs[o_pz + 2 * ((size_t)k * Z + z)]);
   for (int p = 0; p < np; ++p) {
-    for (int z = 0; z < Z; ++z) phase(moms[p][2], z, Z, &tabs[o_pz + 2 * ((size_t)p * Z + z)]);
     for (int nu = 0; nu < 3; ++nu) {
       double* f = &tabs[o_sh + 2 * ((size_t)p * 3 + nu)];
       phase(moms[p][nu], 1, ext[nu], f);
@@ -425,6 +439,10 @@ static int loops_device(dl_ctx* ctx, dl_accum* a, int p2max, const double (*w)[3
   }
   std::vector<int> itab(pair_ix);
   itab.insert(itab.end(), pj.begin(), pj.end());
+  itab.insert(itab.end(), pk.begin(), pk.end());
+  itab.insert(itab.end(), order.begin(), order.end());
+  itab.insert(itab.end(), kx_mod.begin(), kx_mod.end());
+  itab.insert(itab.end(), ky_mod.begin(), ky_mod.end());
   DevBuf dtab(ctx, tabs.size() * sizeof(double)), ditab(ctx, std::max<size_t>(itab.size(), 1) * sizeof(int));
   HIPCHECK(hipMemcpyAsync(dtab.p, tabs.data(), tabs.size() * sizeof(double), hipMemcpyHostToDevice, ctx->st));
   if (!itab.empty())
@@ -432,8 +450,10 @@ static int loops_device(dl_ctx* ctx, dl_accum* a, int p2max, const double (*w)[3
   ProjTables tb{};
   tb.np = np; tb.nkx = nkx; tb.nkxy = nkxy;
   const double* dt = dtab.as<double>();
-  tb.px = dt + o_px; tb.py = dt + o_py; tb.pz = dt + o_pz; tb.shift = dt + o_sh;
+  tb.roots_x = dt + o_px; tb.roots_y = dt + o_py; tb.pz = dt + o_pz; tb.shift = dt + o_sh;
   tb.pair_ix = ditab.as<int>(); tb.pj = ditab.as<int>() + nkxy;
+  tb.pk = tb.pj + np; tb.order = tb.pk + np;
+  tb.kx_mod = tb.order + np; tb.ky_mod = tb.kx_mod + nkx;
   const int nops = (a->ops & DL_OPS_DERIV) ? 5 : 1;
   const size_t per_out = (size_t)2 * 2 * nops * 16 * T * np;   // doubles
   const size_t pbytes = std::max<size_t>(sizeof(double) * 2 * (size_t)a->nq * T * np, 16);

@@ -117,11 +117,15 @@ void launch_contract_deriv(int prec, const SlotDesc* slots, int nslots, int tota
 // host from the momentum list: distinct kx values, distinct (kx, ky) pairs.
 struct ProjTables {
   int np, nkx, nkxy;
-  const double* px;     // [nkx][X] complex e^{-2 pi i kx x / X}
-  const double* py;     // [nkxy][Y] complex e^{-2 pi i ky y / Y}, ky of pair j
+  const double* roots_x;  // [X] complex e^{-2 pi i m / X}
+  const double* roots_y;  // [Y] complex e^{-2 pi i m / Y}
+  const int* kx_mod;    // [nkx] kx mod X of distinct value ix
+  const int* ky_mod;    // [nkxy] ky mod Y of pair j
   const int* pair_ix;   // [nkxy] kx index of pair j
-  const double* pz;     // [np][Z] complex e^{-2 pi i kz z / Z}
+  const double* pz;     // [nkz][Z] complex e^{-2 pi i kz z / Z}, kz of distinct value k
   const int* pj;        // [np] pair index of momentum p
+  const int* pk;        // [np] distinct-kz index of momentum p
+  const int* order;     // [np] momenta sorted by (kz, pair): the z-sum's thread order
   const double* shift;  // [np][3] complex 1 + e^{-2 pi i n_nu / L_nu}
 };
 // proj [nq][T][Np] complex = projection of sum_k w[k] acc[k] (null sets

@@ -12,16 +12,22 @@ namespace dl {
 // of the TSM-combined accumulator value v = sum_sets w_set acc_set.
 // Stage 1+2 (one workgroup per (q, t, z) plane): the plane goes to LDS, is
 // summed over x for every distinct kx, then over y for every distinct
-// (kx, ky) pair of the momentum list.  Stage 3 (one thread per (q, t, p)):
+// (kx, ky) pair of the momentum list (twiddles from LDS roots of unity).  Stage 3 (one thread per (q, t, p)):
 // the sum over z.  Each accumulator value is read once, in whole rows.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_proj_plane(const double* a0, const double* a1, const double* a2, double w0,
                                                     double w1, double w2, int X, int Y, int Z, int T, long long vp,
-                                                    int nkx, int nkxy, const double2* px, const double2* py,
+                                                    int nkx, int nkxy, const double2* roots_x,
+                                                    const double2* roots_y, const int* kx_mod, const int* ky_mod,
                                                     const int* pair_ix, double2* r2) {
+  // LDS: the plane v[Y][X], its x-transform r1[Y][nkx], the roots of unity
+  // e^{-2 pi i m / X} and e^{-2 pi i m / Y}; the twiddle of (k, x) is root
+  // (k x mod X), stepped by k per x.
   extern __shared__ double lds[];
-  double* v = lds;                               // [Y][X]
-  double2* r1 = (double2*)(lds + X * Y);         // [Y][nkx]
+  double* v = lds;                                   // [Y][X]
+  double2* r1 = (double2*)(lds + X * Y);             // [Y][nkx]
+  double2* wx = r1 + Y * nkx;                        // [X]
+  double2* wy = wx + X;                              // [Y]
   int b = blockIdx.x;
   const int z = b % Z;
   b /= Z;
@@ -40,28 +46,39 @@ __global__ __launch_bounds__(256) void k_proj_plane(const double* a0, const doub
     if (a2) val += w2 * a2[k];
     v[y * X + x] = val;
   }
+  for (int i = threadIdx.x; i < X; i += blockDim.x) wx[i] = roots_x[i];
+  for (int i = threadIdx.x; i < Y; i += blockDim.x) wy[i] = roots_y[i];
   __syncthreads();
   for (int o = threadIdx.x; o < Y * nkx; o += blockDim.x) {
     const int y = o / nkx, ix = o - y * nkx;
-    const double2* ph = px + (long long)ix * X;
+    const int m = kx_mod[ix];
+    const double* row = v + y * X;
     double re = 0.0, im = 0.0;
+    int idx = 0;
+#pragma unroll 4
     for (int x = 0; x < X; ++x) {
-      const double val = v[y * X + x];
-      re += val * ph[x].x;
-      im += val * ph[x].y;
+      const double val = row[x];
+      const double2 f = wx[idx];
+      re += val * f.x;
+      im += val * f.y;
+      idx += m;
+      if (idx >= X) idx -= X;
     }
     r1[o] = make_double2(re, im);
   }
   __syncthreads();
   double2* out = r2 + ((long long)(q * T + t) * Z + z) * nkxy;
   for (int j = threadIdx.x; j < nkxy; j += blockDim.x) {
-    const int ix = pair_ix[j];
-    const double2* ph = py + (long long)j * Y;
+    const int ix = pair_ix[j], m = ky_mod[j];
     double re = 0.0, im = 0.0;
+    int idx = 0;
+#pragma unroll 4
     for (int y = 0; y < Y; ++y) {
-      const double2 a = r1[y * nkx + ix], f = ph[y];
+      const double2 a = r1[y * nkx + ix], f = wy[idx];
       re += a.x * f.x - a.y * f.y;
       im += a.x * f.y + a.y * f.x;
+      idx += m;
+      if (idx >= Y) idx -= Y;
     }
     out[j] = make_double2(re, im);
   }
@@ -71,16 +88,18 @@ __global__ __launch_bounds__(256) void k_proj_plane(const double* a0, const doub
 // (nu = (q - q_link) / 48) whose site value is F(x) + F(x - nu): spatial nu
 // multiplies the projection by 1 + e^{-2 pi i n_nu / L_nu}, nu = t adds the
 // projection of time slice t - 1 (periodic wrap; the boundary sign is inside F).
+// Threads take the momenta in (kz, pair) order: neighbouring lanes read
+// neighbouring r2 entries and share the kz twiddles.
 __global__ __launch_bounds__(256) void k_proj_z(const double2* r2, int nq, int q_link, int Z, int T, int np, int nkxy,
-                                                const double2* pz, const int* pj, const double2* shift,
-                                                double2* proj) {
+                                                const double2* pz, const int* pj, const int* pk, const int* order,
+                                                const double2* shift, double2* proj) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (long long)nq * T * np) return;
-  const int p = (int)(i % np);
+  const int p = order[(int)(i % np)];
   const long long qt = i / np;
   const int t = (int)(qt % T), q = (int)(qt / T);
   const int j = pj[p];
-  const double2* ph = pz + (long long)p * Z;
+  const double2* ph = pz + (long long)pk[p] * Z;
   auto zsum = [&](int tt) {
     const double2* row = r2 + (long long)(q * T + tt) * Z * nkxy + j;
     double re = 0.0, im = 0.0;
@@ -103,21 +122,22 @@ __global__ __launch_bounds__(256) void k_proj_z(const double2* r2, int nq, int q
       r.y += o.y;
     }
   }
-  proj[i] = r;
+  proj[qt * np + p] = r;
 }
 
 void launch_project(const double* const acc[3], const double w[3], int nq, int q_link, int X, int Y, int Z, int T,
                     const ProjTables& tb, double* r2, double* proj, hipStream_t st) {
   if (tb.np <= 0 || nq <= 0) return;
   const long long vp = pad_half((long long)X * Y * Z * T / 2);
-  const size_t lds = sizeof(double) * (size_t)X * Y + sizeof(double2) * (size_t)Y * tb.nkx;
+  const size_t lds = sizeof(double) * (size_t)X * Y + sizeof(double2) * ((size_t)Y * tb.nkx + X + Y);
   if (lds > 65536) throw std::runtime_error("momentum projection: x-y plane too large for LDS");
   hipLaunchKernelGGL(k_proj_plane, dim3((unsigned)(nq * T * Z)), dim3(256), lds, st, acc[0], acc[1], acc[2], w[0],
-                     w[1], w[2], X, Y, Z, T, vp, tb.nkx, tb.nkxy, (const double2*)tb.px, (const double2*)tb.py,
-                     tb.pair_ix, (double2*)r2);
+                     w[1], w[2], X, Y, Z, T, vp, tb.nkx, tb.nkxy, (const double2*)tb.roots_x,
+                     (const double2*)tb.roots_y, tb.kx_mod, tb.ky_mod, tb.pair_ix, (double2*)r2);
   const long long n = (long long)nq * T * tb.np;
   hipLaunchKernelGGL(k_proj_z, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (const double2*)r2, nq, q_link,
-                     Z, T, tb.np, tb.nkxy, (const double2*)tb.pz, tb.pj, (const double2*)tb.shift, (double2*)proj);
+                     Z, T, tb.np, tb.nkxy, (const double2*)tb.pz, tb.pj, tb.pk, tb.order, (const double2*)tb.shift,
+                     (double2*)proj);
 }
 
 // ---------------------------------------------------------------------------
