@@ -131,4 +131,7 @@ WORKLOADS = {
                             gauge_seed=1402, source_seed=6751),
     "batched_24x24x24x48": dict(dims=(24, 24, 24, 48), eps=0.2, kappa=0.1615, mu=0.004,
                                 gauge_seed=1403, source_seed=6752),
+    # the volume of the paper's ensembles (largest size the tests run)
+    "paper_32x32x32x64": dict(dims=(32, 32, 32, 64), eps=0.2, kappa=0.1615, mu=0.004,
+                              gauge_seed=1404, source_seed=6753),
 }

@@ -454,7 +454,7 @@ def _boundary_sites(dims, rng, n):
     return pick
 
 
-@pytest.mark.parametrize("name", ["tsm_16x16x16x32", "batched_24x24x24x48"])
+@pytest.mark.parametrize("name", ["tsm_16x16x16x32", "batched_24x24x24x48", "paper_32x32x32x64"])
 def test_full_size_hop_sampled(ctx, name):
     w = synth.WORKLOADS[name]
     dims = w["dims"]
@@ -505,6 +505,29 @@ def test_full_size_loops_from_gpu_solutions(ctx):
             e = rel(sets[dl.DL_SET_LP, f, op], want[f, op])
             log("  flavour", f, "op", op, "rel err", e)
             assert e < tol, (f, op, e)
+    lat.close()
+
+
+def test_largest_size_tiers_true_residual(ctx):
+    """32^3 x 64 (the volume of the paper's ensembles): bf16 LP and FP32 + reliable-update
+    HP solves; the oracle's FP64 operator recomputes each returned solution's true
+    residual, which must agree with the library's report and meet the tier's target."""
+    w = synth.WORKLOADS["paper_32x32x32x64"]
+    log("largest size tiers 32^3x64")
+    lat = make_lattice(ctx, w["dims"], w["gauge_seed"], w["eps"], w["kappa"], w["mu"])
+    for tier, tol in ((dl.DL_TIER_LP_BF16, 1e-2), (dl.DL_TIER_HP_FP32, 1e-8)):
+        sol = zeros_dev((1,) + lat.field_shape)
+        rc, stats = dl.dl_solve_batch(ctx, dl.make_job(lat.h, noise=dl.DL_NOISE_Z4, tier=tier, seed=w["source_seed"],
+                                                       nsrc=1, tol=tol, maxiter=2000, report_true_resid=1,
+                                                       sol_out=sol))
+        assert rc == dl.DL_OK
+        eta = noise.source(w["dims"], w["source_seed"], 0, noise.Z4)
+        tr = solver.true_residual(lat.U, eta, host(sol)[0], lat.kappa, lat.mu, lat.bc)
+        log("  tier", tier, "iters", stats[0].iters, "true resid", tr, "reported", stats[0].true_resid)
+        assert abs(stats[0].true_resid - tr) < 1e-6 * tr + 1e-12
+        # rho bounds the iterated normal-equation residual; the true one is looser
+        assert tr < (5 if tier == dl.DL_TIER_LP_BF16 else 10) * tol, tr   # measured 1.03e-2, 8.8e-9
+        del sol
     lat.close()
 
 
