@@ -12,7 +12,12 @@
  *   - one-end-trick contractions for all ultra-local and one-derivative
  *     insertions, with and without tau_3 (Section 2.1.1, Section 2.2),
  *     accumulated over sources on the GPU (the all-GPU scheme of Section 2.4,
- *     Fig. 4) and projected to momenta with a p^2 cut (Section 2.3).
+ *     Fig. 4) and projected to momenta with a p^2 cut (Section 2.3);
+ *   - the options the interfaces combine with them: per-set partial sums for
+ *     base-2 storage (Section 2.1.1, Fig. 2; dl_loops_sets), the hopping
+ *     parameter expansion of the loops without tau_3 (Section 2.3;
+ *     DL_OPS_HPE), time-diluted sources (Section 2.2; dl_job.tdil), and the
+ *     Wilson operator as mu = 0 (Section 2.4).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
