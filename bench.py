@@ -35,6 +35,7 @@ WORKLOADS = {
     "tsm_16x16x16x32": dict(n_lp=200, n_hp=10, p2max=4, noise="Z2"),
     # not TSM steps of one lattice: see bench_uneven / bench_grad / bench_sweep
     "uneven": None,
+    "uneven_small": None,
     "grad_16x16x16x32": None,
     "dslash_sweep": None,
     "tsm_error_16x16x16x32": None,
@@ -43,6 +44,10 @@ WORKLOADS = {
 # serving-shaped mix of lattices: (dims, eps, LP sources); kappa 0.1615, mu 0.004
 UNEVEN = [((8, 8, 8, 8), 0.1, 64), ((8, 8, 8, 8), 0.3, 4), ((16, 16, 16, 32), 0.2, 32),
           ((16, 16, 16, 32), 0.1, 8), ((24, 24, 24, 48), 0.3, 16), ((24, 24, 24, 48), 0.2, 4)]
+# many small lattices, where one call per lattice is launch-bound
+UNEVEN_SMALL = [((8, 8, 8, 8), round(0.1 + 0.05 * (i % 4), 2), 8 + 8 * (i % 3)) for i in range(8)] + \
+               [((12, 12, 12, 12), 0.2, 16), ((12, 12, 12, 24), 0.2, 8), ((16, 16, 16, 16), 0.2, 8),
+                ((8, 8, 8, 16), 0.3, 24)]
 
 
 def _setup_lattice(dl, torch, synth, ctx, dims, seed, eps, kappa, mu):
@@ -110,11 +115,12 @@ def bench_sweep(a) -> int:
     return 0
 
 
-def bench_uneven(a) -> int:
-    """Uneven batch: six lattices (8^4 .. 24^3x48) solved in one dl_solve_batch
-    call (shared launches) against one call per lattice.  Per lattice: FP16 LP
-    sources at rho = 1e-2, n/8 HP sources (FP32 + FP64 reliable updates) at 1e-8
-    and their LPC solves, all with local + derivative contractions."""
+def bench_uneven(a, table=UNEVEN, name="uneven") -> int:
+    """Uneven batch: lattices of different sizes (six from 8^4 to 24^3x48, or twelve
+    small ones) solved in one dl_solve_batch call (shared launches) against one
+    call per lattice.  Per lattice: FP16 LP sources at rho = 1e-2, n/8 HP sources
+    (FP32 + FP64 reliable updates) at 1e-8 and their LPC solves, all with local +
+    derivative contractions."""
     import numpy as np
     import torch
 
@@ -124,13 +130,13 @@ def bench_uneven(a) -> int:
     ctx = dl.dl_create(0, torch.cuda.current_stream().cuda_stream)
     dl.dl_set_option(ctx, "inflight_mb", a.inflight_mb)
     lats, accs = [], []
-    for i, (dims, eps, n) in enumerate(UNEVEN):
+    for i, (dims, eps, n) in enumerate(table):
         lat, _ = _setup_lattice(dl, torch, synth, ctx, dims, 1410 + i, eps, 0.1615, 0.004)
         lats.append(lat)
         accs.append(dl.dl_accum_create(lat, dl.DL_OPS_LOCAL | dl.DL_OPS_DERIV))
 
     def jobs(i):
-        lat, acc, n = lats[i], accs[i], UNEVEN[i][2]
+        lat, acc, n = lats[i], accs[i], table[i][2]
         nh = max(1, n // 8)
         return [dl.make_job(lat, noise=dl.DL_NOISE_Z2, tier=dl.DL_TIER_LP_FP16, seed=6760 + i, nsrc=n, tol=1e-2,
                             maxiter=500, accum=acc, accum_set=dl.DL_SET_LP),
@@ -142,7 +148,7 @@ def bench_uneven(a) -> int:
     def together():
         for acc in accs:
             dl.dl_accum_reset(acc)
-        dl.dl_solve_batch(ctx, [j for i in range(len(UNEVEN)) for j in jobs(i)])
+        dl.dl_solve_batch(ctx, [j for i in range(len(table)) for j in jobs(i)])
 
     def separate():
         for i, acc in enumerate(accs):
@@ -160,12 +166,12 @@ def bench_uneven(a) -> int:
         return (time.perf_counter() - t) / a.steps
 
     t_tog, t_sep = timed(together), timed(separate)
-    n_lp = sum(n for _, _, n in UNEVEN)
+    n_lp = sum(n for _, _, n in table)
     res = {"metric": "uneven batch LP solves/s (one call for all lattices)", "value": round(n_lp / t_tog, 2),
            "unit": "LP solves/s", "ms_per_step": round(t_tog * 1e3, 2), "ms_per_step_separate_calls":
            round(t_sep * 1e3, 2), "batched_vs_separate": round(t_sep / t_tog, 3), "steps": a.steps,
-           "config": {"workload": "uneven", "lattices": [f"{'x'.join(map(str, d))} eps={e} n_lp={n}"
-                                                         for d, e, n in UNEVEN]}}
+           "config": {"workload": name, "lattices": [f"{'x'.join(map(str, d))} eps={e} n_lp={n}"
+                                                     for d, e, n in table]}}
     print(json.dumps(res), flush=True)
     return 0
 
@@ -386,6 +392,8 @@ def main() -> int:
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if a.workload == "uneven":
         return bench_uneven(a)
+    if a.workload == "uneven_small":
+        return bench_uneven(a, UNEVEN_SMALL, "uneven_small")
     if a.workload == "grad_16x16x16x32":
         return bench_grad(a)
     if a.workload == "dslash_sweep":
