@@ -117,6 +117,68 @@ __device__ inline XsComps xs_comps(const SlotDesc& sd, int t, int nu) {
   return {t % sd.tdil, nu == 3 ? tn % sd.tdil : -1};
 }
 
+// ---------------------------------------------------------------------------
+// 16-bit fields: the products run on the packed (re, im) words with the dot2
+// instructions, two products per instruction, accumulating into the FP32
+// register sums.  Products of stored 16-bit values are exact in FP32; a
+// transported vector (an FP32 colour product) is rounded to the storage format
+// first, as the field it came from was.
+// ---------------------------------------------------------------------------
+__device__ inline void load_words16(const void* f, long vp, int s, uint32_t (&w)[12]) {
+  const uint4* q = (const uint4*)f;
+  const uint4 q0 = q[s], q1 = q[vp + s], q2 = q[2 * vp + s];
+  w[0] = q0.x; w[1] = q0.y; w[2] = q0.z; w[3] = q0.w;
+  w[4] = q1.x; w[5] = q1.y; w[6] = q1.z; w[7] = q1.w;
+  w[8] = q2.x; w[9] = q2.y; w[10] = q2.z; w[11] = q2.w;
+}
+// (im, -re) of a packed (re, im) pair: Im(conj(a) b) = dot2(a, iq16(b)).
+__device__ inline uint32_t iq16(uint32_t w) { return swap16(w) ^ 0x80000000u; }
+// both halves negated
+__device__ inline uint32_t neg16(uint32_t w) { return w ^ 0x80008000u; }
+
+template <class S, bool HPE>
+__device__ inline void local_rhs16(const void* sf, const void* xf, const void* pf, long long off, long vp, int s,
+                                   bool xs, float (&a)[48]) {
+  uint32_t sw[12];
+  load_words16(field_at<S>(sf, off), vp, s, sw);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    float v = a[i];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v = dot2<S>(sw[3 * i + c], sw[3 * i + c], v);
+    a[i] = v;
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    float re = a[4 + 2 * k], im = a[5 + 2 * k];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      re = dot2<S>(sw[3 * up_a(k) + c], sw[3 * up_b(k) + c], re);
+      im = dot2<S>(sw[3 * up_a(k) + c], iq16(sw[3 * up_b(k) + c]), im);
+    }
+    a[4 + 2 * k] = re;
+    a[5 + 2 * k] = im;
+  }
+  if (xs) {
+    uint32_t xw[12];
+    load_words16(field_at<S>(xf, off), vp, s, xw);
+    if constexpr (HPE) load_words16(field_at<S>(pf, off), vp, s, sw);   // phi from here on
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float re = a[16 + 2 * (4 * i + j)], im = a[17 + 2 * (4 * i + j)];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          re = dot2<S>(xw[3 * i + c], sw[3 * j + c], re);
+          im = dot2<S>(xw[3 * i + c], iq16(sw[3 * j + c]), im);
+        }
+        a[16 + 2 * (4 * i + j)] = re;
+        a[17 + 2 * (4 * i + j)] = im;
+      }
+  }
+}
+
 template <class S, bool HPE, bool DIL>
 __global__ __launch_bounds__(256) void k_contract_local(const SlotDesc* slots, int nslots, int total_units,
                                                         const void* s_e, const void* s_o, const void* xi_e,
@@ -154,6 +216,9 @@ __global__ __launch_bounds__(256) void k_contract_local(const SlotDesc* slots, i
       xs = xc.c0 == comp || xc.c1 == comp;
     }
     any_xs = any_xs || xs;
+    if constexpr (Traits<S>::NC == 3) {
+      local_rhs16<S, HPE>(sf, xf, pf, off, vp, s, xs, a);
+    } else {
     cx<R> sv[12];
     load_spinor<S>(field_at<S>(sf, off), vp, s, sv);
 #pragma unroll
@@ -185,6 +250,7 @@ __global__ __launch_bounds__(256) void k_contract_local(const SlotDesc* slots, i
           a[16 + 2 * (4 * i + j)] += (A)t.re;
           a[17 + 2 * (4 * i + j)] += (A)t.im;
         }
+    }
     }
     if (++inblk == AccT<S>::KB) {
       flush<false, HPE>(acc, V, lane_off, a, any_xs);
@@ -221,6 +287,100 @@ __device__ inline void transport_fwd(const void* f_other, long vp, int sp, const
         out[3 * s4 + a] = f;
       }
   }
+}
+
+// T = (colour product of v) as packed words: (re, im) in tp, (im, -re) in tq.
+template <class S>
+__device__ inline void pack_transport(const uint32_t (&cr)[9], const uint32_t (&ci)[9], const uint32_t (&v)[12],
+                                      uint32_t (&tp)[12], uint32_t (&tq)[12]) {
+  cx<float> t[12];
+  colour_mul16<S>(cr, ci, v, t);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    tp[k] = pack2<S>(t[k]);
+    tq[k] = pack2<S>(mk<float>(t[k].im, -t[k].re));
+  }
+}
+
+// One rhs of the link-centred derivative contraction on 16-bit fields (the
+// same sums as the generic body below; constant factors at the flush).
+template <class S, bool HPE>
+__device__ inline void deriv_rhs16(const void* s_here, const void* s_other, const void* x_here, const void* x_other,
+                                   const void* f_here, const void* f_other, long long off, long vp, int s, int sp,
+                                   const uint32_t (&cr)[9], const uint32_t (&ci)[9], bool xs, float (&a)[48]) {
+  uint32_t sw[12], w[12], tp[12], tq[12];
+  load_words16(field_at<S>(s_here, off), vp, s, sw);
+  load_words16(field_at<S>(s_other, off), vp, sp, w);
+  pack_transport<S>(cr, ci, w, tp, tq);                     // T_s
+  // s-s block: F_aa = (i/2) Im sum_c conj(s_a) T_a; off the diagonal
+  // conj(s_a) T_b - conj(T_a) s_b
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    float v = a[i];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v = dot2<S>(sw[3 * i + c], tq[3 * i + c], v);
+    a[i] = v;
+  }
+#pragma unroll
+  for (int k6 = 0; k6 < 6; ++k6) {
+    const int ia = up_a(k6), ib = up_b(k6);
+    float re = a[4 + 2 * k6], im = a[5 + 2 * k6];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      re = dot2<S>(sw[3 * ia + c], tp[3 * ib + c], re);
+      re = dot2<S>(neg16(sw[3 * ib + c]), tp[3 * ia + c], re);
+      im = dot2<S>(sw[3 * ia + c], tq[3 * ib + c], im);
+      im = dot2<S>(sw[3 * ib + c], tq[3 * ia + c], im);
+    }
+    a[4 + 2 * k6] = re;
+    a[5 + 2 * k6] = im;
+  }
+  if (!xs) return;
+  // xi-s block, first half: conj(xi_a) T_phi,b (phi = s unless HPE)
+  uint32_t xw[12];
+  load_words16(field_at<S>(x_here, off), vp, s, xw);
+  if constexpr (HPE) {
+    load_words16(field_at<S>(f_other, off), vp, sp, w);
+    pack_transport<S>(cr, ci, w, tp, tq);                   // T_phi
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float re = a[16 + 2 * (4 * i + j)], im = a[17 + 2 * (4 * i + j)];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        re = dot2<S>(xw[3 * i + c], tp[3 * j + c], re);
+        im = dot2<S>(xw[3 * i + c], tq[3 * j + c], im);
+      }
+      a[16 + 2 * (4 * i + j)] = re;
+      a[17 + 2 * (4 * i + j)] = im;
+    }
+  // second half: - conj(T_xi,a) phi_b, with (-re, -im) and (-re, im) of T_xi
+  if constexpr (HPE) load_words16(field_at<S>(f_here, off), vp, s, sw);   // phi
+  load_words16(field_at<S>(x_other, off), vp, sp, w);
+  {
+    cx<float> t[12];
+    colour_mul16<S>(cr, ci, w, t);                          // T_xi
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      tp[k] = pack2<S>(mk<float>(-t[k].re, -t[k].im));
+      tq[k] = pack2<S>(mk<float>(-t[k].re, t[k].im));
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float re = a[16 + 2 * (4 * i + j)], im = a[17 + 2 * (4 * i + j)];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        re = dot2<S>(tp[3 * i + c], sw[3 * j + c], re);
+        im = dot2<S>(tq[3 * i + c], swap16(sw[3 * j + c]), im);
+      }
+      a[16 + 2 * (4 * i + j)] = re;
+      a[17 + 2 * (4 * i + j)] = im;
+    }
 }
 
 // One-derivative contractions in link-centred form.  With T_psi(x) =
@@ -293,6 +453,9 @@ __global__ __launch_bounds__(256) void k_contract_deriv(const SlotDesc* slots, i
       xs = xc.c0 == comp || xc.c1 == comp;
     }
     any_xs = any_xs || xs;
+    if constexpr (Traits<S>::NC == 3) {
+      deriv_rhs16<S, HPE>(s_here, s_other, x_here, x_other, f_here, f_other, off, vp, s, sp, cr, ci, xs, a);
+    } else {
     cx<R> sv[12], t[12];
     load_spinor<S>(field_at<S>(s_here, off), vp, s, sv);
     transport_fwd<S>(field_at<S>(s_other, off), vp, sp, up, cr, ci, t);   // t = T_s
@@ -347,6 +510,7 @@ __global__ __launch_bounds__(256) void k_contract_deriv(const SlotDesc* slots, i
           a[16 + 2 * (4 * i + j)] -= (A)w.re;
           a[17 + 2 * (4 * i + j)] -= (A)w.im;
         }
+    }
     }
     if (++inblk == AccT<S>::KB) {
       flush<true, HPE>(acc, V, lane_off, a, any_xs);

@@ -4,8 +4,9 @@ FP64 oracle, through the C ABI.
 FP64 solves: every order 1..4, local and derivative insertions, per-set sums and the
 normalised estimate to 1e-10 relative, on a lattice with a ragged tile tail.  The
 storage-precision tiers are compared with the oracle evaluated on the solutions the
-GPU returned (so only the expansion's arithmetic differs): FP32 to 5e-6, bf16 to a few
-units of its 2^-8 storage rounding; the bf16 maps are bit-identical across slot shapes.
+GPU returned (so only the expansion's arithmetic differs): FP32 to 5e-6, bf16 and fp16 to
+a few units of their 2^-8 / 2^-11 storage rounding; the bf16 maps are bit-identical across
+slot shapes.
 """
 import sys
 
@@ -99,7 +100,8 @@ def test_local_only_hpe_accumulator(ctx, lat):
     dl.dl_accum_destroy(acc)
 
 
-@pytest.mark.parametrize("tier,tol", [(dl.DL_TIER_HP_FP32, 5e-6), (dl.DL_TIER_LP_BF16, 2e-2)])
+@pytest.mark.parametrize("tier,tol", [(dl.DL_TIER_HP_FP32, 5e-6), (dl.DL_TIER_LP_BF16, 2e-2),
+                                      (dl.DL_TIER_LP_FP16, 4e-3)])
 def test_storage_precision_hpe_against_oracle_on_gpu_solutions(ctx, lat, tier, tol):
     seed, nsrc, p2, n = 33, 4, 3, 4
     log("hpe tier", tier)
