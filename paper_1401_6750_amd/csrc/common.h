@@ -109,18 +109,70 @@ template <> __device__ inline float dot2<f16s>(uint32_t a, uint32_t b, float c) 
 }
 // First product of a chain: the three-operand form with an inline zero
 // accumulator (the two-operand form accumulates into its destination and
-// would need the register cleared first).
+// would need the register cleared first).  The compiler cannot see that the
+// asm holds a dot2, whose result a different vector instruction (the
+// accumulating two-operand form included) may read only after three wait
+// states, so the asm supplies them.
 template <class S> __device__ inline float dot2_first(uint32_t a, uint32_t b);
 template <> __device__ inline float dot2_first<bf16s>(uint32_t a, uint32_t b) {
   float r;
-  asm("v_dot2_f32_bf16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
+  asm("v_dot2_f32_bf16 %0, %1, %2, 0\n\ts_nop 2" : "=v"(r) : "v"(a), "v"(b));
   return r;
 }
 template <> __device__ inline float dot2_first<f16s>(uint32_t a, uint32_t b) {
   float r;
-  asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
+  asm("v_dot2_f32_f16 %0, %1, %2, 0\n\ts_nop 2" : "=v"(r) : "v"(a), "v"(b));
   return r;
 }
+// Six chained dot2 products in one asm block, x = sum_k a_k . b_k, the first
+// three with the input modifiers (L1, H1) on a_k, the last three with (L2, H2):
+// neg_lo / neg_hi flip the sign of the low / high half of a_k, the same
+// products as a_k with those sign bits XOR-ed, without the XOR.  Inside the
+// block each product takes the previous sum as its accumulator, which the
+// hardware forwards between dot2 instructions of one opcode; the block ends
+// with three wait states, because a dot2 result must not be read sooner by a
+// different vector instruction and the compiler cannot see what the block
+// holds.
+#define DL_NEG00 ""
+#define DL_NEG10 " neg_lo:[1,0,0]"
+#define DL_NEG01 " neg_hi:[1,0,0]"
+#define DL_NEG11 " neg_lo:[1,0,0] neg_hi:[1,0,0]"
+template <class S, int L1, int H1, int L2, int H2> struct Chain6;
+#define DL_CHAIN6(S, INSTR, L1, H1, L2, H2)                                                                  \
+  template <> struct Chain6<S, L1, H1, L2, H2> {                                                             \
+    __device__ static inline float run(uint32_t a0, uint32_t a1, uint32_t a2, uint32_t a3, uint32_t a4,      \
+                                       uint32_t a5, uint32_t b0, uint32_t b1, uint32_t b2, uint32_t b3,      \
+                                       uint32_t b4, uint32_t b5) {                                           \
+      float x;                                                                                               \
+      asm(INSTR " %0, %1, %7, 0" DL_NEG##L1##H1 "\n\t"                                                       \
+          INSTR " %0, %2, %8, %0" DL_NEG##L1##H1 "\n\t"                                                      \
+          INSTR " %0, %3, %9, %0" DL_NEG##L1##H1 "\n\t"                                                      \
+          INSTR " %0, %4, %10, %0" DL_NEG##L2##H2 "\n\t"                                                     \
+          INSTR " %0, %5, %11, %0" DL_NEG##L2##H2 "\n\t"                                                     \
+          INSTR " %0, %6, %12, %0" DL_NEG##L2##H2 "\n\t"                                                     \
+          "s_nop 2"                                                                                          \
+          : "=&v"(x)                                                                                         \
+          : "v"(a0), "v"(a1), "v"(a2), "v"(a3), "v"(a4), "v"(a5), "v"(b0), "v"(b1), "v"(b2), "v"(b3),        \
+            "v"(b4), "v"(b5));                                                                               \
+      return x;                                                                                              \
+    }                                                                                                        \
+  };
+#define DL_CHAIN6_H2(S, INSTR, L1, H1, L2) DL_CHAIN6(S, INSTR, L1, H1, L2, 0) DL_CHAIN6(S, INSTR, L1, H1, L2, 1)
+#define DL_CHAIN6_L2(S, INSTR, L1, H1) DL_CHAIN6_H2(S, INSTR, L1, H1, 0) DL_CHAIN6_H2(S, INSTR, L1, H1, 1)
+#define DL_CHAIN6_H1(S, INSTR, L1) DL_CHAIN6_L2(S, INSTR, L1, 0) DL_CHAIN6_L2(S, INSTR, L1, 1)
+#define DL_CHAIN6_ALL(S, INSTR) DL_CHAIN6_H1(S, INSTR, 0) DL_CHAIN6_H1(S, INSTR, 1)
+DL_CHAIN6_ALL(bf16s, "v_dot2_f32_bf16")
+DL_CHAIN6_ALL(f16s, "v_dot2_f32_f16")
+#undef DL_CHAIN6_ALL
+#undef DL_CHAIN6_H1
+#undef DL_CHAIN6_L2
+#undef DL_CHAIN6_H2
+#undef DL_CHAIN6
+#undef DL_NEG00
+#undef DL_NEG10
+#undef DL_NEG01
+#undef DL_NEG11
+
 __device__ inline uint32_t swap16(uint32_t w) { return (w >> 16) | (w << 16); }
 
 // Colour-product coefficients of one link for the packed path: row a of

@@ -7,11 +7,11 @@
 // right-hand sides.  Units of one tile are consecutive for all right-hand-side
 // groups of the slot, tiles are visited in time-blocked order (tile_of), and
 // each XCD receives a contiguous range of units, so a tile's links are
-// fetched once into that XCD's L2.  In 16-bit storage the kernel is bound by
-// instruction issue rather than HBM bandwidth, so the design minimises
+// fetched once into that XCD's L2.  In 16-bit storage the design minimises
 // per-(site, rhs) work that is not arithmetic of the hop: the colour
-// products run on the packed 16-bit words (dot2), conversions use the packed
-// hardware converts, neighbour indices are offsets of the lexicographic index.
+// products run on the packed 16-bit words (dot2) with every sign taken as an
+// input modifier, conversions use the packed hardware converts, neighbour
+// indices are offsets of the lexicographic index.
 //
 // Operator pieces (kappa normalised, chiral basis, gamma_5 = diag(1,1,-1,-1)):
 //   (H psi)(x) = sum_mu (1 - gamma_mu) U_mu(x) psi(x+mu) + (1 + gamma_mu) U_mu(x-mu)^dag psi(x-mu)
@@ -230,44 +230,65 @@ __device__ inline void hop_load16(HopWords<G>& h, const void* gauge, long vp, in
   }
 }
 
+// Coefficient operand of the packed colour products: the link word w (SW =
+// false) or its half-swapped form (SW = true), with the signs of its low / high
+// half flipped (NLO / NHI) by the dot2 input modifiers, so no instruction is
+// spent on signs.  Row a of U (forward) or U^dag (backward):
+//   forward:  cr = (Re U_ab, -Im U_ab) = w with NHI,  ci = (Im U_ab, Re U_ab) = swap(w)
+//   backward: cr = (Re U_ba,  Im U_ba) = w,            ci = (-Im U_ba, Re U_ba) = swap(w) with NLO
+// and the projection factors -1, +i, -i of the second spin component select
+// -cr, -ci, ci for the real part (-ci, cr, -cr for the imaginary part).
+template <bool SW, int NLO, int NHI>
+struct Coef16 {
+  static constexpr bool sw = SW;
+  static constexpr int lo = NLO, hi = NHI;
+};
+template <class O> using NegOf = Coef16<O::sw, 1 - O::lo, 1 - O::hi>;
+template <bool FWD> using CrOf = Coef16<false, 0, FWD ? 1 : 0>;
+template <bool FWD> using CiOf = Coef16<true, FWD ? 0 : 1, 0>;
+// projection code c (0: +1, 1: -1, 2: +i, 3: -i) -> operands of the real and imaginary part
+template <int C, bool FWD>
+using ProjRe = std::conditional_t<C == 0, CrOf<FWD>, std::conditional_t<C == 1, NegOf<CrOf<FWD>>,
+               std::conditional_t<C == 2, NegOf<CiOf<FWD>>, CiOf<FWD>>>>;
+template <int C, bool FWD>
+using ProjIm = std::conditional_t<C == 0, CiOf<FWD>, std::conditional_t<C == 1, NegOf<CiOf<FWD>>,
+               std::conditional_t<C == 2, CrOf<FWD>, NegOf<CrOf<FWD>>>>>;
+
+// Re or Im of one colour row of M (h_a + c h_b): three products with the
+// operand O1 on spin sa and three with O2 on spin sb.
+template <class S, class O1, class O2>
+__device__ inline float chain16(const uint32_t (&w)[3], const uint32_t (&sw)[3], const uint32_t (&v)[12], int sa,
+                                int sb) {
+  return Chain6<S, O1::lo, O1::hi, O2::lo, O2::hi>::run(
+      O1::sw ? sw[0] : w[0], O1::sw ? sw[1] : w[1], O1::sw ? sw[2] : w[2], O2::sw ? sw[0] : w[0],
+      O2::sw ? sw[1] : w[1], O2::sw ? sw[2] : w[2], v[3 * sa], v[3 * sa + 1], v[3 * sa + 2], v[3 * sb],
+      v[3 * sb + 1], v[3 * sb + 2]);
+}
+
 // The arithmetic of one hop, one colour row a at a time (only that row's
-// coefficient words are live).
+// link words are live).
 template <class S, int MU, bool FWD, bool INIT, int G>
 __device__ inline void hop_compute16(const HopWords<G>& h, float sign, const bool (&act)[G],
                                      cx<float> (&acc)[G][12]) {
   using PS = ProjSpec<MU, FWD>;
+  using Cr = CrOf<FWD>;
+  using Ci = CiOf<FWD>;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    uint32_t cr[3], ci[3];
+    uint32_t w[3], sw[3];
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-      const uint32_t w = FWD ? h.e[3 * a + b] : h.e[3 * b + a];
-      cr[b] = FWD ? (w ^ 0x80000000u) : w;
-      ci[b] = FWD ? swap16(w) : (swap16(w) ^ 0x00008000u);
-    }
-    uint32_t pr0[3], pi0[3], pr1[3], pi1[3];
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      const uint32_t ncr = cr[b] ^ 0x80008000u, nci = ci[b] ^ 0x80008000u;
-      pr0[b] = PS::c0 == 0 ? cr[b] : (PS::c0 == 1 ? ncr : (PS::c0 == 2 ? nci : ci[b]));
-      pi0[b] = PS::c0 == 0 ? ci[b] : (PS::c0 == 1 ? nci : (PS::c0 == 2 ? cr[b] : ncr));
-      pr1[b] = PS::c1 == 0 ? cr[b] : (PS::c1 == 1 ? ncr : (PS::c1 == 2 ? nci : ci[b]));
-      pi1[b] = PS::c1 == 0 ? ci[b] : (PS::c1 == 1 ? nci : (PS::c1 == 2 ? cr[b] : ncr));
+      w[b] = FWD ? h.e[3 * a + b] : h.e[3 * b + a];
+      sw[b] = swap16(w[b]);
     }
 #pragma unroll
     for (int i = 0; i < G; ++i) {
       if (!act[i]) continue;
       const uint32_t (&v)[12] = h.v[i];
-      auto chain = [&](const uint32_t (&c)[3], int sa, const uint32_t (&p)[3], int sb) {
-        float x = dot2_first<S>(c[0], v[3 * sa]);
-        x = dot2<S>(c[1], v[3 * sa + 1], x);
-        x = dot2<S>(c[2], v[3 * sa + 2], x);
-        x = dot2<S>(p[0], v[3 * sb], x);
-        x = dot2<S>(p[1], v[3 * sb + 1], x);
-        return dot2<S>(p[2], v[3 * sb + 2], x);
-      };
-      const cx<float> w0 = mk<float>(chain(cr, 0, pr0, PS::b0), chain(ci, 0, pi0, PS::b0));
-      const cx<float> w1 = mk<float>(chain(cr, 1, pr1, PS::b1), chain(ci, 1, pi1, PS::b1));
+      const cx<float> w0 = mk<float>(chain16<S, Cr, ProjRe<PS::c0, FWD>>(w, sw, v, 0, PS::b0),
+                                     chain16<S, Ci, ProjIm<PS::c0, FWD>>(w, sw, v, 0, PS::b0));
+      const cx<float> w1 = mk<float>(chain16<S, Cr, ProjRe<PS::c1, FWD>>(w, sw, v, 1, PS::b1),
+                                     chain16<S, Ci, ProjIm<PS::c1, FWD>>(w, sw, v, 1, PS::b1));
       reconstruct_row<MU, FWD, INIT>(acc[i], a, w0, w1, sign);
     }
   }
