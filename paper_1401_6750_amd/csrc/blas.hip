@@ -465,18 +465,20 @@ __global__ __launch_bounds__(256) void k_pack_gauge(const double* src, int X, in
   const int par = (x + y + z + t) & 1;
   const long long s = lex >> 1;
   const double2* u = (const double2*)src + (lex * 4 + mu) * 9;
-  const long long rec = (long long)(mu * 2 + par) * vp + s;   // link record index
-  double2* r64 = (double2*)g64 + rec * 9;
-  float2* r32 = (float2*)g32 + rec * 10;                      // 5 chunks = 10 complex
-  uint32_t* rb = (uint32_t*)gb16 + rec * 12;                  // 3 chunks = 12 complex
-  uint32_t* rh = (uint32_t*)gh16 + rec * 12;
+  // chunk rows [mu][parity][chunk][site] of vp sites (common.h)
+  const long long row = (long long)(mu * 2 + par);
+  double2* r64 = (double2*)g64;
+  float2* r32 = (float2*)g32;        // 5 chunks of 2 complex
+  uint32_t* rb = (uint32_t*)gb16;    // 3 chunks of 4 complex
+  uint32_t* rh = (uint32_t*)gh16;
   for (int e = 0; e < 12; ++e) {
     const double2 q = e < 9 ? u[e] : make_double2(0.0, 0.0);  // zero padding
-    if (e < 9) r64[e] = q;
-    if (e < 10) r32[e] = make_float2((float)q.x, (float)q.y);
+    if (e < 9) r64[(row * 9 + e) * vp + s] = q;
+    if (e < 10) r32[((row * 5 + e / 2) * vp + s) * 2 + e % 2] = make_float2((float)q.x, (float)q.y);
     const cx<float> qf = mk<float>((float)q.x, (float)q.y);
-    rb[e] = pack2<bf16s>(qf);
-    rh[e] = pack2<f16s>(qf);
+    const long long w16 = ((row * 3 + e / 4) * vp + s) * 4 + e % 4;
+    rb[w16] = pack2<bf16s>(qf);
+    rh[w16] = pack2<f16s>(qf);
   }
 }
 

@@ -5,8 +5,12 @@
 //                                                index within the parity
 //       FP64: 12 chunks of 1 complex, FP32: 6 chunks of 2 complex,
 //       bf16 / fp16: 3 chunks of 4 complex.  Component k = 3 * spin + colour.
-//   gauge field:                  [mu][parity][entry 9][site]  one complex
-//                                                element per (mu, parity, entry, site)
+//   gauge field:                  [mu][parity][chunk][site]  16-byte chunks in rows
+//                                                of the padded half volume, so a wave's
+//                                                link loads are contiguous like its
+//                                                spinor loads.  FP64: 9 chunks of 1
+//                                                complex, FP32: 5 of 2 (one padding),
+//                                                bf16 / fp16: 3 of 4 (three padding)
 //   loop accumulators (FP64):     [component q][full e/o site = parity * Vh + site]
 //
 // A "batch" interleaves several lattices and right-hand sides: rhs r of slot i
@@ -347,29 +351,29 @@ __device__ inline void load_link(const void* g, long vh, int mu, int par, long s
 
 template <>
 __device__ inline void load_link<double>(const void* g, long vh, int mu, int par, long s, cx<double> (&u)[9]) {
-  const double2* p = (const double2*)g + ((long)(mu * 2 + par) * vh + s) * 9;
+  const double2* p = (const double2*)g + (long)(mu * 2 + par) * 9 * vh + s;
 #pragma unroll
   for (int e = 0; e < 9; ++e) {
-    double2 w = p[e];
+    double2 w = p[e * vh];
     u[e] = {w.x, w.y};
   }
 }
 template <>
 __device__ inline void load_link<float>(const void* g, long vh, int mu, int par, long s, cx<float> (&u)[9]) {
-  const float4* p = (const float4*)g + ((long)(mu * 2 + par) * vh + s) * 5;
+  const float4* p = (const float4*)g + (long)(mu * 2 + par) * 5 * vh + s;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    float4 w = p[k];
+    float4 w = p[k * vh];
     u[2 * k] = {w.x, w.y};
     u[2 * k + 1] = {w.z, w.w};
   }
-  float4 w = p[4];
+  float4 w = p[4 * vh];
   u[8] = {w.x, w.y};
 }
 template <class S16>
 __device__ inline void load_link16(const void* g, long vh, int mu, int par, long s, cx<float> (&u)[9]) {
-  const uint4* p = (const uint4*)g + ((long)(mu * 2 + par) * vh + s) * 3;
-  const uint4 a = p[0], b = p[1], c = p[2];
+  const uint4* p = (const uint4*)g + (long)(mu * 2 + par) * 3 * vh + s;
+  const uint4 a = p[0], b = p[vh], c = p[2 * vh];
   u[0] = unpack2<S16>(a.x); u[1] = unpack2<S16>(a.y); u[2] = unpack2<S16>(a.z); u[3] = unpack2<S16>(a.w);
   u[4] = unpack2<S16>(b.x); u[5] = unpack2<S16>(b.y); u[6] = unpack2<S16>(b.z); u[7] = unpack2<S16>(b.w);
   u[8] = unpack2<S16>(c.x);

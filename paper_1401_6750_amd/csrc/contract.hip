@@ -419,8 +419,8 @@ __global__ __launch_bounds__(256) void k_contract_deriv(const SlotDesc* slots, i
   cx<R> up[9];
   uint32_t cr[9], ci[9];
   if constexpr (Traits<S>::NC == 3) {
-    const uint4* lp = (const uint4*)gauge + ((long)(nu * 2 + par) * vp + s) * 3;
-    const uint4 l0 = lp[0], l1 = lp[1], l2 = lp[2];
+    const uint4* lp = (const uint4*)gauge + (long)(nu * 2 + par) * 3 * vp + s;
+    const uint4 l0 = lp[0], l1 = lp[vp], l2 = lp[2 * vp];
     const uint32_t e[9] = {l0.x, l0.y, l0.z, l0.w, l1.x, l1.y, l1.z, l1.w, l2.x};
     link_coef16<true>(e, b < (R)0, cr, ci);
   } else {

@@ -216,8 +216,8 @@ struct HopWords {
 template <int MU, int G>
 __device__ inline void hop_load16(HopWords<G>& h, const void* gauge, long vp, int link_par, int link_site, int nb,
                                   const void* const (&inb)[G]) {
-  const uint4* lp = (const uint4*)gauge + ((long)(MU * 2 + link_par) * vp + link_site) * 3;
-  const uint4 l0 = lp[0], l1 = lp[1], l2 = lp[2];
+  const uint4* lp = (const uint4*)gauge + (long)(MU * 2 + link_par) * 3 * vp + link_site;
+  const uint4 l0 = lp[0], l1 = lp[vp], l2 = lp[2 * vp];
   h.e[0] = l0.x; h.e[1] = l0.y; h.e[2] = l0.z; h.e[3] = l0.w;
   h.e[4] = l1.x; h.e[5] = l1.y; h.e[6] = l1.z; h.e[7] = l1.w; h.e[8] = l2.x;
 #pragma unroll
