@@ -451,7 +451,7 @@ void launch_diff_norms(const SlotDesc* slots, int nslots, int total_units, const
 __global__ __launch_bounds__(256) void k_pack_gauge(const double* src, int X, int Y, int Z, int T, void* g64,
                                                     void* g32, void* gb16, void* gh16) {
   const long long V = (long long)X * Y * Z * T;
-  const long long vp = pad_half(V / 2);   // record stride per (mu, parity)
+  const long long vp = pad_half(V / 2);   // row stride of the link chunk rows
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= V * 4) return;
   const int mu = (int)(i / V);

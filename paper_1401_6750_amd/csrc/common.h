@@ -339,10 +339,11 @@ template <class S> __device__ inline void* field_at(void* base, long long off) {
 }
 
 // ---------------------------------------------------------------------------
-// gauge links: one record per (mu, parity, site) = the 9 complex entries of
-// the 3x3 matrix, row-major, padded to whole 16-byte chunks (FP64 9 chunks,
-// FP32 5, 16-bit 3) so a lane fetches its link with 3-9 vector loads from one
-// address.  Record index (mu * 2 + parity) * Vh + site.
+// gauge links: the 9 complex entries of each 3x3 matrix, row-major, padded to
+// whole 16-byte chunks (FP64 9 chunks, FP32 5, 16-bit 3); chunk k of the link
+// (mu, parity, site) sits at row (mu * 2 + parity) * nchunks + k, column site,
+// rows Vp apart, so the lanes of a wave load one chunk of their 64 links as
+// 1 KiB contiguous.
 // ---------------------------------------------------------------------------
 inline int link_chunks(int prec) { return prec == P64 ? 9 : (prec == P32 ? 5 : 3); }
 
@@ -421,7 +422,7 @@ static_assert((DL_RPW16 == 1 || DL_RPW16 == 2 || DL_RPW16 == 4) && (DL_RPW32 == 
               "right-hand sides per wave: 1, 2 or 4");
 
 // Site stride of every per-parity device array (spinor chunk rows, link
-// records, accumulator rows): Vh rounded up to an odd number of 64-site
+// chunk rows, accumulator rows): Vh rounded up to an odd number of 64-site
 // tiles.  Rows then start an odd number of KiB apart; with the unpadded Vh
 // (2^12 * 81 at 24^3x48, 2^15 at 16^3x32) the rows of one site sit at
 // multiples of 64 KiB and compete for the same L2 sets.

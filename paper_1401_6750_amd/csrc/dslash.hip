@@ -204,7 +204,7 @@ __device__ inline void hop(const void* gauge, long vp, int link_par, int link_si
 }
 
 // ---- software-pipelined 16-bit hops ---------------------------------------
-// The words one hop needs (link record, neighbour spinor of every group
+// The words one hop needs (link chunks, neighbour spinor of every group
 // member) are loaded one hop ahead of the arithmetic that uses them, so a
 // wave has the next hop's loads in flight while it computes the current one.
 template <int G>
@@ -326,7 +326,7 @@ __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
   if (!any) return;
   const int s = tile * TILE + lane;
   const bool valid = s < sd.Vh;
-  const long vp = sd.Vp;   // row stride of fields and link records
+  const long vp = sd.Vp;   // row stride of fields and link chunk rows
   long long off[G];
 #pragma unroll
   for (int i = 0; i < G; ++i) off[i] = sd.fo + (long long)(r0 + i) * vp;
