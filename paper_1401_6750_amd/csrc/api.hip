@@ -100,7 +100,7 @@ int dl_lattice_create(dl_ctx* ctx, const int dims[4], int t_bc, dl_lattice** out
     L->Vh = V / 2;
     try {
       for (int p = 0; p < 4; ++p) {
-        const size_t bytes = (size_t)(2 * pad_half(V / 2)) * 4 * link_chunks(p) * 16;
+        const size_t bytes = (size_t)pad_half(V / 2) * link_rows(p) * 16;
         if (hipMalloc(&L->gauge[p], bytes) != hipSuccess) {
           (void)hipGetLastError();
           throw Error(DL_ENOMEM, "dl_lattice_create: gauge allocation failed");

@@ -479,6 +479,19 @@ __global__ __launch_bounds__(256) void k_pack_gauge(const double* src, int X, in
     const long long w16 = ((row * 3 + e / 4) * vp + s) * 4 + e % 4;
     rb[w16] = pack2<bf16s>(qf);
     rh[w16] = pack2<f16s>(qf);
+    if (e == 8) {   // the ninth entry again, beside those of the site's other forward links
+      const long long n16 = ((long long)(LINK_ROW_NINTH + par) * vp + s) * 4 + mu;
+      rb[n16] = pack2<bf16s>(qf);
+      rh[n16] = pack2<f16s>(qf);
+      // and at x + mu, among the links reaching that site from behind
+      int xn[4] = {x, y, z, t};
+      const int ext[4] = {X, Y, Z, T};
+      xn[mu] = xn[mu] + 1 == ext[mu] ? 0 : xn[mu] + 1;
+      const long long lexn = xn[0] + (long long)X * (xn[1] + (long long)Y * (xn[2] + (long long)Z * xn[3]));
+      const long long b16 = ((long long)(LINK_ROW_NINTH_BWD + 1 - par) * vp + (lexn >> 1)) * 4 + mu;
+      rb[b16] = pack2<bf16s>(qf);
+      rh[b16] = pack2<f16s>(qf);
+    }
   }
 }
 

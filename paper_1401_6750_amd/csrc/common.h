@@ -346,6 +346,15 @@ template <class S> __device__ inline void* field_at(void* base, long long off) {
 // 1 KiB contiguous.
 // ---------------------------------------------------------------------------
 inline int link_chunks(int prec) { return prec == P64 ? 9 : (prec == P32 ? 5 : 3); }
+// Rows of Vp chunks per precision: 8 (mu, parity) x link_chunks; 16-bit links
+// add, per parity, one row with the ninth entries of the four links leaving a
+// site forward, U_mu(x) (row 24 + parity, word mu), and one with those of the
+// four links reaching it from behind, U_mu(x - mu) (row 26 + parity), so the
+// eight hops of a site fetch their ninth entries with two loads instead of
+// eight (copies; the entries also stay in the links' own chunk rows).
+constexpr int LINK_ROW_NINTH = 24;
+constexpr int LINK_ROW_NINTH_BWD = 26;
+inline int link_rows(int prec) { return 8 * link_chunks(prec) + ((prec == PB16 || prec == PH16) ? 4 : 0); }
 
 template <class S>
 __device__ inline void load_link(const void* g, long vh, int mu, int par, long s, cx<typename Traits<S>::R> (&u)[9]);

@@ -213,13 +213,17 @@ struct HopWords {
   uint32_t v[G][12];
 };
 
-template <int MU, int G>
+// NINE: the ninth link entry is `nine` (fetched with those of the site's other
+// forward links) instead of a load of its own.
+template <int MU, bool NINE, int G>
 __device__ inline void hop_load16(HopWords<G>& h, const void* gauge, long vp, int link_par, int link_site, int nb,
-                                  const void* const (&inb)[G]) {
+                                  const void* const (&inb)[G], uint32_t nine) {
   const uint4* lp = (const uint4*)gauge + (long)(MU * 2 + link_par) * 3 * vp + link_site;
-  const uint4 l0 = lp[0], l1 = lp[vp], l2 = lp[2 * vp];
+  const uint4 l0 = lp[0], l1 = lp[vp];
   h.e[0] = l0.x; h.e[1] = l0.y; h.e[2] = l0.z; h.e[3] = l0.w;
-  h.e[4] = l1.x; h.e[5] = l1.y; h.e[6] = l1.z; h.e[7] = l1.w; h.e[8] = l2.x;
+  h.e[4] = l1.x; h.e[5] = l1.y; h.e[6] = l1.z; h.e[7] = l1.w;
+  if constexpr (NINE) h.e[8] = nine;
+  else h.e[8] = lp[2 * vp].x;
 #pragma unroll
   for (int i = 0; i < G; ++i) {
     const uint4* q = (const uint4*)inb[i];
@@ -375,21 +379,25 @@ __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
       const void* ld[G];
 #pragma unroll
       for (int i = 0; i < G; ++i) ld[i] = act[i] ? inb[i] : fa;
+      // ninth entries of the four links leaving this site and of the four
+      // reaching it, one load each
+      const uint4 nf = ((const uint4*)gauge)[(long)(LINK_ROW_NINTH + p_out) * vp + s];
+      const uint4 nb = ((const uint4*)gauge)[(long)(LINK_ROW_NINTH_BWD + p_out) * vp + s];
       HopWords<G> h0, h1;
-      hop_load16<0>(h0, gauge, vp, p_out, s, nxp, ld);
-      hop_load16<0>(h1, gauge, vp, q, nxm, nxm, ld);
+      hop_load16<0, true>(h0, gauge, vp, p_out, s, nxp, ld, nf.x);
+      hop_load16<0, true>(h1, gauge, vp, q, nxm, nxm, ld, nb.x);
       hop_compute16<S, 0, true, true>(h0, 1.0f, act, acc);
-      hop_load16<1>(h0, gauge, vp, p_out, s, nyp, ld);
+      hop_load16<1, true>(h0, gauge, vp, p_out, s, nyp, ld, nf.y);
       hop_compute16<S, 0, false, false>(h1, 1.0f, act, acc);
-      hop_load16<1>(h1, gauge, vp, q, nym, nym, ld);
+      hop_load16<1, true>(h1, gauge, vp, q, nym, nym, ld, nb.y);
       hop_compute16<S, 1, true, false>(h0, 1.0f, act, acc);
-      hop_load16<2>(h0, gauge, vp, p_out, s, nzp, ld);
+      hop_load16<2, true>(h0, gauge, vp, p_out, s, nzp, ld, nf.z);
       hop_compute16<S, 1, false, false>(h1, 1.0f, act, acc);
-      hop_load16<2>(h1, gauge, vp, q, nzm, nzm, ld);
+      hop_load16<2, true>(h1, gauge, vp, q, nzm, nzm, ld, nb.z);
       hop_compute16<S, 2, true, false>(h0, 1.0f, act, acc);
-      hop_load16<3>(h0, gauge, vp, p_out, s, ntp, ld);
+      hop_load16<3, true>(h0, gauge, vp, p_out, s, ntp, ld, nf.w);
       hop_compute16<S, 2, false, false>(h1, 1.0f, act, acc);
-      hop_load16<3>(h1, gauge, vp, q, ntm, ntm, ld);
+      hop_load16<3, true>(h1, gauge, vp, q, ntm, ntm, ld, nb.w);
       hop_compute16<S, 3, true, false>(h0, (float)sp, act, acc);
       hop_compute16<S, 3, false, false>(h1, (float)sm, act, acc);
     } else {
