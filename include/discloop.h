@@ -149,7 +149,10 @@ typedef struct dl_job {
                             trick structures contract every component over the whole
                             lattice; the hopping parameter expansion, which pairs eta
                             with the solution, only next to the component's slices. */
-  int reserved;          /* set to 0 */
+  int grad_ops;          /* dl_loops_backward without an accumulator (accum NULL):
+                            the insertion set of the loops, DL_OPS_LOCAL or
+                            DL_OPS_LOCAL | DL_OPS_DERIV (0 = LOCAL | DERIV).
+                            Ignored when accum is set; dl_solve_batch ignores it. */
 } dl_job;
 
 typedef struct dl_src_stats {
@@ -184,6 +187,25 @@ int dl_lattice_destroy(dl_lattice* lat);
  * and fp16 even-odd layouts.  on_device: 0 host pointer, 1 device pointer.
  * The caller keeps ownership of `links`. */
 int dl_gauge_set(dl_lattice* lat, const double* links, int on_device);
+
+/* Synthetic gauge field, the stand-in for the paper's twisted-mass ensembles
+ * (Section 2.1.1 measures on 32^3 x 64 configurations): every link is
+ * U = exp(i eps H), H = sum_a h_a lambda_a / 2 over the eight Gell-Mann
+ * matrices with h_a ~ N(0, 1).  The Gaussians come from Box-Muller on a
+ * SplitMix64 counter stream (Steele, Lea & Flood 2014): link l = 4 site + mu
+ * (site lexicographic, x fastest) uses outputs 8 l .. 8 l + 7 of stream
+ * `seed`, output i being mix(seed + (i + 1) 0x9E3779B97F4A7C15), mapped to
+ * (0, 1) by its top 53 bits; pair k gives h_2k = sqrt(-2 ln u_2k) cos(2 pi
+ * u_2k+1), h_2k+1 the sine.  A link is a pure function of (seed, site, mu),
+ * so a C caller and the library's Python test inputs build the same field.
+ *   dl_gauge_random      generates the field on the host and loads it into
+ *                        the lattice as dl_gauge_set does;
+ *   dl_gauge_random_host writes it to caller host memory `links`, complex128
+ *                        [t][z][y][x][mu][3][3] (the dl_gauge_set layout),
+ *                        dims {X, Y, Z, T} >= 1; no GPU is used.
+ * Errors: DL_EINVAL (NULL argument, non-finite eps). */
+int dl_gauge_random(dl_lattice* lat, uint64_t seed, double eps);
+int dl_gauge_random_host(const int dims[4], uint64_t seed, double eps, double* links);
 
 /* Set kappa (> 0) and mu of the operator.  mu = 0 is the Wilson operator
  * (Section 2.4 expects the code to carry over to Wilson-type fermions): u and
@@ -242,7 +264,9 @@ int dl_loops_sets(dl_ctx* ctx, dl_accum* acc, int p2max, double* out, int out_on
 /* Gradients of the loops of one job's sources with respect to the sources and
  * to mu, for a real loss F.  The loops are the plain estimator over the job's
  * nsrc sources (what dl_loops returns for an accumulator that holds only
- * them); nops is that of job->accum (5 if job->accum is NULL).
+ * them); nops is that of job->accum, or of job->grad_ops when job->accum
+ * is NULL (the accumulator is read for its insertion set only, so a caller
+ * may free it after dl_loops and pass grad_ops instead).
  * Complex gradients follow PyTorch's convention, dF/dRe z + i dF/dIm z:
  *   grad_loops  host complex128 [2][nops][16][T][Np], the gradient of F with
  *               respect to the loops;

@@ -61,7 +61,7 @@ class dl_job(ctypes.Structure):
         ("accum_set", ctypes.c_int),
         ("guess_from", ctypes.c_int),
         ("tdil", ctypes.c_int),
-        ("reserved", ctypes.c_int),
+        ("grad_ops", ctypes.c_int),
     ]
 
 
@@ -90,6 +90,8 @@ _SIGS = {
     "dl_lattice_destroy": ([_P], _I),
     "dl_gauge_set": ([_P, _P, _I], _I),
     "dl_set_params": ([_P, _D, _D], _I),
+    "dl_gauge_random": ([_P, ctypes.c_uint64, _D], _I),
+    "dl_gauge_random_host": ([ctypes.POINTER(_I), ctypes.c_uint64, _D, _P], _I),
     "dl_solve_batch": ([_P, ctypes.POINTER(dl_job), _I, ctypes.POINTER(dl_src_stats)], _I),
     "dl_accum_create": ([_P, _I, ctypes.POINTER(_P)], _I),
     "dl_accum_reset": ([_P], _I),
@@ -175,6 +177,16 @@ def dl_gauge_set(lat, links, on_device: int) -> None:
     _check(lib().dl_gauge_set(lat, _ptr(links), on_device))
 
 
+def dl_gauge_random(lat, seed: int, eps: float) -> None:
+    _check(lib().dl_gauge_random(lat, seed, eps))
+
+
+def dl_gauge_random_host(dims, seed: int, eps: float, links) -> None:
+    """Fill host complex128 links [T, Z, Y, X, 4, 3, 3] with the synthetic field."""
+    d = (_I * 4)(*dims)
+    _check(lib().dl_gauge_random_host(d, seed, eps, _ptr(links)))
+
+
 def dl_set_params(lat, kappa: float, mu: float) -> None:
     _check(lib().dl_set_params(lat, kappa, mu))
 
@@ -211,11 +223,12 @@ def dl_momenta(dims, p2max: int):
 
 def make_job(lat, *, noise=DL_NOISE_Z2, tier=DL_TIER_FP64, seed=0, first_src=0, nsrc=1, maxiter=1000,
              tol=1e-10, rhs_block=0, report_true_resid=0, src_in=None, sol_out=None, accum=None,
-             accum_set=DL_SET_HP, guess_from=0, tdil=0) -> dl_job:
+             accum_set=DL_SET_HP, guess_from=0, tdil=0, grad_ops=0) -> dl_job:
     """One job; guess_from = j + 1 starts an HP job from the solutions of job j of the same call;
-    tdil = D >= 2 dilutes every noise vector into D time-slice components."""
+    tdil = D >= 2 dilutes every noise vector into D time-slice components; grad_ops names the
+    insertion set for dl_loops_backward when accum is None."""
     return dl_job(lat, noise, tier, seed, first_src, nsrc, maxiter, tol, rhs_block, report_true_resid,
-                  _ptr(src_in), _ptr(sol_out), accum, accum_set, guess_from, tdil, 0)
+                  _ptr(src_in), _ptr(sol_out), accum, accum_set, guess_from, tdil, grad_ops)
 
 
 def dl_solve_batch(ctx, jobs):
@@ -293,37 +306,37 @@ def _make_disc_loops():
             eta = eta.contiguous()
             nsrc = eta.shape[0]
             acc = dl_accum_create(lat, ops)
-            sol = torch.empty_like(eta)
-            job = make_job(lat, noise=DL_NOISE_USER, tier=tier, nsrc=nsrc, tol=tol, maxiter=10000,
-                           src_in=eta, sol_out=sol, accum=acc, accum_set=DL_SET_HP)
-            dl_solve_batch(dlctx, job)
-            T = eta.shape[1]
-            nops = 5 if ops & DL_OPS_DERIV else 1
-            np_ = len(dl_momenta((eta.shape[4], eta.shape[3], eta.shape[2], T), p2max))
-            out = torch.empty((2, nops, 16, T, np_), dtype=torch.complex128, device=eta.device)
-            dl_loops(dlctx, acc, p2max, out, 1)
-            torch.cuda.current_stream().synchronize()
-            if not any(fctx.needs_input_grad[:2]):
-                dl_accum_destroy(acc)          # no backward will come
-                acc = None
+            try:
+                sol = torch.empty_like(eta)
+                job = make_job(lat, noise=DL_NOISE_USER, tier=tier, nsrc=nsrc, tol=tol, maxiter=10000,
+                               src_in=eta, sol_out=sol, accum=acc, accum_set=DL_SET_HP)
+                dl_solve_batch(dlctx, job)
+                T = eta.shape[1]
+                nops = 5 if ops & DL_OPS_DERIV else 1
+                np_ = len(dl_momenta((eta.shape[4], eta.shape[3], eta.shape[2], T), p2max))
+                out = torch.empty((2, nops, 16, T, np_), dtype=torch.complex128, device=eta.device)
+                dl_loops(dlctx, acc, p2max, out, 1)
+                torch.cuda.current_stream().synchronize()
+            finally:
+                # the backward pass needs only the insertion set (grad_ops), not the sums
+                dl_accum_destroy(acc)
             fctx.save_for_backward(eta, sol)
-            fctx.meta = (dlctx, lat, kappa, mu_v, p2max, acc, tier, tol)
+            fctx.meta = (dlctx, lat, kappa, mu_v, p2max, ops, tier, tol)
             return out
 
         @staticmethod
         def backward(fctx, gout):
             eta, sol = fctx.saved_tensors
-            dlctx, lat, kappa, mu_v, p2max, acc, tier, tol = fctx.meta
+            dlctx, lat, kappa, mu_v, p2max, ops, tier, tol = fctx.meta
             dl_set_params(lat, kappa, mu_v)
             g_host = gout.detach().to("cpu", torch.complex128).contiguous().numpy()
             grad_eta = torch.empty_like(eta)
             gmu = ctypes.c_double()
             job = make_job(lat, noise=DL_NOISE_USER, tier=tier, nsrc=eta.shape[0], tol=tol, maxiter=10000,
-                           src_in=eta, sol_out=sol, accum=acc)
+                           src_in=eta, sol_out=sol, grad_ops=ops & (DL_OPS_LOCAL | DL_OPS_DERIV))
             _check(lib().dl_loops_backward(dlctx, ctypes.byref(job), p2max, g_host.ctypes.data,
                                            grad_eta.data_ptr(), ctypes.addressof(gmu)))
             torch.cuda.current_stream().synchronize()
-            dl_accum_destroy(acc)
             grad_mu = torch.tensor(gmu.value, dtype=torch.float64)
             return grad_eta, grad_mu, None, None, None, None, None, None, None
 

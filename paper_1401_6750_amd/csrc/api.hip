@@ -129,25 +129,50 @@ int dl_lattice_destroy(dl_lattice* lat) {
   });
 }
 
+static void gauge_upload(dl_lattice* lat, const double* links, int on_device) {
+  dl_ctx* c = lat->ctx;
+  stream_enter(c);
+  const size_t bytes = (size_t)lat->V * 4 * 9 * 16;
+  DevBuf stage;
+  const double* src = links;
+  if (!on_device) {
+    stage = DevBuf(c, bytes);
+    HIPCHECK(hipMemcpyAsync(stage.p, links, bytes, hipMemcpyHostToDevice, c->st));
+    src = stage.as<double>();
+  }
+  launch_pack_gauge(src, lat->dims[0], lat->dims[1], lat->dims[2], lat->dims[3], lat->gauge[0], lat->gauge[1],
+                    lat->gauge[2], lat->gauge[3], c->st);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipStreamSynchronize(c->st));
+  stream_exit(c);
+  lat->gauge_set = true;
+}
+
 int dl_gauge_set(dl_lattice* lat, const double* links, int on_device) {
   return guarded([&] {
     require(lat && links, "dl_gauge_set: NULL argument");
-    dl_ctx* c = lat->ctx;
-    stream_enter(c);
-    const size_t bytes = (size_t)lat->V * 4 * 9 * 16;
-    DevBuf stage;
-    const double* src = links;
-    if (!on_device) {
-      stage = DevBuf(c, bytes);
-      HIPCHECK(hipMemcpyAsync(stage.p, links, bytes, hipMemcpyHostToDevice, c->st));
-      src = stage.as<double>();
-    }
-    launch_pack_gauge(src, lat->dims[0], lat->dims[1], lat->dims[2], lat->dims[3], lat->gauge[0], lat->gauge[1],
-                      lat->gauge[2], lat->gauge[3], c->st);
-    HIPCHECK(hipGetLastError());
-    HIPCHECK(hipStreamSynchronize(c->st));
-    stream_exit(c);
-    lat->gauge_set = true;
+    gauge_upload(lat, links, on_device);
+    return 0;
+  });
+}
+
+int dl_gauge_random_host(const int dims[4], uint64_t seed, double eps, double* links) {
+  return guarded([&] {
+    require(dims && links, "dl_gauge_random_host: NULL argument");
+    for (int k = 0; k < 4; ++k) require(dims[k] >= 1, "dl_gauge_random_host: extents must be >= 1");
+    require(std::isfinite(eps), "dl_gauge_random_host: eps must be finite");
+    random_gauge_host(dims, seed, eps, links);
+    return 0;
+  });
+}
+
+int dl_gauge_random(dl_lattice* lat, uint64_t seed, double eps) {
+  return guarded([&] {
+    require(lat != nullptr, "dl_gauge_random: NULL lattice");
+    require(std::isfinite(eps), "dl_gauge_random: eps must be finite");
+    std::vector<double> links((size_t)lat->V * 4 * 18);
+    random_gauge_host(lat->dims, seed, eps, links.data());
+    gauge_upload(lat, links.data(), 0);
     return 0;
   });
 }
@@ -527,6 +552,10 @@ int dl_loops(dl_ctx* ctx, dl_accum* a, int p2max, double* out, int out_on_device
     require(L->params_set, "dl_loops: kappa / mu not set");
     require(a->count[DL_SET_LPC] == 0 || a->count[DL_SET_LPC] == a->count[DL_SET_HP],
             "dl_loops: the LPC set must hold the same sources as the HP set");
+    // with both LP and HP sources the estimate is the TSM one, which needs the
+    // LP solves of the HP sources; S_LP / N_LP + S_HP / N_HP would count the loop twice
+    require(a->count[DL_SET_LP] == 0 || a->count[DL_SET_HP] == 0 || a->count[DL_SET_LPC] == a->count[DL_SET_HP],
+            "dl_loops: LP and HP sets without the LPC set (the LP solves of the HP sources) form no estimator");
     // TSM combination L = S_LP / N_LP + (S_HP - S_LPC) / N_HP, taken on the
     // accumulators so one projection serves all three sets
     const double w_lp = a->count[DL_SET_LP] > 0 ? 1.0 / (double)a->count[DL_SET_LP] : 0.0;
@@ -647,6 +676,9 @@ int dl_loops_backward(dl_ctx* ctx, const dl_job* job, int p2max, const double* g
     require(!job->accum || DL_OPS_HPE_ORDER(job->accum->ops) == 0,
             "dl_loops_backward: loops with the hopping parameter expansion are not differentiated");
     require(job->tdil <= 1, "dl_loops_backward: time-diluted sources are not differentiated");
+    require(job->accum || job->grad_ops == 0 || job->grad_ops == DL_OPS_LOCAL ||
+                job->grad_ops == (DL_OPS_LOCAL | DL_OPS_DERIV),
+            "dl_loops_backward: grad_ops must be 0, DL_OPS_LOCAL or DL_OPS_LOCAL | DL_OPS_DERIV");
     loops_backward(ctx, *job, p2max, grad_loops, grad_eta, grad_mu);
     return 0;
   });

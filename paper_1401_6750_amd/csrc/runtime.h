@@ -153,6 +153,10 @@ bool solve_jobs(dl_ctx* ctx, const std::vector<dl_job>& J, dl_src_stats* stats);
 // Write the Z2 / Z4 sources of the plan's slots to their sol_user arrays.
 void fill_noise_fields(dl_ctx* ctx, const std::vector<SlotPlan>& plan, const std::vector<dl_job>& jobs);
 
+// Synthetic links U = exp(i eps H) (gauge.hip) into host memory, complex128
+// [t][z][y][x][mu][3][3]; multi-threaded.
+void random_gauge_host(const int dims[4], uint64_t seed, double eps, double* links);
+
 // Adjoint-solve gradients of the loops (dl_loops_backward).
 void loops_backward(dl_ctx* ctx, const dl_job& job, int p2max, const double* grad_loops, double* grad_eta,
                     double* grad_mu);

@@ -613,8 +613,12 @@ void run_batch(dl_ctx* ctx, int tier, const std::vector<SlotPlan>& plan, const s
   CgFields f{x.p, r.p, p.p, t.p, u.p};
   std::vector<int> ru_count(b.nrhs, 0);
   // s_e / s_o / xi fields in the contraction precision
-  int PC = P;
+  // The high-precision tier contracts its FP64 solution with FP64 products and
+  // per-source FP64 sums (the correction term of the estimator carries the HP
+  // accuracy into the loops); the other tiers contract in their storage type.
+  const int PC = tier == DL_TIER_HP_FP32 ? P64 : P;
   DevBuf s64_e, s64_o;   // FP64 solution when the solve keeps one (HP tier)
+  DevBuf e64_e, e64_o;   // FP64 sources (HP tier)
 
   if (tier != DL_TIER_HP_FP32) {
     cg_start(b, P, eta_e.p, eta_o.p, f);
@@ -625,7 +629,9 @@ void run_batch(dl_ctx* ctx, int tier, const std::vector<SlotPlan>& plan, const s
   } else {
     // High precision: FP32 CG with FP64 reliable updates (true residual of
     // the normal equations recomputed in FP64, solution accumulated in FP64).
-    DevBuf e64_e = b.field(P64), e64_o = b.field(P64), c64 = b.field(P64), xhi = b.field(P64),
+    e64_e = b.field(P64);
+    e64_o = b.field(P64);
+    DevBuf c64 = b.field(P64), xhi = b.field(P64),
            t64 = b.field(P64), u64 = b.field(P64), ap64 = b.field(P64);
     launch_sources(P64, b.slots(), b.nslots, b.u_rhs, 0, e64_e.p, st);
     launch_sources(P64, b.slots(), b.nslots, b.u_rhs, 1, e64_o.p, st);
@@ -790,21 +796,32 @@ void run_batch(dl_ctx* ctx, int tier, const std::vector<SlotPlan>& plan, const s
     s64_o = std::move(xhi);
     s64_e = b.field(P64);
     b.dslash(P64, F_Y, CK_RECON, 0, s64_o.p, s64_e.p, e64_e.p, nullptr);
-    // FP32 copies for the contractions
-    launch_convert(P64, P32, b.slots(), b.nslots, b.u_rhs, s64_o.p, x.p, 0, nullptr, st);
   }
 
   // ---- solution, xi fields, contractions ---------------------------------
-  // fields: s_o = x, s_e = r, xi_e = p, xi_o = t
+  // fields in the contraction precision: s_o, s_e, xi_e, xi_o (LP / FP64
+  // tiers reuse x, r, p, t; the HP tier its FP64 solution and two FP64 fields)
   bool any_acc = false, any_sol = false;
   for (const SlotPlan& sp : plan) {
     any_acc = any_acc || sp.acc;
     any_sol = any_sol || sp.sol_user;
   }
+  void *so_f = x.p, *se_f = r.p, *xe_f = p.p, *xo_f = t.p;
+  const void *eta_ef = eta_e.p, *eta_of = eta_o.p;
+  DevBuf xi64_e, xi64_o;
   bool xi_e_done = false;
   if (tier == DL_TIER_HP_FP32) {
-    launch_convert(P64, P32, b.slots(), b.nslots, b.u_rhs, s64_e.p, r.p, 0, nullptr, st);
-  } else if (any_acc && PC == P) {
+    so_f = s64_o.p;
+    se_f = s64_e.p;
+    eta_ef = e64_e.p;
+    eta_of = e64_o.p;
+    if (any_acc) {
+      xi64_e = b.field(P64);
+      xi64_o = b.field(P64);
+      xe_f = xi64_e.p;
+      xo_f = xi64_o.p;
+    }
+  } else if (any_acc) {
     // s_e and xi_e = s_e - kappa H_eo s_o share the hop H_eo s_o
     b.dslash(P, F_Y | F_DUAL, CK_RECON_XI, 0, x.p, r.p, eta_e.p, nullptr, nullptr, nullptr, nullptr, p.p);
     xi_e_done = true;
@@ -821,17 +838,17 @@ void run_batch(dl_ctx* ctx, int tier, const std::vector<SlotPlan>& plan, const s
       else any_plain = true;
     }
     if (any_plain) {
-      if (!xi_e_done) b.dslash(PC, F_Y, CK_XI, 0, x.p, p.p, r.p, nullptr);
-      b.dslash(PC, F_Y, CK_XI, 1, r.p, t.p, x.p, nullptr);
+      if (!xi_e_done) b.dslash(PC, F_Y, CK_XI, 0, so_f, xe_f, se_f, nullptr);
+      b.dslash(PC, F_Y, CK_XI, 1, se_f, xo_f, so_f, nullptr);
     }
     HpeFields h;
     DevBuf fa_e, fa_o, fb_e, fb_o;
     if (hpe) {
       // phi_k = (kappa B H)^k s, k = 1..n, alternating between two fields;
-      // the source eta (eta_e / eta_o, still intact) is the other vector
+      // the source eta (still intact) is the other vector
       fa_e = b.field(PC); fa_o = b.field(PC); fb_e = b.field(PC); fb_o = b.field(PC);
-      const void* in_e = r.p;
-      const void* in_o = x.p;
+      const void* in_e = se_f;
+      const void* in_o = so_f;
       for (int k = 1; k <= hpe; ++k) {
         void* oe = (k & 1) ? fa_e.p : fb_e.p;
         void* oo = (k & 1) ? fa_o.p : fb_o.p;
@@ -841,11 +858,11 @@ void run_batch(dl_ctx* ctx, int tier, const std::vector<SlotPlan>& plan, const s
         in_o = oo;
       }
       const int nd = std::min(hpe, 3);
-      h.eta[0] = eta_e.p; h.eta[1] = eta_o.p;
+      h.eta[0] = eta_ef; h.eta[1] = eta_of;
       h.loc[0] = (hpe & 1) ? fa_e.p : fb_e.p; h.loc[1] = (hpe & 1) ? fa_o.p : fb_o.p;
       h.der[0] = (nd & 1) ? fa_e.p : fb_e.p; h.der[1] = (nd & 1) ? fa_o.p : fb_o.p;
     }
-    contract_passes(b, PC, r.p, x.p, p.p, t.p, h);
+    contract_passes(b, PC, se_f, so_f, xe_f, xo_f, h);
   }
   if (any_sol) {
     if (tier == DL_TIER_HP_FP32) {
@@ -1179,9 +1196,10 @@ bool solve_jobs(dl_ctx* ctx, const std::vector<dl_job>& J, dl_src_stats* stats) 
         const SlotPlan& sp = all[i];
         const double vp = (double)pad_half(sp.lat->Vh);
         double per = vp * sp.nrhs * (7.0 * chunks_of(P) * 16);
-        if (tier == DL_TIER_HP_FP32) per += vp * sp.nrhs * 9.0 * 192;
+        if (tier == DL_TIER_HP_FP32) per += vp * sp.nrhs * 11.0 * 192;
         if (J[sp.job].report_true_resid) per += vp * sp.nrhs * 6.0 * 192;
-        if (J[sp.job].accum && DL_OPS_HPE_ORDER(J[sp.job].accum->ops)) per += vp * sp.nrhs * (4.0 * chunks_of(P) * 16);
+        const int PCk = tier == DL_TIER_HP_FP32 ? P64 : P;
+        if (J[sp.job].accum && DL_OPS_HPE_ORDER(J[sp.job].accum->ops)) per += vp * sp.nrhs * (4.0 * chunks_of(PCk) * 16);
         if (!wave.empty() && (bytes + per > budget || nrhs + sp.nrhs > max_rhs)) break;
         wave.push_back(sp);
         bytes += per;
@@ -1231,7 +1249,8 @@ void loops_backward(dl_ctx* ctx, const dl_job& job, int p2max, const double* gra
     throw Error(DL_EINVAL, "dl_loops_backward: dF/dmu needs mu != 0");
   (void)tier_prec(job.tier);
   hipStream_t st = ctx->st;
-  const int nops = job.accum ? ((job.accum->ops & DL_OPS_DERIV) ? 5 : 1) : 5;
+  const int ops = job.accum ? job.accum->ops : (job.grad_ops ? job.grad_ops : DL_OPS_LOCAL | DL_OPS_DERIV);
+  const int nops = (ops & DL_OPS_DERIV) ? 5 : 1;
   const int N = job.nsrc;
   const long long V = L->V;
   const int X = L->dims[0], Y = L->dims[1], Z = L->dims[2], T = L->dims[3];

@@ -88,3 +88,29 @@ def test_binding_refuses_to_run_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(dl, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         dl.lib()
+
+
+@pytest.mark.parametrize("dims,seed,eps", [((4, 4, 4, 4), 1401, 0.3), ((6, 2, 4, 8), 7, 0.2),
+                                           ((16, 16, 16, 32), 1402, 0.2), ((2, 2, 2, 2), 2**63 + 11, 1.0)])
+def test_gauge_random_host_matches_synthetic_generator(dims, seed, eps):
+    """dl_gauge_random_host (the library's own link generator, host code) reproduces the
+    seeded synthetic ensemble the tests and benchmark build in Python: same counter stream,
+    Box-Muller pairs and Gell-Mann generator; the exponentials agree to rounding."""
+    import synth
+    X, Y, Z, T = dims
+    got = np.zeros((T, Z, Y, X, 4, 3, 3), dtype=np.complex128)
+    dl.dl_gauge_random_host(dims, seed, eps, got)
+    want = synth.random_gauge(dims, seed, eps)
+    assert np.abs(got - want).max() < 1e-13
+    u = got.reshape(-1, 3, 3)[:500]
+    assert np.abs(np.einsum("nab,ncb->nac", u, u.conj()) - np.eye(3)).max() < 1e-13
+    assert np.abs(np.linalg.det(u) - 1).max() < 1e-13
+
+
+def test_gauge_random_host_argument_errors():
+    lib = dl.lib()
+    dims = (ctypes.c_int * 4)(4, 4, 4, 4)
+    assert lib.dl_gauge_random_host(dims, 1, 0.2, None) == dl.DL_EINVAL
+    assert lib.dl_gauge_random(None, 1, 0.2) == dl.DL_EINVAL
+    buf = np.zeros(4 ** 4 * 4 * 18)
+    assert lib.dl_gauge_random_host(dims, 1, float("nan"), buf.ctypes.data) == dl.DL_EINVAL

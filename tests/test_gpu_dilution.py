@@ -13,7 +13,7 @@ import pytest
 
 import paper_1401_6750_amd as dl
 from oracle import dilution, hpe, loops, noise, solver
-from tests.gpu_util import dev, host, make_lattice, rel, torch, zeros_dev
+from tests.gpu_util import dev, elementwise, host, make_lattice, rel, torch, zeros_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -92,10 +92,7 @@ def test_fp64_diluted_one_end_loops_match_oracle(ctx, lat, D):
     sets = np.zeros((3, 2, 5, 16, lat.dims[3], npm), dtype=np.complex128)
     dl.dl_loops_sets(ctx, acc, p2, sets, 0)
     want = oracle_vector_sums(lat, seed, range(nsrc), D, p2)
-    assert rel(sets[dl.DL_SET_LP], want) < 1e-10
-    for f in range(2):
-        for op in range(5):
-            assert rel(sets[dl.DL_SET_LP, f, op], want[f, op]) < 1e-9, (f, op)
+    log("  worst |d|/max|block|", elementwise(sets[dl.DL_SET_LP], want, 1e-10, 1e-10, 3))
     dl.dl_accum_destroy(acc)
 
 
@@ -114,9 +111,7 @@ def test_fp64_diluted_hpe_loops_match_oracle(ctx, lat, D, block):
     sets = np.zeros((3, 2, 5, 16, lat.dims[3], npm), dtype=np.complex128)
     dl.dl_loops_sets(ctx, acc, p2, sets, 0)
     want = oracle_vector_sums(lat, seed, range(nsrc), D, p2, n_hpe=n)
-    for f in range(2):
-        for op in range(5):
-            assert rel(sets[dl.DL_SET_HP, f, op], want[f, op]) < 1e-9, (f, op)
+    log("  worst |d|/max|block|", elementwise(sets[dl.DL_SET_HP], want, 1e-10, 1e-10, 3))
     dl.dl_accum_destroy(acc)
 
 

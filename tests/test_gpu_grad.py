@@ -101,3 +101,29 @@ def test_autograd_function_against_finite_differences(ctx):
     assert abs(mu.grad.item() - fd_mu) < 1e-6 * abs(fd_mu)
     assert abs(dir_grad - fd_eta) < 1e-6 * abs(fd_eta)
     lat.close()
+
+
+def test_autograd_double_backward_and_local_only(ctx):
+    """retain_graph: a second backward through the same graph gives the same gradients (the
+    forward frees its accumulator at once; the backward needs only the insertion set), also
+    for a local-only insertion set, whose gradient has one op."""
+    t = torch()
+    dims = (4, 4, 4, 4)
+    lat = make_lattice(ctx, dims, 1408, 0.3, 0.16, 0.02)
+    for ops in (dl.DL_OPS_LOCAL | dl.DL_OPS_DERIV, dl.DL_OPS_LOCAL):
+        nops = 5 if ops & dl.DL_OPS_DERIV else 1
+        etas = np.stack([noise.source(dims, 6756, r, noise.Z2) for r in range(2)])
+        np_ = len(loops.momenta(1, dims))
+        rng = np.random.default_rng(6)
+        gw = dev(rng.standard_normal((2, nops, 16, dims[3], np_)) + 1j * rng.standard_normal((2, nops, 16, dims[3], np_)))
+        eta = dev(etas).requires_grad_(True)
+        mu = t.tensor(lat.mu, dtype=t.float64, requires_grad=True)
+        L = dl.DiscLoops.apply(eta, mu, ctx, lat.h, lat.kappa, 1, ops, dl.DL_TIER_FP64, 1e-12)
+        assert L.shape == (2, nops, 16, dims[3], np_)
+        F = (L * gw.conj()).real.sum()
+        g1 = t.autograd.grad(F, (eta, mu), retain_graph=True)
+        g2 = t.autograd.grad(F, (eta, mu))
+        assert t.equal(g1[0], g2[0]) and t.equal(g1[1], g2[1])
+        want, dmu = grad.vjp(lat.U, etas, host(gw), lat.kappa, lat.mu, lat.bc, dims, 1, tol=1e-12)
+        assert rel(host(g1[0]), want) < 1e-9 and abs(g1[1].item() - dmu) < 1e-9 * abs(dmu)
+    lat.close()

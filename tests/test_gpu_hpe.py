@@ -4,9 +4,10 @@ FP64 oracle, through the C ABI.
 FP64 solves: every order 1..4, local and derivative insertions, per-set sums and the
 normalised estimate to 1e-10 relative, on a lattice with a ragged tile tail.  The
 storage-precision tiers are compared with the oracle evaluated on the solutions the
-GPU returned (so only the expansion's arithmetic differs): FP32 to 5e-6, bf16 and fp16 to
-a few units of their 2^-8 / 2^-11 storage rounding; the bf16 maps are bit-identical across
-slot shapes.
+GPU returned (so only the expansion's arithmetic differs): the HP tier (FP64 contraction of
+its FP64 solution) to 1e-10, bf16 and fp16 to a few units of their 2^-8 / 2^-11 storage
+rounding; the bf16 maps are bit-identical across slot shapes.  Loops are compared element
+by element against max|block| (gpu_util.elementwise).
 """
 import sys
 
@@ -15,7 +16,7 @@ import pytest
 
 import paper_1401_6750_amd as dl
 from oracle import hpe, loops, noise, solver
-from tests.gpu_util import host, make_lattice, rel, torch, zeros_dev
+from tests.gpu_util import elementwise, host, make_lattice, rel, torch, zeros_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -73,17 +74,14 @@ def test_fp64_hpe_loops_match_oracle(ctx, lat, n):
     sets = np.zeros((3, 2, 5, 16, lat.dims[3], npm), dtype=np.complex128)
     dl.dl_loops_sets(ctx, acc, p2, sets, 0)
     want = oracle_sums(lat, seed, range(nsrc), n, p2)
-    assert rel(sets[dl.DL_SET_LP], want) < 1e-10, rel(sets[dl.DL_SET_LP], want)
-    for f in range(2):
-        for op in range(5):
-            assert rel(sets[dl.DL_SET_LP, f, op], want[f, op]) < 1e-9, (f, op)
+    log("  worst |d|/max|block|", elementwise(sets[dl.DL_SET_LP], want, 1e-10, 1e-10, 3))
     # the remainder on its own (exact part taken out) still agrees
     ex = 4 * lat.kappa * nsrc * hpe.hpe_exact_projected(lat.kappa, lat.mu, n, p2, lat.dims)
-    assert rel(sets[dl.DL_SET_LP, 1] - ex, want[1] - ex) < 1e-9
+    elementwise(sets[dl.DL_SET_LP, 1] - ex, want[1] - ex, 1e-9, 1e-9, 2)
     assert np.abs(sets[dl.DL_SET_HP]).max() == 0 and np.abs(sets[dl.DL_SET_LPC]).max() == 0
     est = np.zeros((2, 5, 16, lat.dims[3], npm), dtype=np.complex128)
     dl.dl_loops(ctx, acc, p2, est, 0)
-    assert rel(est, want / nsrc) < 1e-10
+    elementwise(est, want / nsrc, 1e-10, 1e-10, 3)
     dl.dl_accum_destroy(acc)
 
 
@@ -96,11 +94,11 @@ def test_local_only_hpe_accumulator(ctx, lat):
     est = np.zeros((2, 1, 16, lat.dims[3], npm), dtype=np.complex128)
     dl.dl_loops(ctx, acc, p2, est, 0)
     want = oracle_sums(lat, seed, range(nsrc), n, p2, kind=noise.Z2)[:, :1] / nsrc
-    assert rel(est, want) < 1e-10
+    elementwise(est, want, 1e-10, 1e-10, 3)
     dl.dl_accum_destroy(acc)
 
 
-@pytest.mark.parametrize("tier,tol", [(dl.DL_TIER_HP_FP32, 5e-6), (dl.DL_TIER_LP_BF16, 2e-2),
+@pytest.mark.parametrize("tier,tol", [(dl.DL_TIER_HP_FP32, 1e-10), (dl.DL_TIER_LP_BF16, 2e-2),
                                       (dl.DL_TIER_LP_FP16, 4e-3)])
 def test_storage_precision_hpe_against_oracle_on_gpu_solutions(ctx, lat, tier, tol):
     seed, nsrc, p2, n = 33, 4, 3, 4
@@ -120,9 +118,9 @@ def test_storage_precision_hpe_against_oracle_on_gpu_solutions(ctx, lat, tier, t
     ex = 4 * lat.kappa * nsrc * hpe.hpe_exact_projected(lat.kappa, lat.mu, n, p2, lat.dims)
     for f in range(2):
         for op in range(5):
-            e = rel(sets[dl.DL_SET_LP, f, op] - (ex[op] if f else 0), want[f, op] - (ex[op] if f else 0))
-            log("  flavour", f, "op", op, "rel err", e)
-            assert e < tol, (f, op, e)
+            e = elementwise(sets[dl.DL_SET_LP, f, op] - (ex[op] if f else 0), want[f, op] - (ex[op] if f else 0),
+                            tol if tier == dl.DL_TIER_HP_FP32 else 0.0, tol, 1)
+            log("  flavour", f, "op", op, "worst |d|/max|block|", e)
     dl.dl_accum_destroy(acc)
 
 
@@ -167,12 +165,12 @@ def test_tsm_with_hpe_and_mixed_accumulators(ctx, lat):
     est_p = np.zeros_like(est_h)
     dl.dl_loops(ctx, a_h, p2, est_h, 0)
     dl.dl_loops(ctx, a_p, p2, est_p, 0)
-    assert rel(est_h[0], est_p[0]) < 1e-12
+    elementwise(est_h[0], est_p[0], 1e-12, 1e-12, 2)
     s_lp = oracle_sums(lat, seed, range(n_lp), n, p2, tol=1e-2)
     s_hp = oracle_sums(lat, seed, range(n_lp, n_lp + n_hp), n, p2, tol=1e-11)
     s_lpc = oracle_sums(lat, seed, range(n_lp, n_lp + n_hp), n, p2, tol=1e-2)
     want = s_lp / n_lp + (s_hp - s_lpc) / n_hp
-    assert rel(est_h, want) < 1e-9, rel(est_h, want)
+    elementwise(est_h, want, 1e-9, 1e-9, 3)
     dl.dl_accum_destroy(a_h)
     dl.dl_accum_destroy(a_p)
 

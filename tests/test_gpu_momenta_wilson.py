@@ -14,7 +14,7 @@ import pytest
 
 import paper_1401_6750_amd as dl
 from oracle import dirac, hpe, loops, noise, solver
-from tests.gpu_util import dev, host, make_lattice, rel, torch, zeros_dev
+from tests.gpu_util import dev, elementwise, host, make_lattice, rel, torch, zeros_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -59,9 +59,7 @@ def test_every_momentum_matches_oracle(ctx, p2):
     out = np.zeros((2, 5, 16, la.dims[3], len(moms)), dtype=np.complex128)
     assert dl.dl_loops(ctx, acc, p2, out, 0) == len(moms)
     want = loops.estimate(np.array([per_source(la, seed, r, p2) for r in range(nsrc)]), la.kappa, la.mu)
-    for f in range(2):
-        for op in range(5):
-            assert rel(out[f, op], want[f, op]) < 1e-9, (f, op)
+    log("  worst |d|/max|block|", elementwise(out, want, 1e-10, 1e-10, 3))
     dl.dl_accum_destroy(acc)
     la.close()
 
@@ -92,8 +90,7 @@ def test_wilson_operator_and_loops(ctx):
         dl.dl_loops(ctx, acc, p2, out, 0)
         assert np.abs(out[0]).max() == 0          # u = d: the tau_3 loops vanish
         want = loops.estimate(np.array([per_source(la, seed, r, p2, n) for r in range(nsrc)]), la.kappa, 0.0)
-        for op in range(5):
-            assert rel(out[1, op], want[1, op]) < 1e-9, (n, op)
+        elementwise(out[1], want[1], 1e-10, 1e-10, 2)
         dl.dl_accum_destroy(acc)
     g = np.zeros((2, 5, 16, la.dims[3], npm), dtype=np.complex128)
     gm = np.zeros(1)

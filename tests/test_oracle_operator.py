@@ -162,3 +162,44 @@ def test_cg_residual_definition_and_stop():
         # one iteration fewer would not have met the target
         _, info2 = solver.cgnr_eo(U, eta, k, mu, -1, DIMS, tol=tol, maxiter=info["iters"] - 1)
         assert not info2["converged"]
+
+
+@pytest.mark.parametrize("bc_t", [-1, 1])
+def test_hop_at_sites_matches_whole_field_hop(bc_t):
+    """The site-by-site hopping term (the checker of the full-size GPU tests) equals the
+    whole-field ``hop`` at boundary and random sites, on a lattice with unequal extents and
+    an extent of 2, for both time boundaries."""
+    for dims in [(4, 6, 2, 8), (6, 4, 4, 6)]:
+        X, Y, Z, T = dims
+        U = synth.random_gauge(dims, 77, 0.5)
+        psi = synth.random_spinor(dims, 78)
+        full = dirac.hop(U, psi, bc_t)
+        rng = np.random.default_rng(4)
+        sites = [(0, 0, 0, 0), (T - 1, Z - 1, Y - 1, X - 1), (0, Z - 1, 0, X - 1), (T - 1, 0, Y - 1, 0)]
+        sites += [tuple(int(rng.integers(n)) for n in (T, Z, Y, X)) for _ in range(40)]
+        got = dirac.hop_at_sites(U, psi, bc_t, sites)
+        want = np.array([full[s] for s in sites])
+        assert rel(got, want) < 1e-14
+
+
+@pytest.mark.parametrize("bc_t", [-1, 1])
+def test_hop_at_sites_free_field_closed_form(bc_t):
+    """U = 1: H e^{ipx} u = e^{ipx} [2 sum cos p - 2 i sum gamma sin p] u at single sites,
+    with the time momentum shifted by pi/T for the antiperiodic boundary (an independent
+    pin of the site-by-site spelling: a wrong sign, projector or boundary factor fails it)."""
+    dims = (4, 6, 2, 8)
+    X, Y, Z, T = dims
+    U = synth.unit_gauge(dims)
+    rng = np.random.default_rng(9)
+    u = rng.standard_normal((4, 3)) + 1j * rng.standard_normal((4, 3))
+    n = (1, 2, 1, 3)
+    shift = 0.5 if bc_t == -1 else 0.0
+    p = [2 * np.pi * n[0] / X, 2 * np.pi * n[1] / Y, 2 * np.pi * n[2] / Z, 2 * np.pi * (n[3] + shift) / T]
+    t, z, y, x = np.meshgrid(*[np.arange(L) for L in (T, Z, Y, X)], indexing="ij")
+    phase = np.exp(1j * (p[0] * x + p[1] * y + p[2] * z + p[3] * t))
+    psi = phase[..., None, None] * u
+    hp = 2 * sum(np.cos(q) for q in p) * np.eye(4) - 2j * sum(dirac.GAMMA[m] * np.sin(p[m]) for m in range(4))
+    sites = [(0, 0, 0, 0), (T - 1, Z - 1, Y - 1, X - 1), (3, 1, 5, 2), (T - 1, 0, 0, 3)]
+    got = dirac.hop_at_sites(U, psi, bc_t, sites)
+    want = np.array([phase[s] * (hp @ u) for s in sites])
+    assert rel(got, want) < 1e-13
