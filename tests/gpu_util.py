@@ -51,14 +51,14 @@ def rel(a, b):
     return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
 
 
-def elementwise(got, want, rtol, atol, nblock):
-    """Element-wise parity of loop arrays.
+def elementwise_check(got, want, rtol, atol, nblock):
+    """Element-wise parity of loop arrays, without asserting.
 
     Every element must satisfy |got - want| <= rtol |want| + atol m, where m is the
     largest |want| of its block: one index of the leading ``nblock`` axes (flavour,
     op, Gamma for a [2][nops][16][T][Np] array) over the remaining ones (time slice,
     momentum).  A small wrong entry inside a block cannot hide behind the block's
-    norm.  Returns the worst |got - want| / m, for the log.
+    norm.  Returns (worst |got - want| / m, list of the first bad indices, count).
     """
     got = np.asarray(got)
     want = np.asarray(want)
@@ -69,8 +69,15 @@ def elementwise(got, want, rtol, atol, nblock):
     bound = rtol * np.abs(want) + atol * m
     worst = float((d / np.where(m > 0, m, 1.0)).max()) if d.size else 0.0
     bad = d > bound
-    if bad.any():
-        idx = [tuple(int(i) for i in ix) for ix in np.argwhere(bad)[:4]]
-        raise AssertionError(f"{int(bad.sum())} of {bad.size} elements out of bounds (rtol {rtol}, atol {atol}); "
+    idx = [tuple(int(i) for i in ix) for ix in np.argwhere(bad)[:4]]
+    return worst, idx, int(bad.sum())
+
+
+def elementwise(got, want, rtol, atol, nblock):
+    """elementwise_check() that raises on any element out of bounds; returns the worst
+    |got - want| / m, for the log."""
+    worst, idx, nbad = elementwise_check(got, want, rtol, atol, nblock)
+    if nbad:
+        raise AssertionError(f"{nbad} of {np.asarray(want).size} elements out of bounds (rtol {rtol}, atol {atol}); "
                              f"first {idx}; worst |d|/m {worst:.3e}")
     return worst

@@ -18,7 +18,7 @@ import pytest
 import paper_1401_6750_amd as dl
 import synth
 from oracle import dirac, loops, noise, solver
-from tests.gpu_util import dev, elementwise, host, make_lattice, rel, torch, zeros_dev
+from tests.gpu_util import dev, elementwise, elementwise_check, host, make_lattice, rel, torch, zeros_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -568,12 +568,18 @@ def test_full_size_hop_sampled(ctx, name):
     lat.close()
 
 
-# Element-wise bounds (atol x max|block|) of the 16-bit LP tier's loops against the
-# oracle on the same solutions, per (flavour, derivative?): the tau_3 local block
-# multiplies stored bf16 values exactly (FP32 sums of 64 sources); the derivative
-# insertions transport with the tier's bf16 links and round the transported vector
-# to bf16; the structure without tau_3 reads xi = (1 - kappa H) s stored in bf16.
-FULL_BF16_TOL = {(0, False): 1e-5, (0, True): 2e-2, (1, False): 1e-2, (1, True): 2e-2}
+# Element-wise bounds of the 16-bit LP tier's loops against the oracle on the same
+# solutions, per (flavour, derivative?): (atol, nblock) for gpu_util.elementwise.  The
+# tau_3 local block multiplies stored bf16 values exactly (FP32 sums of 64 sources),
+# checked per Gamma block.  The derivative insertions transport with the tier's bf16
+# links and round the transported vector to bf16; the structure without tau_3 reads
+# xi = (1 - kappa H) s built with bf16 links and stored in bf16.  Those rounding errors
+# enter all 16 Gamma of one (flavour, op) with one absolute scale, that of the fields,
+# so for the structure without tau_3, whose gamma_5-like blocks are a few hundred
+# times smaller than its scalar block, the scale is the (flavour, op) maximum over
+# Gamma, t and p (nblock 2 on [2][5][16][T][Np]).  Bounds are about 3x the measured
+# worst |d| / m.
+FULL_BF16_TOL = {(0, False): (2e-7, 3), (0, True): (8e-3, 3), (1, False): (1e-3, 2), (1, True): (1e-3, 2)}
 
 
 @pytest.mark.timeout(900)
@@ -609,11 +615,18 @@ def test_full_size_loops_all_sets_from_gpu_solutions(ctx):
         per = list(ex.map(lambda x: loops.source_loops(lat.U, x, lat.kappa, lat.bc, p2, lat.dims), sols))
     pre = lambda x: loops.apply_prefactors(x, lat.kappa, lat.mu)
     want = {dl.DL_SET_LP: pre(per[0] + per[1]), dl.DL_SET_LPC: pre(per[2]), dl.DL_SET_HP: pre(per[3])}
+    failed = []
     for k, name in ((dl.DL_SET_LP, "LP"), (dl.DL_SET_LPC, "LPC")):
         for f in range(2):
             for op in range(5):
-                e = elementwise(sets[k, f, op], want[k][f, op], 0.0, FULL_BF16_TOL[(f, op > 0)], 1)
-                log(f"  {name} flavour {f} op {op}: worst |d|/max|block| {e:.2e}")
+                atol, nb = FULL_BF16_TOL[(f, op > 0)]
+                # blocks of nblock leading axes of [2][5][16][T][Np]
+                e, idx, nbad = elementwise_check(sets[k][f:f + 1, op:op + 1], want[k][f:f + 1, op:op + 1], 0.0,
+                                                 atol, nb)
+                log(f"  {name} flavour {f} op {op}: worst |d|/m {e:.2e} (blocks of {nb} axes, bound {atol:g})")
+                if nbad:
+                    failed.append((name, f, op, e, idx))
+    assert not failed, failed
     e = elementwise(sets[dl.DL_SET_HP], want[dl.DL_SET_HP], 1e-10, 1e-10, 3)
     log(f"  HP (FP64 contraction): worst |d|/max|block| {e:.2e}")
     lat.close()
