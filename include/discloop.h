@@ -261,6 +261,28 @@ int dl_loops(dl_ctx* ctx, dl_accum* acc, int p2max, double* out, int out_on_devi
  * Fig. 2).  Errors as dl_loops. */
 int dl_loops_sets(dl_ctx* ctx, dl_accum* acc, int p2max, double* out, int out_on_device, int* np_out);
 
+/* Bytes of the per-GPU device scratch array of dl_loops_noalloc. */
+#define DL_LOOPS_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* dl_loops for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * same projection, Gamma rebuild, TSM combination and prefactors as dl_loops,
+ * through the same kernels, with out a device pointer (complex128
+ * [2][nops][16][T][Np]); *np_out receives Np.  No hipMalloc, hipFree or other
+ * device allocation: the projection's tables and partial sums use a file-scope
+ * device array of DL_LOOPS_NOALLOC_SCRATCH_BYTES (64 MiB) that every GPU the
+ * library runs on holds from its first dl_create until the process ends.  A
+ * projection needs about 16 (nq T Z n_xy + nq T Np) bytes of it (nq = 48
+ * local, 240 with derivative insertions; n_xy distinct (n_x, n_y) pairs among
+ * the Np momenta): 61 MiB for 24^3 x 48 with derivatives at p^2 <= 4.  A call
+ * that needs more fails with DL_EINVAL before any GPU work.  All calls on one
+ * GPU share the array and every call overwrites all of it that it reads, so
+ * nothing carries over between calls; calls that overlap on one GPU (other
+ * contexts' streams, other threads) race and must be ordered by the caller.
+ * The small index and phase tables are uploaded from host memory with
+ * hipMemcpyAsync.  Errors as dl_loops. */
+int dl_loops_noalloc(dl_ctx* ctx, dl_accum* acc, int p2max, double* out, int* np_out);
+
 /* Gradients of the loops of one job's sources with respect to the sources and
  * to mu, for a real loss F.  The loops are the plain estimator over the job's
  * nsrc sources (what dl_loops returns for an accumulator that holds only

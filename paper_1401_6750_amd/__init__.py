@@ -100,6 +100,7 @@ _SIGS = {
     "dl_momenta": ([ctypes.POINTER(_I), _I, ctypes.POINTER(_I), _I, ctypes.POINTER(_I)], _I),
     "dl_loops": ([_P, _P, _I, _P, _I, ctypes.POINTER(_I)], _I),
     "dl_loops_sets": ([_P, _P, _I, _P, _I, ctypes.POINTER(_I)], _I),
+    "dl_loops_noalloc": ([_P, _P, _I, _P, ctypes.POINTER(_I)], _I),
     "dl_loops_backward": ([_P, ctypes.POINTER(dl_job), _I, _P, _P, _P], _I),
     "dl_set_option": ([_P, ctypes.c_char_p, _D], _I),
     "dl_profile_read": ([_P, _I, ctypes.POINTER(_D)], _I),
@@ -252,6 +253,13 @@ def dl_loops_sets(ctx, acc, p2max: int, out, out_on_device: int) -> int:
     """Per-set loop sums [3][2][nops][16][T][Np] (LP, HP, LPC), not divided by the counts."""
     n = _I()
     _check(lib().dl_loops_sets(ctx, acc, p2max, _ptr(out), out_on_device, ctypes.byref(n)))
+    return n.value
+
+
+def dl_loops_noalloc(ctx, acc, p2max: int, out) -> int:
+    """dl_loops into device memory `out`, using the library's static device scratch (no allocation)."""
+    n = _I()
+    _check(lib().dl_loops_noalloc(ctx, acc, p2max, _ptr(out), ctypes.byref(n)))
     return n.value
 
 

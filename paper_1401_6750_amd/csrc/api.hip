@@ -5,12 +5,37 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "runtime.h"
 
 using namespace dl;
+
+// Device scratch of dl_loops_noalloc: the projection's tables and partial
+// sums live here instead of in pool memory.  Every GPU the library runs on
+// holds its own copy until the process ends.  In host code this name is only
+// a stand-in for the symbol: the device address of a GPU's copy comes from
+// hipGetSymbolAddress with that GPU current (scratch_address, called by
+// dl_create), and only that address is handed to kernels and copies.
+static __device__ __align__(256) unsigned char scratch[DL_LOOPS_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static std::map<int, unsigned char*> g_scratch_ptr;   // device -> address of its copy
+
+// Address of `device`'s copy of the scratch array; `device` must be current.
+static unsigned char* scratch_address(int device) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  if (it != g_scratch_ptr.end()) return it->second;
+  void* ptr = nullptr;
+  HIPCHECK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr) throw Error(DL_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+  g_scratch_ptr[device] = (unsigned char*)ptr;
+  return (unsigned char*)ptr;
+}
 
 static thread_local std::string g_last_error;
 
@@ -59,6 +84,7 @@ int dl_create(dl_ctx** out, int device, void* hip_stream) {
       HIPCHECK(hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking));
       HIPCHECK(hipEventCreateWithFlags(&c->ev, hipEventDisableTiming));
       init_gamma_table();
+      c->scratch = scratch_address(device);
     } catch (...) {
       if (c->st) (void)hipStreamDestroy(c->st);
       if (c->ev) (void)hipEventDestroy(c->ev);
@@ -405,7 +431,30 @@ static std::vector<std::complex<double>> hpe_exact_table(double kappa, double mu
   return out;
 }
 
-static int loops_device(dl_ctx* ctx, dl_accum* a, int p2max, const double (*w)[3], int nw, double* target) {
+// Device buffers of one projection: carved from `scratch` (the no-allocation
+// entry point) or taken from the context pool.
+struct LoopsWork {
+  dl_ctx* ctx;
+  unsigned char* scratch;
+  size_t cap, used = 0;
+  std::vector<DevBuf> held;
+  LoopsWork(dl_ctx* c, unsigned char* s, size_t cp) : ctx(c), scratch(s), cap(cp) {}
+  void* get(size_t bytes) {
+    bytes = std::max<size_t>(bytes, 16);
+    if (!scratch) {
+      held.emplace_back(ctx, bytes);
+      return held.back().p;
+    }
+    void* p = scratch + used;
+    used += (bytes + 255) & ~(size_t)255;
+    return p;
+  }
+};
+
+static size_t round256(size_t b) { return (std::max<size_t>(b, 16) + 255) & ~(size_t)255; }
+
+static int loops_device(dl_ctx* ctx, dl_accum* a, int p2max, const double (*w)[3], int nw, double* target,
+                        unsigned char* scratch, size_t scratch_cap) {
   dl_lattice* L = a->lat;
   auto moms = momentum_list(L->dims, p2max);
   const int np = (int)moms.size();
@@ -468,26 +517,38 @@ static int loops_device(dl_ctx* ctx, dl_accum* a, int p2max, const double (*w)[3
   itab.insert(itab.end(), order.begin(), order.end());
   itab.insert(itab.end(), kx_mod.begin(), kx_mod.end());
   itab.insert(itab.end(), ky_mod.begin(), ky_mod.end());
-  DevBuf dtab(ctx, tabs.size() * sizeof(double)), ditab(ctx, std::max<size_t>(itab.size(), 1) * sizeof(int));
-  HIPCHECK(hipMemcpyAsync(dtab.p, tabs.data(), tabs.size() * sizeof(double), hipMemcpyHostToDevice, ctx->st));
+  const int nops = (a->ops & DL_OPS_DERIV) ? 5 : 1;
+  const int hpe = DL_OPS_HPE_ORDER(a->ops);
+  const size_t per_out = (size_t)2 * 2 * nops * 16 * T * np;   // doubles
+  const size_t tab_bytes = tabs.size() * sizeof(double), itab_bytes = std::max<size_t>(itab.size(), 1) * sizeof(int);
+  const size_t pbytes = std::max<size_t>(sizeof(double) * 2 * (size_t)a->nq * T * np, 16);
+  const size_t r2_bytes = sizeof(double) * 2 * (size_t)a->nq * T * Z * nkxy;
+  const size_t ex_bytes = hpe ? sizeof(double) * 2 * (size_t)nw * nops * 16 : 0;
+  if (scratch) {
+    const size_t need = round256(tab_bytes) + round256(itab_bytes) + round256(pbytes) + round256(r2_bytes) +
+                        (hpe ? round256(ex_bytes) : 0);
+    if (need > scratch_cap)
+      throw Error(DL_EINVAL, "dl_loops_noalloc: this projection needs " + std::to_string(need) +
+                                 " bytes of device scratch, the limit is " + std::to_string(scratch_cap));
+  }
+  LoopsWork wk(ctx, scratch, scratch_cap);
+  double* dtab = (double*)wk.get(tab_bytes);
+  int* ditab = (int*)wk.get(itab_bytes);
+  HIPCHECK(hipMemcpyAsync(dtab, tabs.data(), tab_bytes, hipMemcpyHostToDevice, ctx->st));
   if (!itab.empty())
-    HIPCHECK(hipMemcpyAsync(ditab.p, itab.data(), itab.size() * sizeof(int), hipMemcpyHostToDevice, ctx->st));
+    HIPCHECK(hipMemcpyAsync(ditab, itab.data(), itab.size() * sizeof(int), hipMemcpyHostToDevice, ctx->st));
   ProjTables tb{};
   tb.np = np; tb.nkx = nkx; tb.nkxy = nkxy;
-  const double* dt = dtab.as<double>();
+  const double* dt = dtab;
   tb.roots_x = dt + o_px; tb.roots_y = dt + o_py; tb.pz = dt + o_pz; tb.shift = dt + o_sh;
-  tb.pair_ix = ditab.as<int>(); tb.pj = ditab.as<int>() + nkxy;
+  tb.pair_ix = ditab; tb.pj = ditab + nkxy;
   tb.pk = tb.pj + np; tb.order = tb.pk + np;
   tb.kx_mod = tb.order + np; tb.ky_mod = tb.kx_mod + nkx;
-  const int nops = (a->ops & DL_OPS_DERIV) ? 5 : 1;
-  const size_t per_out = (size_t)2 * 2 * nops * 16 * T * np;   // doubles
-  const size_t pbytes = std::max<size_t>(sizeof(double) * 2 * (size_t)a->nq * T * np, 16);
-  DevBuf proj(ctx, pbytes);
-  DevBuf r2(ctx, std::max<size_t>(sizeof(double) * 2 * (size_t)a->nq * T * Z * nkxy, 16));
+  double* proj = (double*)wk.get(pbytes);
+  double* r2 = (double*)wk.get(r2_bytes);
   // exact part of the hopping parameter expansion: per output, the spatial
   // volume (momentum 0) times the weighted source count of the sets used
-  const int hpe = DL_OPS_HPE_ORDER(a->ops);
-  DevBuf dex;
+  double* dex = nullptr;
   if (hpe) {
     const auto ex = hpe_exact_table(L->kappa, L->mu, hpe, nops);
     std::vector<double> h((size_t)nw * nops * 16 * 2);
@@ -501,8 +562,8 @@ static int loops_device(dl_ctx* ctx, dl_accum* a, int p2max, const double (*w)[3
         h[((size_t)k * nops * 16 + i) * 2 + 1] = f * ex[i].imag();
       }
     }
-    dex = DevBuf(ctx, h.size() * sizeof(double));
-    HIPCHECK(hipMemcpyAsync(dex.p, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, ctx->st));
+    dex = (double*)wk.get(ex_bytes);
+    HIPCHECK(hipMemcpyAsync(dex, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, ctx->st));
     HIPCHECK(hipStreamSynchronize(ctx->st));   // h ends with this scope
   }
   for (int k = 0; k < nw; ++k) {
@@ -510,12 +571,12 @@ static int loops_device(dl_ctx* ctx, dl_accum* a, int p2max, const double (*w)[3
     for (int s = 0; s < 3; ++s) sets[s] = (w[k][s] != 0.0 && a->count[s] > 0) ? a->acc[s] : nullptr;
     if (sets[0] || sets[1] || sets[2]) {
       // derivative rows (q >= 48) hold link-centred sums
-      launch_project(sets, w[k], a->nq, 48, X, Y, Z, T, tb, r2.as<double>(), proj.as<double>(), ctx->st);
+      launch_project(sets, w[k], a->nq, 48, X, Y, Z, T, tb, r2, proj, ctx->st);
     } else {
-      HIPCHECK(hipMemsetAsync(proj.p, 0, pbytes, ctx->st));
+      launch_fill_zero(proj, pbytes / sizeof(double), ctx->st);
     }
-    const double* exk = hpe ? dex.as<double>() + (size_t)k * nops * 16 * 2 : nullptr;
-    launch_loops_finalize(proj.as<double>(), nops, T, np, L->kappa, L->mu, exk, target + k * per_out, ctx->st);
+    const double* exk = hpe ? dex + (size_t)k * nops * 16 * 2 : nullptr;
+    launch_loops_finalize(proj, nops, T, np, L->kappa, L->mu, exk, target + k * per_out, ctx->st);
   }
   HIPCHECK(hipGetLastError());
   return np;
@@ -535,7 +596,7 @@ static void loops_common(dl_ctx* ctx, dl_accum* a, int p2max, const double (*w)[
     dout = DevBuf(ctx, std::max<size_t>(obytes, 16));
     target = dout.as<double>();
   }
-  loops_device(ctx, a, p2max, w, nw, target);
+  loops_device(ctx, a, p2max, w, nw, target, nullptr, 0);
   if (!out_on_device) {
     HIPCHECK(hipMemcpyAsync(out, target, obytes, hipMemcpyDeviceToHost, ctx->st));
     HIPCHECK(hipStreamSynchronize(ctx->st));
@@ -543,25 +604,48 @@ static void loops_common(dl_ctx* ctx, dl_accum* a, int p2max, const double (*w)[
   stream_exit(ctx);
 }
 
+// Checks of dl_loops / dl_loops_noalloc and the TSM weights of the three sets.
+static void tsm_weights(dl_ctx* ctx, dl_accum* a, int p2max, const double* out, const char* fn, double w[3]) {
+  const std::string f(fn);
+  require(ctx && a && out, f + ": NULL argument");
+  require(p2max >= 0, f + ": p2max must be >= 0");
+  dl_lattice* L = a->lat;
+  require(L->ctx == ctx, f + ": accumulator of another context");
+  require(L->params_set, f + ": kappa / mu not set");
+  require(a->count[DL_SET_LPC] == 0 || a->count[DL_SET_LPC] == a->count[DL_SET_HP],
+          f + ": the LPC set must hold the same sources as the HP set");
+  // with both LP and HP sources the estimate is the TSM one, which needs the
+  // LP solves of the HP sources; S_LP / N_LP + S_HP / N_HP would count the loop twice
+  require(a->count[DL_SET_LP] == 0 || a->count[DL_SET_HP] == 0 || a->count[DL_SET_LPC] == a->count[DL_SET_HP],
+          f + ": LP and HP sets without the LPC set (the LP solves of the HP sources) form no estimator");
+  // TSM combination L = S_LP / N_LP + (S_HP - S_LPC) / N_HP, taken on the
+  // accumulators so one projection serves all three sets
+  const double w_lp = a->count[DL_SET_LP] > 0 ? 1.0 / (double)a->count[DL_SET_LP] : 0.0;
+  const double w_hp = a->count[DL_SET_HP] > 0 ? 1.0 / (double)a->count[DL_SET_HP] : 0.0;
+  w[0] = w_lp;
+  w[1] = w_hp;
+  w[2] = -w_hp;
+}
+
 int dl_loops(dl_ctx* ctx, dl_accum* a, int p2max, double* out, int out_on_device, int* np_out) {
   return guarded([&] {
-    require(ctx && a && out, "dl_loops: NULL argument");
-    require(p2max >= 0, "dl_loops: p2max must be >= 0");
-    dl_lattice* L = a->lat;
-    require(L->ctx == ctx, "dl_loops: accumulator of another context");
-    require(L->params_set, "dl_loops: kappa / mu not set");
-    require(a->count[DL_SET_LPC] == 0 || a->count[DL_SET_LPC] == a->count[DL_SET_HP],
-            "dl_loops: the LPC set must hold the same sources as the HP set");
-    // with both LP and HP sources the estimate is the TSM one, which needs the
-    // LP solves of the HP sources; S_LP / N_LP + S_HP / N_HP would count the loop twice
-    require(a->count[DL_SET_LP] == 0 || a->count[DL_SET_HP] == 0 || a->count[DL_SET_LPC] == a->count[DL_SET_HP],
-            "dl_loops: LP and HP sets without the LPC set (the LP solves of the HP sources) form no estimator");
-    // TSM combination L = S_LP / N_LP + (S_HP - S_LPC) / N_HP, taken on the
-    // accumulators so one projection serves all three sets
-    const double w_lp = a->count[DL_SET_LP] > 0 ? 1.0 / (double)a->count[DL_SET_LP] : 0.0;
-    const double w_hp = a->count[DL_SET_HP] > 0 ? 1.0 / (double)a->count[DL_SET_HP] : 0.0;
-    const double w[1][3] = {{w_lp, w_hp, -w_hp}};
+    double w[1][3];
+    tsm_weights(ctx, a, p2max, out, "dl_loops", w[0]);
     loops_common(ctx, a, p2max, w, 1, out, out_on_device, np_out);
+    return 0;
+  });
+}
+
+int dl_loops_noalloc(dl_ctx* ctx, dl_accum* a, int p2max, double* out, int* np_out) {
+  return guarded([&] {
+    double w[1][3];
+    tsm_weights(ctx, a, p2max, out, "dl_loops_noalloc", w[0]);
+    require(ctx->scratch != nullptr, "dl_loops_noalloc: context has no scratch address");
+    const int np = (int)momentum_list(a->lat->dims, p2max).size();
+    if (np_out) *np_out = np;
+    stream_enter(ctx);
+    loops_device(ctx, a, p2max, w, 1, out, ctx->scratch, DL_LOOPS_NOALLOC_SCRATCH_BYTES);
+    stream_exit(ctx);
     return 0;
   });
 }

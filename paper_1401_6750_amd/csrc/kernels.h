@@ -134,6 +134,9 @@ struct ProjTables {
 void launch_project(const double* const acc[3], const double w[3], int nq, int q_link, int X, int Y, int Z, int T,
                     const ProjTables& tb, double* r2, double* proj, hipStream_t st);
 
+// Zero n doubles with a fill kernel.
+void launch_fill_zero(double* p, long long n, hipStream_t st);
+
 // Gamma rebuild and prefactors -> out [2][nops][16][T][Np] complex.
 // exact (device [nops][16] complex, or null): added to the loops without
 // tau_3 at momentum 0 before the prefactor (exact part of the hopping

@@ -140,6 +140,17 @@ void launch_project(const double* const acc[3], const double w[3], int nq, int q
                      (double2*)proj);
 }
 
+__global__ __launch_bounds__(256) void k_fill_zero(double* p, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+// Zero n doubles with a kernel (a fill that a captured graph replays faithfully).
+void launch_fill_zero(double* p, long long n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
+}
+
 // ---------------------------------------------------------------------------
 // final assembly: Gamma rebuild and prefactors (the TSM sets are combined
 // before the projection)

@@ -36,6 +36,7 @@ struct dl_ctx {
   hipStream_t user_stream = nullptr;
   hipStream_t st = nullptr;      // internal stream all work runs on
   hipEvent_t ev = nullptr;
+  unsigned char* scratch = nullptr;   // this GPU's copy of dl_loops_noalloc's scratch array
   dl::Pool pool;
   std::map<std::string, int> tune;   // autotuned rhs block / tile-order block per (dims, precision, size)
   std::string tune_path;
