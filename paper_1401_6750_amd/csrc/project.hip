@@ -130,7 +130,13 @@ void launch_project(const double* const acc[3], const double w[3], int nq, int q
   if (tb.np <= 0 || nq <= 0) return;
   const long long vp = pad_half((long long)X * Y * Z * T / 2);
   const size_t lds = sizeof(double) * (size_t)X * Y + sizeof(double2) * ((size_t)Y * tb.nkx + X + Y);
-  if (lds > 65536) throw std::runtime_error("momentum projection: x-y plane too large for LDS");
+  // gfx950 gives a workgroup up to 160 KiB of LDS; above 64 KiB the kernel
+  // has to be allowed the larger dynamic allocation first
+  if (lds > 163840) throw std::runtime_error("momentum projection: x-y plane too large for LDS");
+  if (lds > 65536 &&
+      hipFuncSetAttribute((const void*)k_proj_plane, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+          hipSuccess)
+    throw std::runtime_error("momentum projection: cannot raise the LDS limit of k_proj_plane");
   hipLaunchKernelGGL(k_proj_plane, dim3((unsigned)(nq * T * Z)), dim3(256), lds, st, acc[0], acc[1], acc[2], w[0],
                      w[1], w[2], X, Y, Z, T, vp, tb.nkx, tb.nkxy, (const double2*)tb.roots_x,
                      (const double2*)tb.roots_y, tb.kx_mod, tb.ky_mod, tb.pair_ix, (double2*)r2);

@@ -97,3 +97,23 @@ def test_wilson_operator_and_loops(ctx):
     with pytest.raises(dl.DiscloopError):
         dl.dl_loops_backward(ctx, dl.make_job(la.h, nsrc=1, tol=1e-8), p2, g, None, gm)
     la.close()
+
+
+def test_wide_plane_projection_above_64k_lds(ctx):
+    """A 96 x 96 x-y plane: the projection's LDS plane (96 * 96 doubles plus the
+    x-transform and the roots, 81 KB at p^2 <= 2) exceeds 64 KiB and uses the larger
+    per-workgroup LDS of gfx950; loops match the oracle to 1e-10."""
+    la = make_lattice(ctx, (96, 96, 2, 2), 1413, 0.3, 0.1, 0.05)
+    seed, nsrc, p2 = 53, 1, 2
+    acc = dl.dl_accum_create(la.h, dl.DL_OPS_LOCAL | dl.DL_OPS_DERIV)
+    rc, _ = dl.dl_solve_batch(ctx, dl.make_job(la.h, noise=dl.DL_NOISE_Z4, tier=dl.DL_TIER_FP64, seed=seed,
+                                               nsrc=nsrc, tol=1e-11, maxiter=1000, accum=acc,
+                                               accum_set=dl.DL_SET_HP))
+    assert rc == dl.DL_OK
+    moms = loops.momenta(p2, la.dims)
+    out = np.zeros((2, 5, 16, la.dims[3], len(moms)), dtype=np.complex128)
+    assert dl.dl_loops(ctx, acc, p2, out, 0) == len(moms)
+    want = loops.estimate(np.array([per_source(la, seed, r, p2) for r in range(nsrc)]), la.kappa, la.mu)
+    log("wide plane worst |d|/max|block|", elementwise(out, want, 1e-10, 1e-10, 3))
+    dl.dl_accum_destroy(acc)
+    la.close()
