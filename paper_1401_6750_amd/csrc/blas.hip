@@ -73,7 +73,7 @@ __global__ __launch_bounds__(64) void k_finalize(int kind, const SlotDesc* slots
       break;
     }
     case FK_STORE:
-      cs.out[g] = v;
+      if (!cs.active || cs.active[g]) cs.out[g] = v;   // the gate: rhs whose partials were written
       break;
   }
 }
@@ -83,6 +83,77 @@ void launch_finalize(int kind, const SlotDesc* slots, int nslots, int nrhs_total
   if (nrhs_total == 0) return;
   hipLaunchKernelGGL(k_finalize, dim3(nrhs_total), dim3(64), 0, st, kind, slots, nslots, nrhs_total,
                      partial, cs);
+}
+
+// ---------------------------------------------------------------------------
+// reliable-update decisions of the high-precision tier, one thread per rhs
+// (the same rules the host applies between plain launches)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_hp_decide(int nrhs, CgScalars cs, HpState hp) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nrhs) return;
+  int h = 0;
+  const double rr = cs.rr[g];
+  if (cs.active[g]) {
+    // no update within 100x (in <r, r>) of the target: the verification's own
+    // FP64 residual follows shortly
+    if (rr < hp.delta2 * hp.rr_ru[g] && rr > 1e2 * (cs.tol2[g] * cs.cc[g])) h = 1;
+  } else if (cs.status[g] == 0 && !hp.verified[g] && cs.cc[g] > 0) {
+    h = 2;
+  }
+  hp.hflag[g] = h;
+  hp.flag[g] = h != 0;
+  hp.react[g] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_hp_post(int nrhs, CgScalars cs, HpState hp) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nrhs) return;
+  const int h = hp.hflag[g];
+  if (!h) return;
+  hp.ru_count[g] += 1;
+  const double rr = cs.rr[g];
+  hp.rr_ru[g] = rr;
+  if (h == 2) {
+    if (rr <= cs.tol2[g] * cs.cc[g]) {
+      hp.verified[g] = 1;
+    } else if (cs.iters[g] < cs.maxiter[g]) {
+      hp.react[g] = 1;
+      cs.active[g] = 1;
+      cs.status[g] = 1;
+    } else {
+      hp.verified[g] = 1;
+      cs.status[g] = 1;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_hp_pending(int nrhs, CgScalars cs, HpState hp) {
+  __shared__ int cnt[256];
+  int n = 0;
+  for (int g = threadIdx.x; g < nrhs; g += blockDim.x)
+    n += cs.active[g] || (cs.status[g] == 0 && !hp.verified[g] && cs.cc[g] > 0);
+  cnt[threadIdx.x] = n;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) cnt[threadIdx.x] += cnt[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) hp.pending[0] = cnt[0];
+}
+
+void launch_hp_decide(int nrhs, const CgScalars& cs, const HpState& hp, hipStream_t st) {
+  if (nrhs <= 0) return;
+  hipLaunchKernelGGL(k_hp_decide, dim3((nrhs + 255) / 256), dim3(256), 0, st, nrhs, cs, hp);
+}
+
+void launch_hp_post(int nrhs, const CgScalars& cs, const HpState& hp, hipStream_t st) {
+  if (nrhs <= 0) return;
+  hipLaunchKernelGGL(k_hp_post, dim3((nrhs + 255) / 256), dim3(256), 0, st, nrhs, cs, hp);
+}
+
+void launch_hp_pending(int nrhs, const CgScalars& cs, const HpState& hp, hipStream_t st) {
+  hipLaunchKernelGGL(k_hp_pending, dim3(1), dim3(256), 0, st, nrhs, cs, hp);
 }
 
 // ---------------------------------------------------------------------------

@@ -56,6 +56,29 @@ struct CgScalars {
 void launch_finalize(int kind, const SlotDesc* slots, int nslots, int nrhs_total,
                      const double* partial, const CgScalars& cs, hipStream_t st);
 
+// Per-rhs state of the reliable updates of the high-precision tier, kept on
+// the device so that a whole step (decision, update, CG iteration) replays
+// from a graph without the host.
+struct HpState {
+  double* rr_ru;   // <r, r> right after the last reliable update
+  int* hflag;      // this step: 0 nothing, 1 reliable update, 2 verification of an rhs whose
+                   // iterated residual converged
+  int* flag;       // hflag != 0: gate of the update kernels
+  int* react;      // verification failed: CG restarts from the true residual this step
+  int* verified;   // converged and verified (or given up at the iteration cap)
+  int* ru_count;   // reliable updates so far
+  int* pending;    // [1] rhs still iterating or awaiting verification (after k_hp_pending)
+  double delta2;   // update when <r, r> fell below delta2 times its value after the last one
+};
+// Decide, per rhs, this step's reliable update or verification (sets hflag,
+// flag, clears react).
+void launch_hp_decide(int nrhs, const CgScalars& cs, const HpState& hp, hipStream_t st);
+// After the update of the flagged rhs: count it, record <r, r>, and settle
+// verifications (verified, restart with react, or iteration cap).
+void launch_hp_post(int nrhs, const CgScalars& cs, const HpState& hp, hipStream_t st);
+// hp.pending[0] = number of rhs still active or awaiting verification.
+void launch_hp_pending(int nrhs, const CgScalars& cs, const HpState& hp, hipStream_t st);
+
 // x += alpha p where upd is set (every rhs that took this iteration's step),
 // Initial guesses: copy the odd solution field of every slot with gsave to
 // its guess buffer (raw words, the field's precision), and load slots with

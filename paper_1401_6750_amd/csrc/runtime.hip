@@ -561,6 +561,83 @@ static void run_cg_plain(Batch& b, int P, const CgFields& f, int maxiter_all, in
   HIPCHECK(hipGraphDestroy(graph));
 }
 
+// High-precision tier, replayed from a graph: one step = decide (per rhs: a
+// reliable update, a verification of a converged residual, or nothing), the
+// FP64 update of the flagged rhs, its bookkeeping (restart from the true
+// residual where the verification failed: p = r), then one CG iteration of
+// every active rhs.  Each rhs goes through the same sequence of updates and
+// iterations as with the host-driven loop, so the results are the same bit for
+// bit; the host only reads the number of pending rhs between bursts.
+template <class RU>
+static void hp_graph_loop(Batch& b, const CgFields& f, int* flag, RU& reliable_update,
+                          const std::vector<double>& rr_ru, const std::vector<int>& verified,
+                          std::vector<int>& ru_count, int maxiter_all, int first_burst, double delta2) {
+  dl_ctx* c = b.ctx;
+  hipStream_t st = c->st;
+  const int n = b.nrhs;
+  DevBuf buf(c, sizeof(double) * n + sizeof(int) * (5 * (size_t)n + 1) + 16);
+  HpState hp{};
+  hp.rr_ru = buf.as<double>();
+  int* ib = (int*)(hp.rr_ru + n);
+  hp.hflag = ib;
+  hp.flag = flag;
+  hp.react = ib + n;
+  hp.verified = ib + 2 * n;
+  hp.ru_count = ib + 3 * n;
+  hp.pending = ib + 4 * n;
+  hp.delta2 = delta2;
+  HIPCHECK(hipMemcpyAsync(hp.rr_ru, rr_ru.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+  HIPCHECK(hipMemcpyAsync(hp.verified, verified.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
+  HIPCHECK(hipMemcpyAsync(hp.ru_count, ru_count.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
+  HIPCHECK(hipMemsetAsync(hp.hflag, 0, sizeof(int) * 2 * n, st));
+  HIPCHECK(hipStreamSynchronize(st));   // the host vectors may change after this call
+
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  HIPCHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  try {
+    launch_hp_decide(n, b.cs, hp, st);
+    reliable_update(hp.flag);
+    launch_hp_post(n, b.cs, hp, st);
+    launch_convert(P32, P32, b.slots(), b.nslots, b.u_rhs, f.r, f.p, 0, hp.react, st);
+    cg_iteration(b, P32, f);
+    launch_hp_pending(n, b.cs, hp, st);
+  } catch (...) {
+    hipGraph_t g2 = nullptr;
+    (void)hipStreamEndCapture(st, &g2);
+    if (g2) (void)hipGraphDestroy(g2);
+    throw;
+  }
+  HIPCHECK(hipStreamEndCapture(st, &graph));
+  hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (ie != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    HIPCHECK(ie);
+  }
+  // the host loop's pass limit, counted in steps
+  const int max_steps = 4 * maxiter_all + 16;
+  int steps = 0, burst = std::max(1, first_burst);
+  try {
+    while (steps < max_steps) {
+      const int k = std::min(burst, max_steps - steps);
+      for (int i = 0; i < k; ++i) HIPCHECK(hipGraphLaunch(exec, st));
+      steps += k;
+      HIPCHECK(hipMemcpyAsync(b.h_int, hp.pending, sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHECK(hipStreamSynchronize(st));
+      if (b.h_int[0] == 0) break;
+      burst = 1;
+    }
+  } catch (...) {
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    throw;
+  }
+  HIPCHECK(hipGraphExecDestroy(exec));
+  HIPCHECK(hipGraphDestroy(graph));
+  HIPCHECK(hipMemcpyAsync(ru_count.data(), hp.ru_count, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+}
+
 // ---------------------------------------------------------------------------
 // the batch pipeline
 // ---------------------------------------------------------------------------
@@ -652,13 +729,13 @@ void run_batch(dl_ctx* ctx, int tier, const std::vector<SlotPlan>& plan, const s
     b.to_host_dbl(b.cs.cc, b.h_dbl);
     b.sync();
     for (int g = 0; g < b.nrhs; ++g) cc[g] = b.h_dbl[g];
-    std::vector<double> tolv(b.nrhs);
+    std::vector<double> tol2v(b.nrhs);
     std::vector<int> maxit(b.nrhs);
     {
       int g = 0;
       for (const SlotPlan& sp : plan)
         for (int q = 0; q < sp.nrhs; ++q, ++g) {
-          tolv[g] = jobs[sp.job].tol;
+          tol2v[g] = jobs[sp.job].tol * jobs[sp.job].tol;   // as cs.tol2
           maxit[g] = jobs[sp.job].maxiter;
         }
     }
@@ -693,7 +770,7 @@ void run_batch(dl_ctx* ctx, int tier, const std::vector<SlotPlan>& plan, const s
       const int zero = 0;
       for (int g = 0; g < b.nrhs; ++g) {
         rr_ru[g] = b.h_dbl[g];
-        if (cc[g] > 0 && b.h_dbl[g] <= tolv[g] * tolv[g] * cc[g]) {   // the guess already converged
+        if (cc[g] > 0 && b.h_dbl[g] <= tol2v[g] * cc[g]) {   // the guess already converged
           verified[g] = 1;
           HIPCHECK(hipMemcpyAsync(b.cs.active + g, &zero, sizeof(int), hipMemcpyHostToDevice, st));
           HIPCHECK(hipMemcpyAsync(b.cs.status + g, &zero, sizeof(int), hipMemcpyHostToDevice, st));
@@ -701,95 +778,102 @@ void run_batch(dl_ctx* ctx, int tier, const std::vector<SlotPlan>& plan, const s
       }
       b.sync();
     }
-    int guard = 0;
-    while (true) {
-      // state after the previous step
-      int* act = b.h_int;
-      int* status = b.h_int + b.nrhs;
-      int* iters = b.h_int + 2 * b.nrhs;
-      b.to_host_int(b.cs.active, act);
-      b.to_host_int(b.cs.status, status);
-      b.to_host_int(b.cs.iters, iters);
-      b.to_host_dbl(b.cs.rr, b.h_dbl);
-      b.sync();
-      bool any_flag = false, any_active = false;
-      for (int g = 0; g < b.nrhs; ++g) {
-        hflag[g] = 0;
-        if (act[g]) {
-          any_active = true;
-          // no update within 100x (in |r|^2) of the target: the convergence
-          // check's own FP64 residual follows shortly
-          if (b.h_dbl[g] < delta2 * rr_ru[g] && b.h_dbl[g] > 1e2 * tolv[g] * tolv[g] * cc[g]) hflag[g] = 1;
-        } else if (status[g] == 0 && !verified[g] && cc[g] > 0) {
-          hflag[g] = 2;   // iterated residual converged: verify with the true residual
-        }
-        any_flag = any_flag || hflag[g];
-      }
-      if (!any_active && !any_flag) break;
-      if (++guard > 4 * maxiter_all + 16) break;
-      if (any_flag) {
-        std::vector<int> f01(b.nrhs);
-        for (int g = 0; g < b.nrhs; ++g) f01[g] = hflag[g] != 0;
-        HIPCHECK(hipMemcpyAsync(flag.p, f01.data(), sizeof(int) * b.nrhs, hipMemcpyHostToDevice, st));
-        reliable_update(flag.as<int>());
+    if (ctx->profile || !ctx->use_graph) {
+      // host-driven: the state goes to the host after every step, each step is
+      // either the flagged rhs' reliable updates or one CG iteration
+      int guard = 0;
+      while (true) {
+        // state after the previous step
+        int* act = b.h_int;
+        int* status = b.h_int + b.nrhs;
+        int* iters = b.h_int + 2 * b.nrhs;
+        b.to_host_int(b.cs.active, act);
+        b.to_host_int(b.cs.status, status);
+        b.to_host_int(b.cs.iters, iters);
         b.to_host_dbl(b.cs.rr, b.h_dbl);
         b.sync();
-        std::vector<int> react;
+        bool any_flag = false, any_active = false;
         for (int g = 0; g < b.nrhs; ++g) {
-          if (!hflag[g]) continue;
-          ru_count[g]++;
-          rr_ru[g] = b.h_dbl[g];
-          if (hflag[g] == 2) {
-            if (b.h_dbl[g] <= tolv[g] * tolv[g] * cc[g]) {
-              verified[g] = 1;
-            } else if (iters[g] < maxit[g]) {
-              react.push_back(g);       // restart CG from the true residual
-            } else {
-              verified[g] = 1;
-              status[g] = 1;
-              HIPCHECK(hipMemcpyAsync(b.cs.status + g, &status[g], sizeof(int), hipMemcpyHostToDevice, st));
-              b.sync();
+          hflag[g] = 0;
+          if (act[g]) {
+            any_active = true;
+            // no update within 100x (in |r|^2) of the target: the convergence
+            // check's own FP64 residual follows shortly
+            if (b.h_dbl[g] < delta2 * rr_ru[g] && b.h_dbl[g] > 1e2 * (tol2v[g] * cc[g])) hflag[g] = 1;
+          } else if (status[g] == 0 && !verified[g] && cc[g] > 0) {
+            hflag[g] = 2;   // iterated residual converged: verify with the true residual
+          }
+          any_flag = any_flag || hflag[g];
+        }
+        if (!any_active && !any_flag) break;
+        if (++guard > 4 * maxiter_all + 16) break;
+        if (any_flag) {
+          std::vector<int> f01(b.nrhs);
+          for (int g = 0; g < b.nrhs; ++g) f01[g] = hflag[g] != 0;
+          HIPCHECK(hipMemcpyAsync(flag.p, f01.data(), sizeof(int) * b.nrhs, hipMemcpyHostToDevice, st));
+          reliable_update(flag.as<int>());
+          b.to_host_dbl(b.cs.rr, b.h_dbl);
+          b.sync();
+          std::vector<int> react;
+          for (int g = 0; g < b.nrhs; ++g) {
+            if (!hflag[g]) continue;
+            ru_count[g]++;
+            rr_ru[g] = b.h_dbl[g];
+            if (hflag[g] == 2) {
+              if (b.h_dbl[g] <= tol2v[g] * cc[g]) {
+                verified[g] = 1;
+              } else if (iters[g] < maxit[g]) {
+                react.push_back(g);       // restart CG from the true residual
+              } else {
+                verified[g] = 1;
+                status[g] = 1;
+                HIPCHECK(hipMemcpyAsync(b.cs.status + g, &status[g], sizeof(int), hipMemcpyHostToDevice, st));
+                b.sync();
+              }
             }
           }
-        }
-        if (!react.empty()) {
-          std::vector<int> ga(b.nrhs, 0);
-          for (int g : react) ga[g] = 1;
-          HIPCHECK(hipMemcpyAsync(flag.p, ga.data(), sizeof(int) * b.nrhs, hipMemcpyHostToDevice, st));
-          launch_convert(P32, P32, b.slots(), b.nslots, b.u_rhs, r.p, p.p, 0, flag.as<int>(), st);
-          const int one = 1;
-          for (int g : react) {
-            HIPCHECK(hipMemcpyAsync(b.cs.active + g, &one, sizeof(int), hipMemcpyHostToDevice, st));
-            HIPCHECK(hipMemcpyAsync(b.cs.status + g, &one, sizeof(int), hipMemcpyHostToDevice, st));
+          if (!react.empty()) {
+            std::vector<int> ga(b.nrhs, 0);
+            for (int g : react) ga[g] = 1;
+            HIPCHECK(hipMemcpyAsync(flag.p, ga.data(), sizeof(int) * b.nrhs, hipMemcpyHostToDevice, st));
+            launch_convert(P32, P32, b.slots(), b.nslots, b.u_rhs, r.p, p.p, 0, flag.as<int>(), st);
+            const int one = 1;
+            for (int g : react) {
+              HIPCHECK(hipMemcpyAsync(b.cs.active + g, &one, sizeof(int), hipMemcpyHostToDevice, st));
+              HIPCHECK(hipMemcpyAsync(b.cs.status + g, &one, sizeof(int), hipMemcpyHostToDevice, st));
+            }
+            b.sync();
           }
-          b.sync();
+          continue;
         }
-        continue;
+        if (ctx->profile) {
+          // time this iteration's hopping launch (u_e = A^-1 H_eo p_o) as the plain CG does
+          std::vector<int> act(b.nrhs);
+          b.to_host_int(b.cs.active, act.data());
+          b.sync();
+          hipEvent_t e0, e1;
+          HIPCHECK(hipEventCreate(&e0));
+          HIPCHECK(hipEventCreate(&e1));
+          cg_iteration(b, P32, f, e0, e1);
+          HIPCHECK(hipEventSynchronize(e1));
+          float ms = 0.f;
+          HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+          (void)hipEventDestroy(e0);
+          (void)hipEventDestroy(e1);
+          double* pr = ctx->prof[P32];
+          int na = 0;
+          for (int g = 0; g < b.nrhs; ++g) na += act[g] != 0;
+          pr[0] += 1;
+          pr[1] += ms;
+          pr[2] += hop_launch_bytes(b, P32, act.data());
+          pr[3] += na;
+        } else {
+          cg_iteration(b, P32, f);
+        }
       }
-      if (ctx->profile) {
-        // time this iteration's hopping launch (u_e = A^-1 H_eo p_o) as the plain CG does
-        std::vector<int> act(b.nrhs);
-        b.to_host_int(b.cs.active, act.data());
-        b.sync();
-        hipEvent_t e0, e1;
-        HIPCHECK(hipEventCreate(&e0));
-        HIPCHECK(hipEventCreate(&e1));
-        cg_iteration(b, P32, f, e0, e1);
-        HIPCHECK(hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        double* pr = ctx->prof[P32];
-        int na = 0;
-        for (int g = 0; g < b.nrhs; ++g) na += act[g] != 0;
-        pr[0] += 1;
-        pr[1] += ms;
-        pr[2] += hop_launch_bytes(b, P32, act.data());
-        pr[3] += na;
-      } else {
-        cg_iteration(b, P32, f);
-      }
+    } else {
+      hp_graph_loop(b, f, flag.as<int>(), reliable_update, rr_ru, verified, ru_count, maxiter_all, first_burst,
+                    delta2);
     }
     // fold the last FP32 correction; reconstruct in FP64
     launch_convert(P32, P64, b.slots(), b.nslots, b.u_rhs, x.p, xhi.p, 1, nullptr, st);

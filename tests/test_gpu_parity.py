@@ -495,6 +495,47 @@ def test_graph_replay_equals_plain_launches(ctx):
     lat.close()
 
 
+def test_hp_graph_equals_host_driven(ctx):
+    """The high-precision tier replayed from a graph (reliable-update decisions on the
+    device) gives the same bits as the host-driven loop: solutions, iteration and
+    reliable-update counts, residuals, status and loops; with and without LP starting
+    guesses, at a tolerance that forces restarts from the true residual, and at an
+    iteration cap."""
+    lat = make_lattice(ctx, (8, 8, 8, 8), 26, 0.2, 0.1615, 0.004)
+    n = 6
+    cases = [dict(tol=1e-8, maxiter=2000, guess=True), dict(tol=1e-10, maxiter=2000, guess=False),
+             dict(tol=1e-8, maxiter=6, guess=False)]
+    for cs in cases:
+        runs = []
+        for use_graph in (1, 0):
+            dl.dl_set_option(ctx, "use_graph", use_graph)
+            sol = zeros_dev((n,) + lat.field_shape)
+            acc = dl.dl_accum_create(lat.h, dl.DL_OPS_LOCAL | dl.DL_OPS_DERIV)
+            hp = dl.make_job(lat.h, noise=dl.DL_NOISE_Z4, tier=dl.DL_TIER_HP_FP32, seed=8, nsrc=n, tol=cs["tol"],
+                             maxiter=cs["maxiter"], rhs_block=4, sol_out=sol, accum=acc, accum_set=dl.DL_SET_HP,
+                             guess_from=2 if cs["guess"] else 0)
+            jobs = [hp]
+            if cs["guess"]:
+                jobs = [hp, dl.make_job(lat.h, noise=dl.DL_NOISE_Z4, tier=dl.DL_TIER_LP_BF16, seed=8, nsrc=n,
+                                        tol=1e-2, maxiter=500)]
+            rc, st = dl.dl_solve_batch(ctx, jobs)
+            out = np.zeros((2, 5, 16, 8, 1), dtype=np.complex128)
+            dl.dl_loops(ctx, acc, 0, out, 0)
+            dl.dl_accum_destroy(acc)
+            runs.append((rc, host(sol), [(x.iters, x.status, x.reliable_updates, x.rel_resid) for x in st[:n]], out))
+        dl.dl_set_option(ctx, "use_graph", 1)
+        (rg, sg, tg, lg), (rp, sp, tp, lp) = runs
+        log(f"hp graph vs host {cs}: rc {rg} stats {tg}")
+        assert rg == rp and tg == tp
+        assert np.array_equal(sg, sp) and np.array_equal(lg, lp)
+        if cs["maxiter"] == 6:
+            assert rg == dl.DL_NOT_CONVERGED and all(t[1] == dl.DL_SRC_MAXITER for t in tg)
+        else:
+            assert rg == dl.DL_OK and all(t[1] == dl.DL_SRC_CONVERGED for t in tg)
+            assert all(t[2] >= 1 for t in tg)
+    lat.close()
+
+
 # fp16 loops against the oracle on the same solutions, per (flavour, derivative?)
 UNEVEN_FP16_TOL = {(0, False): 1e-5, (0, True): 2e-3, (1, False): 2e-3, (1, True): 2e-3}
 
