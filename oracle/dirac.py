@@ -138,19 +138,36 @@ def apply_spin_diag(d, psi):
     return psi * d[:, None]
 
 
-def apply_M(U, psi, kappa, mu, bc_t):
-    """M(mu) psi = psi - kappa H psi + 2 i kappa mu gamma_5 psi."""
-    return psi - kappa * hop(U, psi, bc_t) + 2j * kappa * mu * spin_mul(GAMMA5, psi)
+def _clover(C, psi):
+    """C psi for a clover term C [..., 4, 3, 4, 3] (oracle/clover.py), 0 without one."""
+    if C is None:
+        return 0.0
+    return np.einsum("...sarb,...rb->...sa", C, psi)
 
 
-def apply_Mdag(U, psi, kappa, mu, bc_t):
-    """M(mu)^dag psi = psi - kappa H^dag psi - 2 i kappa mu gamma_5 psi."""
-    return psi - kappa * hop(U, psi, bc_t, dagger=True) - 2j * kappa * mu * spin_mul(GAMMA5, psi)
+def apply_M(U, psi, kappa, mu, bc_t, C=None):
+    """M(mu) psi = psi - kappa H psi + 2 i kappa mu gamma_5 psi (+ C psi with a clover term)."""
+    return psi - kappa * hop(U, psi, bc_t) + 2j * kappa * mu * spin_mul(GAMMA5, psi) + _clover(C, psi)
 
 
-def apply_M0(U, psi, kappa, bc_t):
-    """The mu-independent part M_0 = 1 - kappa H (= 2 kappa D_W)."""
-    return psi - kappa * hop(U, psi, bc_t)
+def apply_Mdag(U, psi, kappa, mu, bc_t, C=None):
+    """M(mu)^dag psi = psi - kappa H^dag psi - 2 i kappa mu gamma_5 psi (+ C psi, C hermitian)."""
+    return (psi - kappa * hop(U, psi, bc_t, dagger=True) - 2j * kappa * mu * spin_mul(GAMMA5, psi)
+            + _clover(C, psi))
+
+
+def apply_M0(U, psi, kappa, bc_t, C=None):
+    """The mu-independent part M_0 = 1 - kappa H (= 2 kappa D_W), plus C with a clover term."""
+    return psi - kappa * hop(U, psi, bc_t) + _clover(C, psi)
+
+
+def apply_A_inv(psi, kappa, mu, C=None):
+    """A^-1 psi with the site-diagonal part A = 1 + 2 i kappa mu gamma_5 (+ C): per spin,
+    or by a 12 x 12 linear solve per site with a clover term."""
+    if C is None:
+        return apply_spin_diag(1.0 / twist_diag(kappa, mu), psi)
+    from . import clover
+    return clover.apply_site_inverse(C, kappa, mu, psi)
 
 
 def hop_at_sites(U, psi, bc_t, sites):
@@ -198,7 +215,7 @@ def project(psi, mask):
     return psi * mask
 
 
-def Mhat(U, psi_o, kappa, mu, bc_t, dims):
+def Mhat(U, psi_o, kappa, mu, bc_t, dims, C=None):
     """Schur complement on odd sites: 1 - kappa^2 A_o^-1 H_oe A_e^-1 H_eo.
 
     With M = [[A_e, -kappa H_eo], [-kappa H_oe, A_o]] (even block first), the
@@ -206,39 +223,36 @@ def Mhat(U, psi_o, kappa, mu, bc_t, dims):
     A_o^-1 (A_o - kappa^2 H_oe A_e^-1 H_eo) s_o = A_o^-1 (eta_o + kappa H_oe A_e^-1 eta_e).
     """
     me, mo = parity_mask(dims, 0), parity_mask(dims, 1)
-    ainv = 1.0 / twist_diag(kappa, mu)
-    u = apply_spin_diag(ainv, me * hop(U, mo * psi_o, bc_t))
-    w = apply_spin_diag(ainv, mo * hop(U, me * u, bc_t))
+    u = apply_A_inv(me * hop(U, mo * psi_o, bc_t), kappa, mu, C)
+    w = apply_A_inv(mo * hop(U, me * u, bc_t), kappa, mu, C)
     return mo * psi_o - kappa ** 2 * w
 
 
-def Mhat_dag(U, psi_o, kappa, mu, bc_t, dims):
+def Mhat_dag(U, psi_o, kappa, mu, bc_t, dims, C=None):
     """Adjoint of ``Mhat``: 1 - kappa^2 H_eo^dag A_e^-dag H_oe^dag A_o^-dag.
 
     (H_eo)^dag = P_o H^dag P_e and (H_oe)^dag = P_e H^dag P_o, with P_p the
-    parity projectors; A^-dag = (1 - 2 i kappa mu gamma_5)^-1.
+    parity projectors; A^-dag = (1 - 2 i kappa mu gamma_5)^-1 = A(-mu)^-1 (also with a
+    hermitian clover term).
     """
     me, mo = parity_mask(dims, 0), parity_mask(dims, 1)
-    ainv_dag = 1.0 / np.conj(twist_diag(kappa, mu))
-    v = apply_spin_diag(ainv_dag, mo * psi_o)
-    u = apply_spin_diag(ainv_dag, me * hop(U, v, bc_t, dagger=True))
+    v = apply_A_inv(mo * psi_o, kappa, -mu, C)
+    u = apply_A_inv(me * hop(U, v, bc_t, dagger=True), kappa, -mu, C)
     w = mo * hop(U, me * u, bc_t, dagger=True)
     return mo * psi_o - kappa ** 2 * w
 
 
-def schur_rhs(U, eta, kappa, mu, bc_t, dims):
+def schur_rhs(U, eta, kappa, mu, bc_t, dims, C=None):
     """bhat = A_o^-1 (eta_o + kappa H_oe A_e^-1 eta_e), an odd-site field."""
     me, mo = parity_mask(dims, 0), parity_mask(dims, 1)
-    ainv = 1.0 / twist_diag(kappa, mu)
-    ue = apply_spin_diag(ainv, me * eta)
-    return apply_spin_diag(ainv, mo * eta + kappa * mo * hop(U, ue, bc_t))
+    ue = apply_A_inv(me * eta, kappa, mu, C)
+    return apply_A_inv(mo * eta + kappa * mo * hop(U, ue, bc_t), kappa, mu, C)
 
 
-def reconstruct_even(U, eta, s_o, kappa, mu, bc_t, dims):
+def reconstruct_even(U, eta, s_o, kappa, mu, bc_t, dims, C=None):
     """Full solution from the odd half: s_e = A_e^-1 (eta_e + kappa H_eo s_o)."""
     me, mo = parity_mask(dims, 0), parity_mask(dims, 1)
-    ainv = 1.0 / twist_diag(kappa, mu)
-    s_e = apply_spin_diag(ainv, me * eta + kappa * me * hop(U, mo * s_o, bc_t))
+    s_e = apply_A_inv(me * eta + kappa * me * hop(U, mo * s_o, bc_t), kappa, mu, C)
     return s_e + mo * s_o
 
 
@@ -260,5 +274,5 @@ def dense(op, dims, batch=64):
     return mat
 
 
-def dense_M(U, kappa, mu, bc_t, dims):
-    return dense(lambda p: apply_M(U, p, kappa, mu, bc_t), dims)
+def dense_M(U, kappa, mu, bc_t, dims, C=None):
+    return dense(lambda p: apply_M(U, p, kappa, mu, bc_t, C), dims)

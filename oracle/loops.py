@@ -50,9 +50,10 @@ def prefactors(kappa, mu):
     return np.array([-2j * mu * (2 * kappa) ** 2, 4 * kappa])
 
 
-def xi_fields(U, s, kappa, bc_t):
-    """The left vectors of the two flavour structures: gamma_5 s and (1 - kappa H) s."""
-    return dirac.spin_mul(dirac.GAMMA5, s), dirac.apply_M0(U, s, kappa, bc_t)
+def xi_fields(U, s, kappa, bc_t, C=None):
+    """The left vectors of the two flavour structures: gamma_5 s and M_0 s = (1 - kappa H) s
+    (M_0 = 1 + C - kappa H with a clover term C)."""
+    return dirac.spin_mul(dirac.GAMMA5, s), dirac.apply_M0(U, s, kappa, bc_t, C)
 
 
 def outer_product(xi, phi):
@@ -84,9 +85,9 @@ def site_loops(U, xi, phi, bc_t, deriv=True):
     return np.stack(ops)
 
 
-def source_site_loops(U, s, kappa, bc_t, deriv=True):
+def source_site_loops(U, s, kappa, bc_t, deriv=True, C=None):
     """Both flavour structures for one solution s: [2, nops, 16, T, Z, Y, X]."""
-    xi_t3, xi_1 = xi_fields(U, s, kappa, bc_t)
+    xi_t3, xi_1 = xi_fields(U, s, kappa, bc_t, C)
     return np.stack([site_loops(U, xi_t3, s, bc_t, deriv),
                      site_loops(U, xi_1, s, bc_t, deriv)])
 
@@ -110,10 +111,10 @@ def project(site_vals, moms, dims):
     return np.einsum("...tzyx,px,py,pz->...tp", site_vals, px, py, pz)
 
 
-def source_loops(U, s, kappa, bc_t, p2max, dims, deriv=True):
+def source_loops(U, s, kappa, bc_t, p2max, dims, deriv=True, C=None):
     """Projected per-source loops, without prefactor: [2, nops, 16, T, Np]."""
     moms = momenta(p2max, dims)
-    return project(source_site_loops(U, s, kappa, bc_t, deriv), moms, dims)
+    return project(source_site_loops(U, s, kappa, bc_t, deriv, C), moms, dims)
 
 
 def apply_prefactors(sums, kappa, mu):
@@ -147,7 +148,7 @@ def tsm_combine(sum_lp, n_lp, sum_hp, sum_lpc, n_hp, kappa, mu):
 # exact loops from dense propagators (tiny lattices)
 # ---------------------------------------------------------------------------
 
-def exact_site_loops(U, kappa, mu, bc_t, dims, deriv=True):
+def exact_site_loops(U, kappa, mu, bc_t, dims, deriv=True, C=None):
     """Exact per-site loops tr[Gamma (D_u^-1 -+ D_d^-1)] from dense inverses.
 
     D^-1 = 2 kappa M^-1 (physical normalisation).  The derivative insertion is
@@ -158,8 +159,8 @@ def exact_site_loops(U, kappa, mu, bc_t, dims, deriv=True):
     """
     X, Y, Z, T = dims
     V = X * Y * Z * T
-    gu = 2 * kappa * np.linalg.inv(dirac.dense_M(U, kappa, mu, bc_t, dims))
-    gd = 2 * kappa * np.linalg.inv(dirac.dense_M(U, kappa, -mu, bc_t, dims))
+    gu = 2 * kappa * np.linalg.inv(dirac.dense_M(U, kappa, mu, bc_t, dims, C))
+    gd = 2 * kappa * np.linalg.inv(dirac.dense_M(U, kappa, -mu, bc_t, dims, C))
     out = []
     coords = [(t, z, y, x) for t in range(T) for z in range(Z) for y in range(Y)
               for x in range(X)]

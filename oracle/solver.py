@@ -27,15 +27,15 @@ def vdot(a, b):
     return np.vdot(a.ravel(), b.ravel())
 
 
-def cgnr_eo(U, eta, kappa, mu, bc_t, dims, tol, maxiter=10000):
+def cgnr_eo(U, eta, kappa, mu, bc_t, dims, tol, maxiter=10000, C=None):
     """Even-odd CGNR solve of M(mu) s = eta.
 
     Returns (s, info) with s the full-lattice solution and info a dict holding
     the iteration count, the final iterated relative residual and whether it
-    converged.
+    converged.  C: optional clover term (oracle/clover.py).
     """
-    bhat = dirac.schur_rhs(U, eta, kappa, mu, bc_t, dims)
-    c = dirac.Mhat_dag(U, bhat, kappa, mu, bc_t, dims)
+    bhat = dirac.schur_rhs(U, eta, kappa, mu, bc_t, dims, C)
+    c = dirac.Mhat_dag(U, bhat, kappa, mu, bc_t, dims, C)
     x = np.zeros_like(c)
     r = c.copy()
     p = r.copy()
@@ -44,11 +44,11 @@ def cgnr_eo(U, eta, kappa, mu, bc_t, dims, tol, maxiter=10000):
     it = 0
     converged = rr <= tol * tol * cc
     while not converged and it < maxiter:
-        t = dirac.Mhat(U, p, kappa, mu, bc_t, dims)
+        t = dirac.Mhat(U, p, kappa, mu, bc_t, dims, C)
         pap = vdot(t, t).real
         alpha = rr / pap
         x = x + alpha * p
-        r = r - alpha * dirac.Mhat_dag(U, t, kappa, mu, bc_t, dims)
+        r = r - alpha * dirac.Mhat_dag(U, t, kappa, mu, bc_t, dims, C)
         rr_new = vdot(r, r).real
         it += 1
         if rr_new <= tol * tol * cc:
@@ -58,20 +58,20 @@ def cgnr_eo(U, eta, kappa, mu, bc_t, dims, tol, maxiter=10000):
         beta = rr_new / rr
         p = r + beta * p
         rr = rr_new
-    s = dirac.reconstruct_even(U, eta, x, kappa, mu, bc_t, dims)
+    s = dirac.reconstruct_even(U, eta, x, kappa, mu, bc_t, dims, C)
     info = dict(iters=it, rel_resid=float(np.sqrt(rr / cc)) if cc > 0 else 0.0,
                 converged=bool(converged))
     return s, info
 
 
-def true_residual(U, eta, s, kappa, mu, bc_t):
+def true_residual(U, eta, s, kappa, mu, bc_t, C=None):
     """||eta - M s|| / ||eta||, evaluated with the full-lattice operator."""
-    r = eta - dirac.apply_M(U, s, kappa, mu, bc_t)
+    r = eta - dirac.apply_M(U, s, kappa, mu, bc_t, C)
     return float(np.linalg.norm(r.ravel()) / np.linalg.norm(eta.ravel()))
 
 
-def dense_solve(U, eta, kappa, mu, bc_t, dims):
+def dense_solve(U, eta, kappa, mu, bc_t, dims, C=None):
     """Exact solve by dense LU (tiny lattices only)."""
-    m = dirac.dense_M(U, kappa, mu, bc_t, dims)
+    m = dirac.dense_M(U, kappa, mu, bc_t, dims, C)
     shape = eta.shape
     return np.linalg.solve(m, eta.reshape(-1)).reshape(shape)
