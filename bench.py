@@ -445,6 +445,8 @@ def main() -> int:
     ap.add_argument("--p2max", type=int, default=-1,
                     help="momentum cut |n|^2 <= p2max of the projection (default: the workload's; "
                          "a cut >= 3 (L/2)^2 keeps every momentum)")
+    ap.add_argument("--csw", type=float, default=0.0,
+                    help="clover coefficient c_sw of the operator (0: the plain twisted-mass operator)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparator", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
@@ -506,6 +508,8 @@ def main() -> int:
     lat = dl.dl_lattice_create(ctx, dims, -1)
     dl.dl_gauge_set(lat, U_dev, 1)
     dl.dl_set_params(lat, kappa, mu)
+    if a.csw:
+        dl.dl_set_clover(lat, a.csw)
     acc = dl.dl_accum_create(lat, dl.DL_OPS_LOCAL | dl.DL_OPS_DERIV | dl.DL_OPS_HPE(a.hpe))
     blocks = {"bf16": list(dl.dl_autotune(ctx, lat, dl.DL_TIER_LP_BF16, n_lp)),
               "fp32": list(dl.dl_autotune(ctx, lat, dl.DL_TIER_HP_FP32, n_hp))}
@@ -664,7 +668,7 @@ def main() -> int:
         "config": {"workload": a.workload, "lattice": "x".join(map(str, dims)), "n_lp": n_lp, "n_hp": n_hp,
                    "n_lpc": n_hp, "lp_storage": "bf16", "hp": "fp32+fp64 reliable updates",
                    "noise": tw["noise"], "p2max": p2, "insertions": 160, "rhs_block": blocks,
-                   "hpe_order": a.hpe, "tdil": a.tdil},
+                   "hpe_order": a.hpe, "tdil": a.tdil, "csw": a.csw},
         "iters_lp_mean": round(float(np.mean(it_lp)), 2), "iters_hp_mean": round(float(np.mean(it_hp)), 2),
         "reliable_updates_hp_mean": round(float(np.mean(ru_hp)), 2),
         "momenta": nmom, "projection_ms": round(loops_ms, 2),

@@ -213,6 +213,26 @@ int dl_gauge_random_host(const int dims[4], uint64_t seed, double eps, double* l
  * Wilson loops, tr Gamma 2 D_W^-1; dl_loops_backward then gives no dF/dmu. */
 int dl_set_params(dl_lattice* lat, double kappa, double mu);
 
+/* Clover term (Section 2.4 expects the package to work for Wilson and clover
+ * fermions; the operator is not printed there).  With c_sw != 0 the operator
+ * is the O(a)-improved one in kappa normalisation:
+ *     M = 1 + C - kappa H + 2 i kappa mu gamma_5,
+ *     C(x) = i kappa c_sw sum_{mu<nu} sigma_{mu nu} Fhat_{mu nu}(x),
+ *     sigma_{mu nu} = (i/2) [gamma_mu, gamma_nu],
+ *     Fhat_{mu nu}(x) = (Q_{mu nu}(x) - Q_{mu nu}(x)^dag) / 8,
+ * Q the four plaquettes of the (mu, nu) plane that start and end at x, each
+ * walked like U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag (links periodic in
+ * every direction; t_bc acts on the fermion hops only).  C is hermitian,
+ * independent of mu and commutes with gamma_5, so the d flavour is M(-mu), the
+ * even-odd solves use the per-site matrices A = 1 + C + 2 i kappa mu gamma_5
+ * (two 6 x 6 blocks) and the loops without tau_3 use xi = (1 + C - kappa H) s.
+ * The site matrices are built on the GPU whenever the gauge field, kappa / mu
+ * or c_sw change (FP64 and FP32 copies, 1.7 kB per site).  c_sw = 0 removes
+ * the term.  Not built for clover lattices: the hopping parameter expansion
+ * (dl_solve_batch refuses DL_OPS_HPE accumulators) and dl_loops_backward.
+ * Errors: DL_EINVAL (NULL lattice, non-finite c_sw), DL_ENOMEM. */
+int dl_set_clover(dl_lattice* lat, double csw);
+
 /* ---- solves and loops -------------------------------------------------- */
 
 /* Solve every source of every job (Section 2, eq. (1)) by even-odd CGNR at

@@ -90,6 +90,7 @@ _SIGS = {
     "dl_lattice_destroy": ([_P], _I),
     "dl_gauge_set": ([_P, _P, _I], _I),
     "dl_set_params": ([_P, _D, _D], _I),
+    "dl_set_clover": ([_P, _D], _I),
     "dl_gauge_random": ([_P, ctypes.c_uint64, _D], _I),
     "dl_gauge_random_host": ([ctypes.POINTER(_I), ctypes.c_uint64, _D, _P], _I),
     "dl_solve_batch": ([_P, ctypes.POINTER(dl_job), _I, ctypes.POINTER(dl_src_stats)], _I),
@@ -190,6 +191,11 @@ def dl_gauge_random_host(dims, seed: int, eps: float, links) -> None:
 
 def dl_set_params(lat, kappa: float, mu: float) -> None:
     _check(lib().dl_set_params(lat, kappa, mu))
+
+
+def dl_set_clover(lat, csw: float) -> None:
+    """Clover coefficient c_sw of the lattice's operator (0: no clover term)."""
+    _check(lib().dl_set_clover(lat, csw))
 
 
 def dl_accum_create(lat, ops: int):

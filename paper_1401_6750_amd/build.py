@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdiscloop.so")
-SOURCES = ["dslash.hip", "blas.hip", "contract.hip", "project.hip", "grad.hip", "gauge.hip", "runtime.hip", "api.hip"]
+SOURCES = ["dslash.hip", "blas.hip", "contract.hip", "project.hip", "grad.hip", "gauge.hip", "clover.hip", "runtime.hip",
+           "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -143,6 +143,12 @@ int dl_lattice_create(dl_ctx* ctx, const int dims[4], int t_bc, dl_lattice** out
   });
 }
 
+static void clover_free(dl_lattice* lat) {
+  if (lat->clv64) (void)hipFree(lat->clv64);
+  if (lat->clv32) (void)hipFree(lat->clv32);
+  lat->clv64 = lat->clv32 = nullptr;
+}
+
 int dl_lattice_destroy(dl_lattice* lat) {
   return guarded([&] {
     if (!lat) return 0;
@@ -150,9 +156,49 @@ int dl_lattice_destroy(dl_lattice* lat) {
     (void)hipStreamSynchronize(lat->ctx->st);
     for (int p = 0; p < 4; ++p)
       if (lat->gauge[p]) (void)hipFree(lat->gauge[p]);
+    clover_free(lat);
     delete lat;
     return 0;
   });
+}
+
+// (Re)build the clover site matrices of a lattice with a clover term once its
+// gauge field and kappa, mu are set (they depend on all three).
+static void clover_rebuild(dl_lattice* lat) {
+  if (lat->csw == 0.0 || !lat->gauge_set || !lat->params_set) return;
+  dl_ctx* c = lat->ctx;
+  HIPCHECK(hipSetDevice(c->device));
+  const long long vp = pad_half(lat->Vh);
+  if (!lat->clv64) {
+    const size_t b64 = (size_t)CLV_KINDS * 2 * clover_rows(P64) * vp * 16;
+    const size_t b32 = (size_t)CLV_KINDS * 2 * clover_rows(P32) * vp * 16;
+    if (hipMalloc(&lat->clv64, b64) != hipSuccess || hipMalloc(&lat->clv32, b32) != hipSuccess) {
+      (void)hipGetLastError();
+      clover_free(lat);
+      throw Error(DL_ENOMEM, "clover term: allocation of the site matrices failed");
+    }
+  }
+  // sigma_{mu nu} = (i/2) [gamma_mu, gamma_nu], gamma_mu = Gamma_{2^mu}
+  std::complex<double> G[16][4][4];
+  gamma_basis(G);
+  double sg[6][4][4][2];
+  int plane = 0;
+  for (int m = 0; m < 4; ++m)
+    for (int n = m + 1; n < 4; ++n, ++plane)
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+          std::complex<double> v = 0.0;
+          for (int k = 0; k < 4; ++k) v += G[1 << m][a][k] * G[1 << n][k][b] - G[1 << n][a][k] * G[1 << m][k][b];
+          v *= std::complex<double>(0.0, 0.5);
+          sg[plane][a][b][0] = v.real();
+          sg[plane][a][b][1] = v.imag();
+        }
+  stream_enter(c);
+  launch_clover_build(lat->gauge[P64], lat->dims, vp, lat->kappa, lat->mu, lat->csw, sg, lat->clv64, lat->clv32,
+                      c->st);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipStreamSynchronize(c->st));
+  stream_exit(c);
 }
 
 static void gauge_upload(dl_lattice* lat, const double* links, int on_device) {
@@ -172,6 +218,7 @@ static void gauge_upload(dl_lattice* lat, const double* links, int on_device) {
   HIPCHECK(hipStreamSynchronize(c->st));
   stream_exit(c);
   lat->gauge_set = true;
+  clover_rebuild(lat);
 }
 
 int dl_gauge_set(dl_lattice* lat, const double* links, int on_device) {
@@ -211,6 +258,23 @@ int dl_set_params(dl_lattice* lat, double kappa, double mu) {
     lat->kappa = kappa;
     lat->mu = mu;
     lat->params_set = true;
+    clover_rebuild(lat);
+    return 0;
+  });
+}
+
+int dl_set_clover(dl_lattice* lat, double csw) {
+  return guarded([&] {
+    require(lat != nullptr, "dl_set_clover: NULL lattice");
+    require(std::isfinite(csw), "dl_set_clover: c_sw must be finite");
+    lat->csw = csw;
+    if (csw == 0.0) {
+      (void)hipSetDevice(lat->ctx->device);
+      (void)hipStreamSynchronize(lat->ctx->st);
+      clover_free(lat);
+    } else {
+      clover_rebuild(lat);
+    }
     return 0;
   });
 }
@@ -336,6 +400,8 @@ int dl_solve_batch(dl_ctx* ctx, const dl_job* jobs, int njobs, dl_src_stats* sta
       if (q.accum) {
         require(q.accum->lat == q.lat, "dl_solve_batch: accumulator of another lattice");
         require(q.accum_set >= 0 && q.accum_set < 3, "dl_solve_batch: bad accum_set");
+        require(q.lat->csw == 0.0 || DL_OPS_HPE_ORDER(q.accum->ops) == 0,
+                "dl_solve_batch: the hopping parameter expansion is not built for clover lattices");
       }
       first_stat[j + 1] = first_stat[j] + (long long)q.nsrc * std::max(q.tdil, 1);
     }
@@ -757,6 +823,7 @@ int dl_loops_backward(dl_ctx* ctx, const dl_job* job, int p2max, const double* g
                       double* grad_mu) {
   return guarded([&] {
     require(ctx && job && grad_loops, "dl_loops_backward: NULL argument");
+    require(!job->lat || job->lat->csw == 0.0, "dl_loops_backward: not built for clover lattices");
     require(!job->accum || DL_OPS_HPE_ORDER(job->accum->ops) == 0,
             "dl_loops_backward: loops with the hopping parameter expansion are not differentiated");
     require(job->tdil <= 1, "dl_loops_backward: time-diluted sources are not differentiated");

@@ -451,6 +451,8 @@ struct SlotDesc {
   long long fo;            // site offset of rhs 0 in every batch field
   double bc;               // time-boundary factor
   const void* gauge[4];    // gauge field per precision
+  const void* clv64;       // clover site matrices (FP64 class), or null: no clover term
+  const void* clv32;       // clover site matrices (FP32 class, all other tiers), or null
   double* acc;             // accumulator set of this slot (contractions), or null
   uint64_t seed;           // noise
   long long src0;          // source index of rhs 0 (time dilution: of the job's first vector)
@@ -484,7 +486,82 @@ __host__ __device__ inline int src_vector(const SlotDesc& sd, int r) {
 //   res = e (.) H(d (.) in) + f (.) y,  out = g (.) res   (per-spin complex factors)
 struct Coef {
   double d[4][2], e[4][2], f[4][2], g[4][2];
+  // clover lattices: site matrix (CloverKind) that each factor applies before
+  // its per-spin constant, -1 for none: d, e, f, g
+  int m[4];
 };
+
+// ---------------------------------------------------------------------------
+// clover term: per-site matrices that replace the per-spin twist factors.
+// The clover term commutes with gamma_5, so every matrix here is two 6 x 6
+// blocks per site (spins 0, 1 and spins 2, 3; component 3 spin + colour).
+// Storage per lattice and class (FP64 for the FP64 tier, FP32 otherwise):
+// kind k, parity p, entry e = 36 b + 6 i + j of block b, row i, column j in
+// chunk rows Vp sites long: FP64 72 rows of one complex, FP32 36 rows of two
+// complex (entries e, e + 1), row (k * 2 + p) * rows + chunk.
+// ---------------------------------------------------------------------------
+enum CloverKind : int {
+  CLV_AINV = 0,    // A(mu)^-1, A = 1 + C + 2 i kappa mu gamma_5
+  CLV_AINV_M = 1,  // A(-mu)^-1
+  CLV_A = 2,       // A(mu)
+  CLV_A_M = 3,     // A(-mu)
+  CLV_AC = 4,      // 1 + C
+  CLV_KINDS = 5
+};
+inline int clover_rows(int prec) { return prec == P64 ? 72 : 36; }
+
+// out[k] = sum_j M(x)[k][j] in[j] for the G right-hand sides of a wave that are
+// active; M is kind `kind` of parity `par` at site s (FP64 and FP32 storage).
+template <int G>
+__device__ inline void site_matvec(const void* m, int kind, int par, long vp, long s, const cx<double> (&in)[G][12],
+                                   cx<double> (&out)[G][12], const bool (&act)[G]) {
+  const double2* p = (const double2*)m + (long)(kind * 2 + par) * 72 * vp + s;
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      cx<double> row[6];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        const double2 w = p[(long)(36 * b + 6 * i + j) * vp];
+        row[j] = mk<double>(w.x, w.y);
+      }
+#pragma unroll
+      for (int r = 0; r < G; ++r) {
+        if (!act[r]) continue;
+        cx<double> a = mk<double>(0.0, 0.0);
+#pragma unroll
+        for (int j = 0; j < 6; ++j) a = a + row[j] * in[r][6 * b + j];
+        out[r][6 * b + i] = a;
+      }
+    }
+}
+
+template <int G>
+__device__ inline void site_matvec(const void* m, int kind, int par, long vp, long s, const cx<float> (&in)[G][12],
+                                   cx<float> (&out)[G][12], const bool (&act)[G]) {
+  const float4* p = (const float4*)m + (long)(kind * 2 + par) * 36 * vp + s;
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      cx<float> row[6];
+#pragma unroll
+      for (int j = 0; j < 6; j += 2) {
+        const float4 w = p[(long)((36 * b + 6 * i + j) / 2) * vp];
+        row[j] = mk<float>(w.x, w.y);
+        row[j + 1] = mk<float>(w.z, w.w);
+      }
+#pragma unroll
+      for (int r = 0; r < G; ++r) {
+        if (!act[r]) continue;
+        cx<float> a = mk<float>(0.f, 0.f);
+#pragma unroll
+        for (int j = 0; j < 6; ++j) a = a + row[j] * in[r][6 * b + j];
+        out[r][6 * b + i] = a;
+      }
+    }
+}
 
 // Hardware dispatches workgroup b to XCD (b mod 8); renumber so that each XCD
 // runs one contiguous range of logical workgroups (neighbouring tiles and the

@@ -345,6 +345,21 @@ __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
     load_coef(cf.f, f);
     load_coef(cf.g, g);
     const int p_out = a.p_out;
+    // clover slots: the site matrices of e, f, g (kind per factor, -1 none);
+    // d was applied to the input beforehand (launch_site_factor)
+    const void* clv = nullptr;
+    int me = -1, mf = -1, mg = -1;
+    if constexpr ((F & F_CLV) != 0) {
+      clv = Traits<S>::prec == P64 ? sd.clv64 : sd.clv32;
+      if (clv) {
+        me = cf.m[1];
+        mf = cf.m[2];
+        mg = cf.m[3];
+        if (cf.m[0] >= 0)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) d[k] = mk<R>((R)1, (R)0);
+      }
+    }
     const Coords c = eo_coords(sd, s, p_out);
     // neighbour even-odd indices from the lexicographic index: a step along
     // y, z or t moves lex by an even stride, one along x flips the parity bit
@@ -410,6 +425,16 @@ __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
     hop<S, 3, true, HD, false>(gauge, vp, p_out, s, ntp, sp, inb, nr, act, d, acc);
     hop<S, 3, false, HD, false>(gauge, vp, q, ntm, ntm, sm, inb, nr, act, d, acc);
     }
+    if constexpr ((F & F_CLV) != 0) {
+      if (me >= 0) {
+        cx<R> t[G][12];
+        site_matvec<G>(clv, me, p_out, vp, s, acc, t, act);
+#pragma unroll
+        for (int i = 0; i < G; ++i)
+#pragma unroll
+          for (int k = 0; k < 12; ++k) acc[i][k] = t[i][k];
+      }
+    }
 #pragma unroll
     for (int i = 0; i < G; ++i) {
       if (!act[i]) continue;
@@ -419,6 +444,17 @@ __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
       cx<R> yv[12];
       if (F & F_Y) {
         load_spinor<S>(field_at<S>(a.y, off[i]), vp, s, yv);
+        if constexpr ((F & F_CLV) != 0) {
+          if (mf >= 0) {
+            cx<R> yi[1][12], yo[1][12];
+            const bool one[1] = {true};
+#pragma unroll
+            for (int k = 0; k < 12; ++k) yi[0][k] = yv[k];
+            site_matvec<1>(clv, mf, p_out, vp, s, yi, yo, one);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) yv[k] = yo[0][k];
+          }
+        }
 #pragma unroll
         for (int k = 0; k < 12; ++k) res[k] = res[k] + f[k / 3] * yv[k];
       }
@@ -434,6 +470,17 @@ __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
       } else {
         if (F & F_POST) {
           if (F & F_NORM) nrm[i] = norm2(res);  // norm before the post factor
+          if constexpr ((F & F_CLV) != 0) {
+            if (mg >= 0) {
+              cx<R> ri[1][12], ro[1][12];
+              const bool one[1] = {true};
+#pragma unroll
+              for (int k = 0; k < 12; ++k) ri[0][k] = res[k];
+              site_matvec<1>(clv, mg, p_out, vp, s, ri, ro, one);
+#pragma unroll
+              for (int k = 0; k < 12; ++k) res[k] = ro[0][k];
+            }
+          }
 #pragma unroll
           for (int k = 0; k < 12; ++k) res[k] = g[k / 3] * res[k];
         } else if (F & F_NORM) {
@@ -482,6 +529,18 @@ static void launch_dslash_t(int flags, const DslashArgs& a, hipStream_t st) {
       hipLaunchKernelGGL((k_dslash<S, F_Y | F_XR | F_NORM>), grid, block, 0, st, a); break;
     case F_Y | F_POST: hipLaunchKernelGGL((k_dslash<S, F_Y | F_POST>), grid, block, 0, st, a); break;
     case F_Y | F_DUAL: hipLaunchKernelGGL((k_dslash<S, F_Y | F_DUAL>), grid, block, 0, st, a); break;
+    case F_CLV: hipLaunchKernelGGL((k_dslash<S, F_CLV>), grid, block, 0, st, a); break;
+    case F_CLV | F_D: hipLaunchKernelGGL((k_dslash<S, F_CLV | F_D>), grid, block, 0, st, a); break;
+    case F_CLV | F_Y: hipLaunchKernelGGL((k_dslash<S, F_CLV | F_Y>), grid, block, 0, st, a); break;
+    case F_CLV | F_D | F_Y: hipLaunchKernelGGL((k_dslash<S, F_CLV | F_D | F_Y>), grid, block, 0, st, a); break;
+    case F_CLV | F_Y | F_NORM:
+      hipLaunchKernelGGL((k_dslash<S, F_CLV | F_Y | F_NORM>), grid, block, 0, st, a); break;
+    case F_CLV | F_Y | F_NORM | F_POST:
+      hipLaunchKernelGGL((k_dslash<S, F_CLV | F_Y | F_NORM | F_POST>), grid, block, 0, st, a); break;
+    case F_CLV | F_Y | F_NORM | F_OUT2:
+      hipLaunchKernelGGL((k_dslash<S, F_CLV | F_Y | F_NORM | F_OUT2>), grid, block, 0, st, a); break;
+    case F_CLV | F_Y | F_XR | F_NORM:
+      hipLaunchKernelGGL((k_dslash<S, F_CLV | F_Y | F_XR | F_NORM>), grid, block, 0, st, a); break;
     default: throw std::runtime_error("unsupported dslash flag combination");
   }
 }

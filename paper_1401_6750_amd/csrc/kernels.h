@@ -14,6 +14,8 @@ enum DslashFlags : int {
   F_OUT2 = 16,  // also store the result to a second field
   F_POST = 32,  // store g (.) result (the norm is taken before the factor)
   F_DUAL = 64,  // with F_Y: also out2 = g (.) H(d (.) in) + f (.) y from the same hop
+  F_CLV = 256,  // clover slots: e, f, g apply their site matrix (Coef.m) before the per-spin
+                // factor; d is 1 there (launch_site_factor applied it beforehand)
 };
 
 struct DslashArgs {
@@ -35,6 +37,16 @@ struct DslashArgs {
 };
 
 void launch_dslash(int prec, int flags, const DslashArgs& a, hipStream_t st);
+
+// Clover site matrices (CloverKind) of a lattice from its packed FP64 links:
+// o64 / o32 hold CLV_KINDS x 2 parities x clover_rows chunk rows of vp sites.
+// sigma: sigma_{mu nu} of the planes 01 02 03 12 13 23 (complex 4 x 4).
+void launch_clover_build(const void* g64, const int dims[4], long long vp, double kappa, double mu, double csw,
+                         const double (&sigma)[6][4][4][2], void* o64, void* o32, hipStream_t st);
+// out = d (.) (M_d in) on slots with a clover term and a d matrix (Coef.m[0]),
+// out = in elsewhere; fields of parity par, UK_RHS units, gated rhs skipped.
+void launch_site_factor(int prec, const SlotDesc* slots, int nslots, int total_units, const Coef* coef, int par,
+                        const void* in, void* out, const int* gate, hipStream_t st);
 
 // finalize kinds
 enum FinKind : int { FK_INIT = 0, FK_ALPHA = 1, FK_BETA = 2, FK_STORE = 3 };

@@ -60,6 +60,11 @@ struct dl_lattice {
   bool gauge_set = false;
   double kappa = 0, mu = 0;
   bool params_set = false;
+  // clover term (c_sw = 0: none); its site matrices follow the gauge field,
+  // kappa and mu (rebuilt by dl_gauge_set, dl_set_params and dl_set_clover)
+  double csw = 0;
+  void* clv64 = nullptr;
+  void* clv32 = nullptr;
 };
 
 struct dl_accum {

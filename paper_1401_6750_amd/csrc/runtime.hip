@@ -164,6 +164,49 @@ static void put(double (&dst)[4][2], const Cd (&v)[4]) {
   }
 }
 
+// Coefficients with a clover term: the twist factors A, A^-1 become site
+// matrices (CloverKind) applied before a per-spin constant (gamma_5 signs and
+// scalars, which commute with them); see csrc/clover.hip for the operator.
+static Coef make_coef_clover(int kind, double kappa) {
+  const double g5[4] = {1, 1, -1, -1};
+  const double k2 = kappa * kappa;
+  Cd d[4], e[4], f[4], g[4];
+  int m[4] = {-1, -1, -1, -1};
+  for (int s = 0; s < 4; ++s) {
+    d[s] = 1.0;
+    e[s] = 1.0;
+    f[s] = 0.0;
+    g[s] = 1.0;
+    const double G5 = g5[s];
+    switch (kind) {
+      case CK_MHAT2P: e[s] = -k2; m[1] = CLV_AINV; f[s] = 1.0; g[s] = G5; m[3] = CLV_AINV_M; break;
+      case CK_MDAG1P: m[1] = CLV_AINV_M; break;
+      case CK_MDAG2P: e[s] = -k2 * G5; f[s] = G5; m[2] = CLV_A_M; break;
+      case CK_MHAT1: m[1] = CLV_AINV; break;
+      case CK_MHAT2: e[s] = -k2; m[1] = CLV_AINV; f[s] = 1.0; break;
+      case CK_MDAG1: d[s] = G5; m[0] = CLV_AINV_M; m[1] = CLV_AINV_M; break;
+      case CK_MDAG2: e[s] = -k2 * G5; f[s] = 1.0; break;
+      case CK_PREP: m[0] = CLV_AINV; e[s] = kappa; m[1] = CLV_AINV; f[s] = 1.0; m[2] = CLV_AINV; break;
+      case CK_RECON: e[s] = kappa; m[1] = CLV_AINV; f[s] = 1.0; m[2] = CLV_AINV; break;
+      case CK_XI: e[s] = -kappa; f[s] = 1.0; m[2] = CLV_AC; break;
+      case CK_MFULL: e[s] = -kappa; f[s] = 1.0; m[2] = CLV_A; break;
+      case CK_MDAGFULL: d[s] = G5; e[s] = -kappa * G5; f[s] = 1.0; m[2] = CLV_A_M; break;
+      case CK_HOP: break;
+      default:
+        // the expansion's kernels, the gradient insertions and the fused
+        // reconstruction of s_e and xi_e are not built for clover lattices
+        break;
+    }
+  }
+  Coef c;
+  put(c.d, d);
+  put(c.e, e);
+  put(c.f, f);
+  put(c.g, g);
+  for (int k = 0; k < 4; ++k) c.m[k] = m[k];
+  return c;
+}
+
 static Coef make_coef(int kind, double kappa, double mu) {
   const double g5[4] = {1, 1, -1, -1};
   Cd one[4], zero[4], A[4], Am[4], Ai[4], Ami[4], G5[4];
@@ -210,6 +253,7 @@ static Coef make_coef(int kind, double kappa, double mu) {
   put(c.e, e);
   put(c.f, f);
   put(c.g, g);
+  for (int k = 0; k < 4; ++k) c.m[k] = -1;
   return c;
 }
 
@@ -226,6 +270,8 @@ struct Batch {
   long long sites = 0;
   DevBuf partial, partial2, scal;
   CgScalars cs{};
+  bool has_clover = false;     // some slot's lattice has a clover term
+  DevBuf fd_tmp;               // clover batches: input of a hop after its site factor d
   int* h_int = nullptr;        // pinned: active / status / iters mirrors
   double* h_dbl = nullptr;     // pinned: rr / cc / out mirrors
 
@@ -249,6 +295,9 @@ struct Batch {
       d.fo = fo;
       d.bc = (double)L->bc;
       for (int p = 0; p < 4; ++p) d.gauge[p] = L->gauge[p];
+      d.clv64 = L->csw != 0.0 ? L->clv64 : nullptr;
+      d.clv32 = L->csw != 0.0 ? L->clv32 : nullptr;
+      if (d.clv64) has_clover = true;
       d.acc = sp.acc;
       d.acc_ops = 0;
       if (jobs && sp.acc) d.acc_ops = (*jobs)[sp.job].accum->ops;
@@ -288,7 +337,7 @@ struct Batch {
     for (int k = 0; k < CK_COUNT; ++k)
       for (int i = 0; i < nslots; ++i) {
         const dl_lattice* L = plan[i].lat;
-        coefs[(size_t)k * nslots + i] = make_coef(k, L->kappa, L->mu);
+        coefs[(size_t)k * nslots + i] = L->csw != 0.0 ? make_coef_clover(k, L->kappa) : make_coef(k, L->kappa, L->mu);
       }
     dcoef = DevBuf(ctx, sizeof(Coef) * coefs.size());
     HIPCHECK(hipMemcpyAsync(dcoef.p, coefs.data(), sizeof(Coef) * coefs.size(), hipMemcpyHostToDevice, ctx->st));
@@ -303,6 +352,7 @@ struct Batch {
     int* ib = (int*)(db + nd);
     cs.active = ib; cs.iters = ib + nrhs; cs.maxiter = ib + 2 * nrhs; cs.status = ib + 3 * nrhs;
     cs.upd = ib + 4 * nrhs;
+    if (has_clover) fd_tmp = DevBuf(ctx, std::max<size_t>(field_bytes(P64), 16));
     HIPCHECK(hipHostMalloc((void**)&h_int, sizeof(int) * 4 * std::max(nrhs, 1), hipHostMallocDefault));
     HIPCHECK(hipHostMalloc((void**)&h_dbl, sizeof(double) * 6 * std::max(nrhs, 1), hipHostMallocDefault));
   }
@@ -324,7 +374,22 @@ struct Batch {
     a.total_units = g == 1 ? u_rhs : (g == 2 ? u_grp2 : u_grp4);
     a.in = in; a.out = out; a.y = y; a.partial = part ? part : partial.as<double>(); a.active = gate;
     a.x = x; a.r = r; a.p = pp; a.alpha = cs.alpha; a.out2 = out2;
+    if (has_clover) {
+      if (flags & F_DUAL) throw Error(DL_EINVAL, "fused reconstruction is not built for clover lattices");
+      if ((flags & F_D) && clover_d(ck)) {
+        // d is a site matrix on clover slots: apply it to the input first
+        launch_site_factor(p, slots(), nslots, u_rhs, coef(ck), 1 - p_out, in, fd_tmp.p, gate, ctx->st);
+        a.in = fd_tmp.p;
+      }
+      flags |= F_CLV;
+    }
     launch_dslash(p, flags, a, ctx->st);
+  }
+  // some clover slot's coefficient d of kind ck is a site matrix
+  bool clover_d(int ck) const {
+    for (int i = 0; i < nslots; ++i)
+      if (hs[i].clv64 && coefs[(size_t)ck * nslots + i].m[0] >= 0) return true;
+    return false;
   }
   void finalize(int kind, const double* part = nullptr) {
     launch_finalize(kind, slots(), nslots, nrhs, part ? part : partial.as<double>(), cs, ctx->st);
@@ -905,8 +970,9 @@ void run_batch(dl_ctx* ctx, int tier, const std::vector<SlotPlan>& plan, const s
       xe_f = xi64_e.p;
       xo_f = xi64_o.p;
     }
-  } else if (any_acc) {
-    // s_e and xi_e = s_e - kappa H_eo s_o share the hop H_eo s_o
+  } else if (any_acc && !b.has_clover) {
+    // s_e and xi_e = s_e - kappa H_eo s_o share the hop H_eo s_o (with a clover
+    // term xi_e = (1 + C) s_e - kappa H_eo s_o: two launches below)
     b.dslash(P, F_Y | F_DUAL, CK_RECON_XI, 0, x.p, r.p, eta_e.p, nullptr, nullptr, nullptr, nullptr, p.p);
     xi_e_done = true;
   } else {
