@@ -328,6 +328,11 @@ int dl_loops_backward(dl_ctx* ctx, const dl_job* job, int p2max, const double* g
  *   "inflight_rhs"  max right-hand sides solved together per launch (>= 1)
  *   "inflight_mb"   device memory budget of one batch of solves, MiB
  *   "use_graph"     1: replay CG iterations from a HIP graph; 0: plain launches
+ *   "block_hop"     1: 16-bit hops through the LDS-staged kernel (a block of
+ *                   whole x-rows and its y / z halo staged in LDS per time
+ *                   slice) on lattices whose shape allows it; 0 (default): the
+ *                   tile kernel.  Changes the norms' summation order, so the
+ *                   low-precision iterates, not their accuracy.
  *   "profile"       1: time every hopping-kernel launch of the CG (the
  *                   u_e = A^-1 H_eo p_o step) with HIP events on the context
  *                   stream and count its compulsory bytes; 0: off

@@ -403,7 +403,7 @@ __device__ inline void load_link<f16s>(const void* g, long vh, int mu, int par, 
 // Unit kinds: UK_RHS (one tile x one rhs), UK_SITE (one tile x one parity),
 // UK_DERIV (one tile x parity x direction), UK_GRP2 / UK_GRP4 (one tile x 2 / 4
 // rhs: the hopping kernel runs that many right-hand sides per wavefront).
-enum UnitKind : int { UK_RHS = 0, UK_SITE = 1, UK_DERIV = 2, UK_GRP2 = 3, UK_GRP4 = 4, UK_COUNT = 5 };
+enum UnitKind : int { UK_RHS = 0, UK_SITE = 1, UK_DERIV = 2, UK_GRP2 = 3, UK_GRP4 = 4, UK_BLK = 5, UK_COUNT = 6 };
 // Right-hand sides per wavefront in the hopping kernel, per storage type
 // (1, 2 or 4).  Sharing a wave shares the link loads, the link-word
 // preparation and the index arithmetic, at the cost of registers.  Measured
@@ -446,6 +446,8 @@ struct SlotDesc {
   int Xh, Vh, ntile, nrhs;
   int Vp;                  // pad_half(Vh): row stride of fields, links, accumulators
   int tblk;                // time slices per block of the hopping kernel's tile order
+  int bby, bbz, bseg;      // LDS-staged hop (16-bit storage, option): x-rows per block in y and z,
+                           // time slices per workgroup (1); bby = 0: the slot uses the tile kernel
   int ubeg[UK_COUNT];      // first unit of this slot per UnitKind
   int rhs_begin;           // global index of this slot's rhs 0
   long long fo;            // site offset of rhs 0 in every batch field

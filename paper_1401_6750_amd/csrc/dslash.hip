@@ -304,6 +304,93 @@ __device__ inline void load_coef(const double (&c)[4][2], cx<R> (&out)[4]) {
   for (int k = 0; k < 4; ++k) out[k] = mk<R>((R)c[k][0], (R)c[k][1]);
 }
 
+// Site-local epilogue of a hop (see the file header): res = e (.) acc + f (.) y,
+// then the CG residual update, the post factor, the norm partial and the stores.
+template <class S, int F, int G>
+__device__ __forceinline__ void dslash_epilogue(const DslashArgs& a, const SlotDesc& sd, const Coef& cf,
+                                                const void* clv, int me, int mf, int mg, int p_out, long vp, int s,
+                                                const long long (&off)[G], int r0, const bool (&act)[G],
+                                                const cx<typename Traits<S>::R> (&e)[4],
+                                                const cx<typename Traits<S>::R> (&f)[4],
+                                                const cx<typename Traits<S>::R> (&g)[4],
+                                                cx<typename Traits<S>::R> (&acc)[G][12], double (&nrm)[G]) {
+  using R = typename Traits<S>::R;
+  (void)cf;
+  if constexpr ((F & F_CLV) != 0) {
+    if (me >= 0) {
+      cx<R> t[G][12];
+      site_matvec<G>(clv, me, p_out, vp, s, acc, t, act);
+#pragma unroll
+      for (int i = 0; i < G; ++i)
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[i][k] = t[i][k];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < G; ++i) {
+    if (!act[i]) continue;
+    cx<R> res[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) res[k] = e[k / 3] * acc[i][k];
+    cx<R> yv[12];
+    if (F & F_Y) {
+      load_spinor<S>(field_at<S>(a.y, off[i]), vp, s, yv);
+      if constexpr ((F & F_CLV) != 0) {
+        if (mf >= 0) {
+          cx<R> yi[1][12], yo[1][12];
+          const bool one[1] = {true};
+#pragma unroll
+          for (int k = 0; k < 12; ++k) yi[0][k] = yv[k];
+          site_matvec<1>(clv, mf, p_out, vp, s, yi, yo, one);
+#pragma unroll
+          for (int k = 0; k < 12; ++k) yv[k] = yo[0][k];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 12; ++k) res[k] = res[k] + f[k / 3] * yv[k];
+    }
+    if (F & F_XR) {
+      const R al = (R)a.alpha[sd.rhs_begin + r0 + i];
+      cx<R> rv[12];
+      load_spinor<S>(field_at<S>(a.r, off[i]), vp, s, rv);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) rv[k] = rv[k] - al * res[k];
+      quantize<S>(rv);                       // the norm is that of the stored residual
+      store_spinor<S>(field_at<S>(a.r, off[i]), vp, s, rv);
+      if (F & F_NORM) nrm[i] = norm2(rv);
+    } else {
+      if (F & F_POST) {
+        if (F & F_NORM) nrm[i] = norm2(res);  // norm before the post factor
+        if constexpr ((F & F_CLV) != 0) {
+          if (mg >= 0) {
+            cx<R> ri[1][12], ro[1][12];
+            const bool one[1] = {true};
+#pragma unroll
+            for (int k = 0; k < 12; ++k) ri[0][k] = res[k];
+            site_matvec<1>(clv, mg, p_out, vp, s, ri, ro, one);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) res[k] = ro[0][k];
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < 12; ++k) res[k] = g[k / 3] * res[k];
+      } else if (F & F_NORM) {
+        quantize<S>(res);                     // the norm of the stored values
+        nrm[i] = norm2(res);
+      }
+      store_spinor<S>(field_at<S>(a.out, off[i]), vp, s, res);
+      if (F & F_OUT2) store_spinor<S>(field_at<S>(a.out2, off[i]), vp, s, res);
+      if (F & F_DUAL) {
+        // second epilogue on the same hop: g (.) H + f (.) y  (y is in yv)
+        cx<R> res2[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) res2[k] = g[k / 3] * acc[i][k] + f[k / 3] * yv[k];
+        store_spinor<S>(field_at<S>(a.out2, off[i]), vp, s, res2);
+      }
+    }
+  }
+}
+
 template <class S, int F>
 __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
   using R = typename Traits<S>::R;
@@ -425,79 +512,7 @@ __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
     hop<S, 3, true, HD, false>(gauge, vp, p_out, s, ntp, sp, inb, nr, act, d, acc);
     hop<S, 3, false, HD, false>(gauge, vp, q, ntm, ntm, sm, inb, nr, act, d, acc);
     }
-    if constexpr ((F & F_CLV) != 0) {
-      if (me >= 0) {
-        cx<R> t[G][12];
-        site_matvec<G>(clv, me, p_out, vp, s, acc, t, act);
-#pragma unroll
-        for (int i = 0; i < G; ++i)
-#pragma unroll
-          for (int k = 0; k < 12; ++k) acc[i][k] = t[i][k];
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < G; ++i) {
-      if (!act[i]) continue;
-      cx<R> res[12];
-#pragma unroll
-      for (int k = 0; k < 12; ++k) res[k] = e[k / 3] * acc[i][k];
-      cx<R> yv[12];
-      if (F & F_Y) {
-        load_spinor<S>(field_at<S>(a.y, off[i]), vp, s, yv);
-        if constexpr ((F & F_CLV) != 0) {
-          if (mf >= 0) {
-            cx<R> yi[1][12], yo[1][12];
-            const bool one[1] = {true};
-#pragma unroll
-            for (int k = 0; k < 12; ++k) yi[0][k] = yv[k];
-            site_matvec<1>(clv, mf, p_out, vp, s, yi, yo, one);
-#pragma unroll
-            for (int k = 0; k < 12; ++k) yv[k] = yo[0][k];
-          }
-        }
-#pragma unroll
-        for (int k = 0; k < 12; ++k) res[k] = res[k] + f[k / 3] * yv[k];
-      }
-      if (F & F_XR) {
-        const R al = (R)a.alpha[sd.rhs_begin + r0 + i];
-        cx<R> rv[12];
-        load_spinor<S>(field_at<S>(a.r, off[i]), vp, s, rv);
-#pragma unroll
-        for (int k = 0; k < 12; ++k) rv[k] = rv[k] - al * res[k];
-        quantize<S>(rv);                       // the norm is that of the stored residual
-        store_spinor<S>(field_at<S>(a.r, off[i]), vp, s, rv);
-        if (F & F_NORM) nrm[i] = norm2(rv);
-      } else {
-        if (F & F_POST) {
-          if (F & F_NORM) nrm[i] = norm2(res);  // norm before the post factor
-          if constexpr ((F & F_CLV) != 0) {
-            if (mg >= 0) {
-              cx<R> ri[1][12], ro[1][12];
-              const bool one[1] = {true};
-#pragma unroll
-              for (int k = 0; k < 12; ++k) ri[0][k] = res[k];
-              site_matvec<1>(clv, mg, p_out, vp, s, ri, ro, one);
-#pragma unroll
-              for (int k = 0; k < 12; ++k) res[k] = ro[0][k];
-            }
-          }
-#pragma unroll
-          for (int k = 0; k < 12; ++k) res[k] = g[k / 3] * res[k];
-        } else if (F & F_NORM) {
-          quantize<S>(res);                     // the norm of the stored values
-          nrm[i] = norm2(res);
-        }
-        store_spinor<S>(field_at<S>(a.out, off[i]), vp, s, res);
-        if (F & F_OUT2) store_spinor<S>(field_at<S>(a.out2, off[i]), vp, s, res);
-        if (F & F_DUAL) {
-          // second epilogue on the same hop: g (.) H + f (.) y  (y is in yv)
-          cx<R> res2[12];
-#pragma unroll
-          for (int k = 0; k < 12; ++k) res2[k] = g[k / 3] * acc[i][k] + f[k / 3] * yv[k];
-          store_spinor<S>(field_at<S>(a.out2, off[i]), vp, s, res2);
-        }
-      }
-    }
+    dslash_epilogue<S, F, G>(a, sd, cf, clv, me, mf, mg, p_out, vp, s, off, r0, act, e, f, g, acc, nrm);
   }
   if (F & F_NORM) {
 #pragma unroll
@@ -506,6 +521,291 @@ __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
       const double t = wave_sum(nrm[i]);
       if (lane == 0 && act[i]) a.partial[sd.ubeg[UK_RHS] + tile * sd.nrhs + r0 + i] = t;
     }
+  }
+}
+
+// ---- LDS-staged 16-bit hop (option "block_hop"; the tile kernel is faster) ---
+// One workgroup is one unit: a block of bby x bbz whole x-rows (y, z) at one
+// time slice of one slot, two right-hand sides.  The input-parity rows of the
+// block and its y / z halo rows are staged in LDS (whole rows, eight in flight
+// per wave), so six of the eight neighbour spinors of an output site come from
+// LDS; the t neighbours and the links are read from global memory as in
+// k_dslash.  Thread tid < bby * bbz * Xh owns output site k = tid mod Xh of row
+// tid / Xh; the per-site arithmetic is that of k_dslash (same hop order).  The
+// norm partial of a (block, slice) goes to partial slot blk * T + t (a fixed
+// summation order that depends on the lattice shape only).
+// LDS word (rhs i, row R, chunk c, site k): ((i * nrows + R) * 3 + c) * Xh + k;
+// rows: centre row r -> r (nc = bby * bbz, r = ry + bby rz), halo h -> nc + h:
+// h < bbz y = y0 - 1, < 2 bbz y = y0 + bby (z = z0 + h mod bbz), < 2 bbz + bby
+// z = z0 - 1, else z = z0 + bbz (y = y0 + h - 2 bbz (- bby)).
+template <int MU, bool NINE, int G>
+__device__ inline void hop_fill16(HopWords<G>& h, const void* gauge, long vp, int link_par, int link_site,
+                                  const uint4* const (&src)[G], int cstride, uint32_t nine) {
+  const uint4* lp = (const uint4*)gauge + (long)(MU * 2 + link_par) * 3 * vp + link_site;
+  const uint4 l0 = lp[0], l1 = lp[vp];
+  h.e[0] = l0.x; h.e[1] = l0.y; h.e[2] = l0.z; h.e[3] = l0.w;
+  h.e[4] = l1.x; h.e[5] = l1.y; h.e[6] = l1.z; h.e[7] = l1.w;
+  if constexpr (NINE) h.e[8] = nine;
+  else h.e[8] = lp[2 * vp].x;
+#pragma unroll
+  for (int i = 0; i < G; ++i) {
+    const uint4 q0 = src[i][0], q1 = src[i][cstride], q2 = src[i][2 * cstride];
+    h.v[i][0] = q0.x; h.v[i][1] = q0.y; h.v[i][2] = q0.z; h.v[i][3] = q0.w;
+    h.v[i][4] = q1.x; h.v[i][5] = q1.y; h.v[i][6] = q1.z; h.v[i][7] = q1.w;
+    h.v[i][8] = q2.x; h.v[i][9] = q2.y; h.v[i][10] = q2.z; h.v[i][11] = q2.w;
+  }
+}
+
+template <class S, int F>
+__global__ __launch_bounds__(256) void k_dslash_blk(DslashArgs a) {
+  static_assert(Traits<S>::NC == 3 && (F & (F_D | F_CLV)) == 0, "16-bit storage, no input factor, no clover");
+  using R = typename Traits<S>::R;
+  constexpr int G = 2;
+  extern __shared__ uint4 lds[];
+  __shared__ double red[4][G];
+  const int u = xcd_logical_block();
+  if (u >= a.total_units) return;
+  const int si = find_slot(a.slots, a.nslots, UK_BLK, u);
+  const SlotDesc& sd = a.slots[si];
+  const int ngrp = (sd.nrhs + G - 1) / G;
+  const int ul = u - sd.ubeg[UK_BLK];
+  const int grp = ul % ngrp;
+  const int nseg = sd.T / sd.bseg;
+  const int seg = (ul / ngrp) % nseg;
+  const int blk = ul / ngrp / nseg;
+  const int r0 = grp * G;
+  const int nr = min(G, sd.nrhs - r0);
+  bool act[G];
+  bool any = false;
+#pragma unroll
+  for (int i = 0; i < G; ++i) {
+    act[i] = i < nr && (!a.active || a.active[sd.rhs_begin + r0 + i]);
+    any = any || act[i];
+  }
+  if (!any) return;   // uniform over the workgroup
+  const int X = sd.X, Y = sd.Y, Z = sd.Z, T = sd.T, Xh = sd.Xh;
+  const int by = sd.bby, bz = sd.bbz;
+  const int nby = Y / by;
+  const int y0 = (blk % nby) * by, z0 = (blk / nby) * bz;
+  const int nc = by * bz, nh = 2 * (by + bz), nrows = nc + nh;
+  const long vp = sd.Vp;
+  const int p_out = a.p_out, q = 1 - p_out;
+  const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, wave = tid >> 6;
+  const bool mine = tid < nc * Xh;
+  const int rr = tid / Xh, k = tid - rr * Xh;
+  const int ry = rr % by, rz = rr / by;
+  const int y = y0 + ry, z = z0 + rz;
+  long long off[G];
+  const uint4* inb[G];
+#pragma unroll
+  for (int i = 0; i < G; ++i) {
+    off[i] = sd.fo + (long long)(r0 + i) * vp;
+    inb[i] = (const uint4*)field_at<S>(a.in, off[i]);
+  }
+  const Coef& cf = a.coef[si];
+  cx<R> e[4], f[4], g[4];
+  load_coef(cf.e, e);
+  load_coef(cf.f, f);
+  load_coef(cf.g, g);
+  const void* gauge = sd.gauge[Traits<S>::prec];
+  const long ntile = sd.ntile;
+  if ((F & F_NORM) && blk == 0 && seg == 0) {
+    // partial slots beyond the blocks' (blk * T + t) range stay zero
+    const long used = (long)(Y / by) * (Z / bz) * T;
+    for (long j = used + tid; j < ntile; j += nthr)
+#pragma unroll
+      for (int i = 0; i < G; ++i)
+        if (act[i]) a.partial[sd.ubeg[UK_RHS] + j * sd.nrhs + r0 + i] = 0.0;
+  }
+  // stage the centre rows of slice tc (with_c; `ring` 0) and the halo rows of
+  // slice th (with_h); rows wrap periodically (the time-boundary factor belongs
+  // to the hop, not to the stored values).  A wave loads whole rows, lane
+  // l < 3 Xh taking chunk l / Xh of site l mod Xh; up to eight rows are loaded
+  // before any of them is written to LDS.
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), nw = nthr >> 6;
+  const int lc = lane / Xh, lk = lane - lc * Xh;
+  const bool lane_ok = lane < 3 * Xh;
+  const long lane_off = (long)lc * vp + lk;
+  const int lane_lds = lc * Xh + lk;
+  auto row_of = [&](int Rw, int tc, int th, int ring, long& eo, int& lrow) {
+    int yy, zz, tt;
+    if (Rw < nc) {
+      yy = y0 + Rw % by;
+      zz = z0 + Rw / by;
+      tt = tc;
+      lrow = ring * nc + Rw;
+    } else {
+      const int h = Rw - nc;
+      tt = th;
+      lrow = nc + h;
+      if (h < bz) { yy = y0 - 1; zz = z0 + h; }
+      else if (h < 2 * bz) { yy = y0 + by; zz = z0 + h - bz; }
+      else if (h < 2 * bz + by) { yy = y0 + h - 2 * bz; zz = z0 - 1; }
+      else { yy = y0 + h - 2 * bz - by; zz = z0 + bz; }
+    }
+    yy = (yy + Y) % Y;
+    zz = (zz + Z) % Z;
+    tt = (tt + T) % T;
+    eo = (long)X * (yy + (long)Y * (zz + (long)Z * tt)) / 2;
+  };
+  auto stage = [&](int ring, int tc, bool with_c, int th, bool with_h) {
+    const int rb = with_c ? 0 : nc, re = with_h ? nc + nh : nc;
+    const int nrw = re - rb, total = G * nrw;
+    auto fetch = [&](int it, uint4& v, int& dst) {
+      dst = -1;
+      if (it >= total) return;
+      const int i = it >= nrw ? 1 : 0;   // G = 2; selects, not a dynamic array index
+      if (!((i ? act[1] : act[0]) && lane_ok)) return;
+      long eo;
+      int lrow;
+      row_of(rb + it - i * nrw, tc, th, ring, eo, lrow);
+      v = (i ? inb[1] : inb[0])[lane_off + eo];
+      dst = (i * nrows + lrow) * 3 * Xh + lane_lds;
+    };
+    for (int base = wv; base < total; base += 8 * nw) {
+      uint4 v0, v1, v2, v3, v4, v5, v6, v7;
+      int d0, d1, d2, d3, d4, d5, d6, d7;
+      fetch(base, v0, d0);
+      fetch(base + nw, v1, d1);
+      fetch(base + 2 * nw, v2, d2);
+      fetch(base + 3 * nw, v3, d3);
+      fetch(base + 4 * nw, v4, d4);
+      fetch(base + 5 * nw, v5, d5);
+      fetch(base + 6 * nw, v6, d6);
+      fetch(base + 7 * nw, v7, d7);
+      if (d0 >= 0) lds[d0] = v0;
+      if (d1 >= 0) lds[d1] = v1;
+      if (d2 >= 0) lds[d2] = v2;
+      if (d3 >= 0) lds[d3] = v3;
+      if (d4 >= 0) lds[d4] = v4;
+      if (d5 >= 0) lds[d5] = v5;
+      if (d6 >= 0) lds[d6] = v6;
+      if (d7 >= 0) lds[d7] = v7;
+    }
+  };
+  // one time slice per workgroup: seg is the slice
+  const int t = seg;
+  stage(0, t, true, t, true);
+  __syncthreads();
+  const int XY = X * Y, XYZ = XY * Z, VV = XYZ * T;
+  {
+    double nrm[G];
+#pragma unroll
+    for (int i = 0; i < G; ++i) nrm[i] = 0.0;
+    if (mine) {
+      const int x = 2 * k + ((p_out + y + z + t) & 1);
+      const int lex = x + X * y + XY * z + XYZ * t;
+      const int s = lex >> 1;
+      const int nxm = (x == 0 ? lex + (X - 1) : lex - 1) >> 1;
+      const int nym = (y == 0 ? lex + (XY - X) : lex - X) >> 1;
+      const int nzm = (z == 0 ? lex + (XYZ - XY) : lex - XY) >> 1;
+      const int ntp = (t + 1 == T ? lex - (VV - XYZ) : lex + XYZ) >> 1;
+      const int ntm = (t == 0 ? lex + (VV - XYZ) : lex - XYZ) >> 1;
+      const float sp = (t + 1 == T) ? (float)sd.bc : 1.0f;
+      const float sm = (t == 0) ? (float)sd.bc : 1.0f;
+      auto row = [&](int i, int lrow, int kk) { return lds + ((i * nrows + lrow) * 3) * Xh + kk; };
+      const int kxp = ((x + 1) % X) >> 1, kxm = ((x + X - 1) % X) >> 1;
+      const int cr = rr;
+      const int ryp = ry + 1 < by ? cr + 1 : nc + bz + rz;
+      const int rym = ry > 0 ? cr - 1 : nc + rz;
+      const int rzp = rz + 1 < bz ? cr + by : nc + 2 * bz + by + ry;
+      const int rzm = rz > 0 ? cr - by : nc + 2 * bz + ry;
+      const uint4* pxp[G]; const uint4* pxm[G]; const uint4* pyp[G]; const uint4* pym[G];
+      const uint4* pzp[G]; const uint4* pzm[G];
+      const void* ld[G];
+#pragma unroll
+      for (int i = 0; i < G; ++i) {
+        pxp[i] = row(i, cr, kxp); pxm[i] = row(i, cr, kxm);
+        pyp[i] = row(i, ryp, k); pym[i] = row(i, rym, k);
+        pzp[i] = row(i, rzp, k); pzm[i] = row(i, rzm, k);
+      }
+      // t neighbours from global memory; inactive members read the first active one's field
+      {
+        const void* fa = nullptr;
+#pragma unroll
+        for (int i = G - 1; i >= 0; --i)
+          if (act[i]) fa = (const void*)inb[i];
+#pragma unroll
+        for (int i = 0; i < G; ++i) ld[i] = act[i] ? (const void*)inb[i] : fa;
+      }
+      const uint4 nf = ((const uint4*)gauge)[(long)(LINK_ROW_NINTH + p_out) * vp + s];
+      const uint4 nbw = ((const uint4*)gauge)[(long)(LINK_ROW_NINTH_BWD + p_out) * vp + s];
+      cx<float> acc[G][12];
+      HopWords<G> h0, h1;
+      // the hops in the tile kernel's order (x, y, z, t; per-site results are the same bits)
+      hop_fill16<0, true>(h0, gauge, vp, p_out, s, pxp, Xh, nf.x);
+      hop_fill16<0, true>(h1, gauge, vp, q, nxm, pxm, Xh, nbw.x);
+      hop_compute16<S, 0, true, true>(h0, 1.0f, act, acc);
+      hop_fill16<1, true>(h0, gauge, vp, p_out, s, pyp, Xh, nf.y);
+      hop_compute16<S, 0, false, false>(h1, 1.0f, act, acc);
+      hop_fill16<1, true>(h1, gauge, vp, q, nym, pym, Xh, nbw.y);
+      hop_compute16<S, 1, true, false>(h0, 1.0f, act, acc);
+      hop_fill16<2, true>(h0, gauge, vp, p_out, s, pzp, Xh, nf.z);
+      hop_compute16<S, 1, false, false>(h1, 1.0f, act, acc);
+      hop_fill16<2, true>(h1, gauge, vp, q, nzm, pzm, Xh, nbw.z);
+      hop_compute16<S, 2, true, false>(h0, 1.0f, act, acc);
+      hop_load16<3, true>(h0, gauge, vp, p_out, s, ntp, ld, nf.w);
+      hop_compute16<S, 2, false, false>(h1, 1.0f, act, acc);
+      hop_load16<3, true>(h1, gauge, vp, q, ntm, ntm, ld, nbw.w);
+      hop_compute16<S, 3, true, false>(h0, sp, act, acc);
+      hop_compute16<S, 3, false, false>(h1, sm, act, acc);
+      dslash_epilogue<S, F, G>(a, sd, cf, nullptr, -1, -1, -1, p_out, vp, s, off, r0, act, e, f, g, acc, nrm);
+    }
+    if (F & F_NORM) {
+#pragma unroll
+      for (int i = 0; i < G; ++i) {
+        const double w = wave_sum(nrm[i]);
+        if (lane == 0) red[wave][i] = w;
+      }
+      __syncthreads();
+      if (tid == 0) {
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+          if (!act[i]) continue;
+          double v = 0.0;
+          for (int w = 0; w < (nthr >> 6); ++w) v += red[w][i];
+          a.partial[sd.ubeg[UK_RHS] + ((long)blk * T + t) * sd.nrhs + r0 + i] = v;
+        }
+      }
+    }
+  }
+}
+
+template <class S>
+static void launch_dslash_blk_t(int flags, const DslashArgs& a, int threads, size_t lds, hipStream_t st) {
+  if (a.total_units == 0) return;
+  dim3 grid(a.total_units), block(threads);
+  switch (flags) {
+    case 0: hipLaunchKernelGGL((k_dslash_blk<S, 0>), grid, block, lds, st, a); break;
+    case F_Y: hipLaunchKernelGGL((k_dslash_blk<S, F_Y>), grid, block, lds, st, a); break;
+    case F_Y | F_NORM: hipLaunchKernelGGL((k_dslash_blk<S, F_Y | F_NORM>), grid, block, lds, st, a); break;
+    case F_Y | F_NORM | F_POST:
+      hipLaunchKernelGGL((k_dslash_blk<S, F_Y | F_NORM | F_POST>), grid, block, lds, st, a); break;
+    case F_Y | F_NORM | F_OUT2:
+      hipLaunchKernelGGL((k_dslash_blk<S, F_Y | F_NORM | F_OUT2>), grid, block, lds, st, a); break;
+    case F_Y | F_XR | F_NORM:
+      hipLaunchKernelGGL((k_dslash_blk<S, F_Y | F_XR | F_NORM>), grid, block, lds, st, a); break;
+    case F_Y | F_POST: hipLaunchKernelGGL((k_dslash_blk<S, F_Y | F_POST>), grid, block, lds, st, a); break;
+    case F_Y | F_DUAL: hipLaunchKernelGGL((k_dslash_blk<S, F_Y | F_DUAL>), grid, block, lds, st, a); break;
+    default: throw std::runtime_error("unsupported flag combination for the block hop");
+  }
+}
+
+bool dslash_blk_supports(int prec, int flags) {
+  if (prec != PB16 && prec != PH16) return false;
+  switch (flags) {
+    case 0: case F_Y: case F_Y | F_NORM: case F_Y | F_NORM | F_POST: case F_Y | F_NORM | F_OUT2:
+    case F_Y | F_XR | F_NORM: case F_Y | F_POST: case F_Y | F_DUAL:
+      return true;
+  }
+  return false;
+}
+
+void launch_dslash_blk(int prec, int flags, const DslashArgs& a, int threads, size_t lds, hipStream_t st) {
+  switch (prec) {
+    case PB16: launch_dslash_blk_t<bf16s>(flags, a, threads, lds, st); break;
+    case PH16: launch_dslash_blk_t<f16s>(flags, a, threads, lds, st); break;
+    default: throw std::runtime_error("block hop: 16-bit storage only");
   }
 }
 

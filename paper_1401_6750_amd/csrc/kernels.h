@@ -37,6 +37,11 @@ struct DslashArgs {
 };
 
 void launch_dslash(int prec, int flags, const DslashArgs& a, hipStream_t st);
+// The LDS-staged hop (16-bit storage; slots with bby > 0, UK_BLK units, one
+// workgroup of `threads` threads and `lds` bytes of dynamic LDS per unit) and
+// the flag combinations it is built for.
+void launch_dslash_blk(int prec, int flags, const DslashArgs& a, int threads, size_t lds, hipStream_t st);
+bool dslash_blk_supports(int prec, int flags);
 
 // Clover site matrices (CloverKind) of a lattice from its packed FP64 links:
 // o64 / o32 hold CLV_KINDS x 2 parities x clover_rows chunk rows of vp sites.

@@ -46,6 +46,7 @@ struct dl_ctx {
   int inflight_rhs = 1024;
   double inflight_mb = 32768.0;
   bool use_graph = true;
+  bool block_hop = false;        // LDS-staged hop for 16-bit storage where the lattice shape allows
   bool profile = false;
   // hopping-kernel profile per storage precision: launches, ms, bytes, rhs
   double prof[4][4] = {};

@@ -257,13 +257,47 @@ static Coef make_coef(int kind, double kappa, double mu) {
   return c;
 }
 
+// Block shape of the LDS-staged hop for a lattice (16-bit storage, no clover
+// term, option "block_hop"): bby | Y, bbz | Z with 64 <= bby * bbz * X/2 <= 256
+// threads and at most 48 KiB of LDS (three or more workgroups per CU), the
+// fewest halo rows per centre row, then the most threads; one time slice per
+// workgroup.  It depends on the lattice shape only, so a source's iterates do
+// not depend on what else shares its batch.  false: no such shape.
+static bool blk_shape(const int dims[4], int& by, int& bz, int& seg, size_t& lds) {
+  const int X = dims[0], Y = dims[1], Z = dims[2], Xh = X / 2;
+  double best = 1e30;
+  int best_n = 0;
+  by = bz = 0;
+  for (int b = 1; b <= Y; ++b) {
+    if (Y % b) continue;
+    for (int c = 1; c <= Z; ++c) {
+      if (Z % c) continue;
+      const int n = b * c * Xh;
+      if (n < 64 || n > 256) continue;
+      const size_t bytes = (size_t)2 * (b * c + 2 * (b + c)) * 3 * Xh * 16;
+      if (bytes > 48 * 1024) continue;
+      const double ratio = 2.0 * (b + c) / (b * c);
+      if (ratio < best - 1e-12 || (ratio < best + 1e-12 && n > best_n)) {
+        best = ratio;
+        best_n = n;
+        by = b;
+        bz = c;
+        lds = bytes;
+      }
+    }
+  }
+  if (!by) return false;
+  seg = 1;   // one time slice per workgroup
+  return true;
+}
+
 // ---------------------------------------------------------------------------
 // batch state
 // ---------------------------------------------------------------------------
 struct Batch {
   dl_ctx* ctx;
   int prec;
-  std::vector<SlotDesc> hs;
+  std::vector<SlotDesc> hs, hs_tile;
   std::vector<Coef> coefs;     // host copies stay alive while their uploads are in flight
   DevBuf dslots, dcoef;
   int nslots = 0, nrhs = 0, u_rhs = 0, u_site = 0, u_deriv = 0, u_grp2 = 0, u_grp4 = 0;
@@ -271,6 +305,12 @@ struct Batch {
   DevBuf partial, partial2, scal;
   CgScalars cs{};
   bool has_clover = false;     // some slot's lattice has a clover term
+  // LDS-staged hop (16-bit storage): its units, workgroup size and LDS bytes;
+  // the tile kernel's slots (UK_GRP2 units of the other slots only) when the
+  // batch mixes shapes
+  int u_blk = 0, blk_threads = 0, u_grp2_tile = 0;
+  size_t blk_lds = 0;
+  DevBuf dslots_tile;
   DevBuf fd_tmp;               // clover batches: input of a hop after its site factor d
   int* h_int = nullptr;        // pinned: active / status / iters mirrors
   double* h_dbl = nullptr;     // pinned: rr / cc / out mirrors
@@ -327,12 +367,45 @@ struct Batch {
       fo += (long long)d.nrhs * d.Vp;
       hs.push_back(d);
     }
+    // LDS-staged hop for 16-bit storage, per lattice shape
+    if ((prec == PB16 || prec == PH16) && ctx->block_hop) {
+      int ub = 0;
+      for (size_t i = 0; i < hs.size(); ++i) {
+        SlotDesc& d = hs[i];
+        d.ubeg[UK_BLK] = ub;
+        int by = 0, bz = 0, seg = 0;
+        size_t lds = 0;
+        const int dims[4] = {d.X, d.Y, d.Z, d.T};
+        if (!d.clv64 && blk_shape(dims, by, bz, seg, lds)) {
+          d.bby = by;
+          d.bbz = bz;
+          d.bseg = seg;
+          ub += (d.Y / by) * (d.Z / bz) * (d.T / seg) * ((d.nrhs + 1) / 2);
+          blk_threads = std::max(blk_threads, (by * bz * d.Xh + 63) / 64 * 64);
+          blk_lds = std::max(blk_lds, lds);
+        }
+      }
+      u_blk = ub;
+    }
     nslots = (int)hs.size();
     nrhs = rb;
     u_rhs = ur; u_site = us; u_deriv = ud; u_grp2 = ug2; u_grp4 = ug4;
     sites = fo;
     dslots = DevBuf(ctx, sizeof(SlotDesc) * nslots);
     HIPCHECK(hipMemcpyAsync(dslots.p, hs.data(), sizeof(SlotDesc) * nslots, hipMemcpyHostToDevice, ctx->st));
+    if (u_blk > 0) {
+      // the tile kernel covers the slots without a block shape only
+      hs_tile = hs;
+      int ut = 0;
+      for (SlotDesc& d : hs_tile) {
+        d.ubeg[UK_GRP2] = ut;
+        if (!d.bby) ut += d.ntile * ((d.nrhs + 1) / 2);
+      }
+      u_grp2_tile = ut;
+      dslots_tile = DevBuf(ctx, sizeof(SlotDesc) * nslots);
+      HIPCHECK(hipMemcpyAsync(dslots_tile.p, hs_tile.data(), sizeof(SlotDesc) * nslots, hipMemcpyHostToDevice,
+                              ctx->st));
+    }
     coefs.resize((size_t)CK_COUNT * nslots);
     for (int k = 0; k < CK_COUNT; ++k)
       for (int i = 0; i < nslots; ++i) {
@@ -382,6 +455,17 @@ struct Batch {
         a.in = fd_tmp.p;
       }
       flags |= F_CLV;
+    }
+    if (u_blk > 0 && p == prec && dslash_blk_supports(p, flags)) {
+      DslashArgs ab = a;
+      ab.total_units = u_blk;
+      launch_dslash_blk(p, flags, ab, blk_threads, blk_lds, ctx->st);
+      if (u_grp2_tile > 0) {
+        a.slots = dslots_tile.as<SlotDesc>();
+        a.total_units = u_grp2_tile;
+        launch_dslash(p, flags, a, ctx->st);
+      }
+      return;
     }
     launch_dslash(p, flags, a, ctx->st);
   }
@@ -1221,8 +1305,13 @@ TuneChoice autotune_block(dl_ctx* ctx, dl_lattice* lat, int prec, int nsrc_hint)
   while (total < nsrc_hint && total < 128) total *= 2;
   static const char* pname[4] = {"fp64", "fp32", "bf16", "fp16"};
   char key[96], tkey[100];
-  snprintf(key, sizeof(key), "%dx%dx%dx%d:%s:%d", lat->dims[0], lat->dims[1], lat->dims[2], lat->dims[3],
-           pname[prec], total);
+  // the LDS-staged hop has its own best slot shape
+  int bb_y, bb_z, bb_s;
+  size_t bb_l;
+  const bool blk = (prec == PB16 || prec == PH16) && ctx->block_hop && lat->csw == 0.0 &&
+                   blk_shape(lat->dims, bb_y, bb_z, bb_s, bb_l);
+  snprintf(key, sizeof(key), "%dx%dx%dx%d:%s:%d%s", lat->dims[0], lat->dims[1], lat->dims[2], lat->dims[3],
+           pname[prec], total, blk ? ":blk" : "");
   snprintf(tkey, sizeof(tkey), "%s:t", key);
   auto it = ctx->tune.find(key);
   auto jt = ctx->tune.find(tkey);

@@ -457,7 +457,9 @@ def test_tile_order_and_tuned_shape_do_not_change_results(tmp_path):
     ref = None
     for blk, tb in [(4, 1), (4, 2), (4, 4), (2, 8), (8, 3), (16, 1)]:
         cache = tmp_path / f"tune_{blk}_{tb}.json"
-        cache.write_text(json.dumps({"8x8x8x8:bf16:16": blk, "8x8x8x8:bf16:16:t": tb}))
+        # the LDS-staged hop keys its own shapes (":blk"); write both
+        cache.write_text(json.dumps({"8x8x8x8:bf16:16": blk, "8x8x8x8:bf16:16:t": tb,
+                                     "8x8x8x8:bf16:16:blk": blk, "8x8x8x8:bf16:16:blk:t": tb}))
         old = os.environ.get("DL_TUNE_CACHE")
         os.environ["DL_TUNE_CACHE"] = str(cache)
         try:
@@ -493,6 +495,48 @@ def test_graph_replay_equals_plain_launches(ctx):
         assert np.array_equal(a, runs[0][0]) and ia == runs[0][1]
         assert np.array_equal(b, runs[0][2]) and ib == runs[0][3]
     lat.close()
+
+
+@pytest.mark.parametrize("dims", [(6, 6, 6, 6), (8, 8, 8, 8), (12, 4, 8, 6), (16, 8, 4, 4)])
+def test_block_hop_option(dims):
+    """The LDS-staged 16-bit hop (option block_hop) does the tile kernel's per-site arithmetic:
+    every 16-bit operator gives the same bits.  Its low-precision solves sum the norms per
+    (block, slice), so their iterates are its own: the LP map is the same for every slot size,
+    and the solutions meet the tier's accuracy against the oracle."""
+    t = torch()
+    lat_args = (dims, 27, 0.3, 0.16, 0.02)
+    psi = synth.random_spinor(dims, 8, nrhs=3)
+    outs = {}
+    for opt in (0, 1):
+        c = dl.dl_create(0, t.cuda.current_stream().cuda_stream)
+        dl.dl_set_option(c, "block_hop", opt)
+        lat = make_lattice(c, *lat_args)
+        for tier in (dl.DL_TIER_LP_BF16, dl.DL_TIER_LP_FP16):
+            for op in OPS:
+                out = zeros_dev(psi.shape)
+                dl.dl_apply_op(lat.h, op, tier, dev(psi), out, 3)
+                t.cuda.synchronize()
+                outs[(opt, tier, op)] = host(out)
+        if opt == 1:
+            sols = []
+            for blk in (6, 4, 1):
+                sol = zeros_dev((6,) + lat.field_shape)
+                rc, st = dl.dl_solve_batch(c, dl.make_job(lat.h, noise=dl.DL_NOISE_Z4, tier=dl.DL_TIER_LP_BF16,
+                                                          seed=17, nsrc=6, tol=1e-2, maxiter=500, rhs_block=blk,
+                                                          sol_out=sol))
+                assert rc == dl.DL_OK
+                sols.append((host(sol), [x.iters for x in st]))
+            assert all(np.array_equal(sols[0][0], x[0]) and sols[0][1] == x[1] for x in sols[1:])
+            for r in range(6):
+                eta = noise.source(dims, 17, r, noise.Z4)
+                tr = solver.true_residual(lat.U, eta, sols[0][0][r], lat.kappa, lat.mu, lat.bc)
+                log(f"block hop {dims} LP source {r}: iters {sols[0][1][r]} true residual {tr:.3e}")
+                assert tr < 5e-2
+        lat.close()
+        dl.dl_destroy(c)
+    for (opt, tier, op), v in outs.items():
+        if opt == 1:
+            assert np.array_equal(v, outs[(0, tier, op)]), (tier, op)
 
 
 def test_hp_graph_equals_host_driven(ctx):
