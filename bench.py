@@ -447,8 +447,8 @@ def main() -> int:
                          "a cut >= 3 (L/2)^2 keeps every momentum)")
     ap.add_argument("--csw", type=float, default=0.0,
                     help="clover coefficient c_sw of the operator (0: the plain twisted-mass operator)")
-    ap.add_argument("--tile-hop", action="store_true",
-                    help="use the tile hopping kernel for 16-bit storage instead of the LDS-staged one")
+    ap.add_argument("--block-hop", action="store_true",
+                    help="16-bit hops through the LDS-staged kernel (option block_hop) instead of the tile kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparator", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
@@ -507,8 +507,8 @@ def main() -> int:
     stream = torch.cuda.current_stream()
     ctx = dl.dl_create(0, stream.cuda_stream)
     dl.dl_set_option(ctx, "inflight_mb", a.inflight_mb)
-    if a.tile_hop:
-        dl.dl_set_option(ctx, "block_hop", 0)
+    if a.block_hop:
+        dl.dl_set_option(ctx, "block_hop", 1)
     lat = dl.dl_lattice_create(ctx, dims, -1)
     dl.dl_gauge_set(lat, U_dev, 1)
     dl.dl_set_params(lat, kappa, mu)

@@ -401,6 +401,9 @@ __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
   const int lane = threadIdx.x & 63;
   const int si = find_slot(a.slots, a.nslots, UK, u);
   const SlotDesc& sd = a.slots[si];
+  // the F_CLV instance runs the slots with a clover term, the plain one the
+  // others, so a slot's arithmetic never depends on what shares its batch
+  if (((F & F_CLV) != 0) != (sd.clv64 != nullptr)) return;
   const int ngrp = (sd.nrhs + G - 1) / G;
   const int ul = u - sd.ubeg[UK];
   const int lt = ul / ngrp;

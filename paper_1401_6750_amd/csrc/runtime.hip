@@ -305,6 +305,7 @@ struct Batch {
   DevBuf partial, partial2, scal;
   CgScalars cs{};
   bool has_clover = false;     // some slot's lattice has a clover term
+  bool has_plain = false;      // some slot's lattice has none
   // LDS-staged hop (16-bit storage): its units, workgroup size and LDS bytes;
   // the tile kernel's slots (UK_GRP2 units of the other slots only) when the
   // batch mixes shapes
@@ -338,6 +339,7 @@ struct Batch {
       d.clv64 = L->csw != 0.0 ? L->clv64 : nullptr;
       d.clv32 = L->csw != 0.0 ? L->clv32 : nullptr;
       if (d.clv64) has_clover = true;
+      else has_plain = true;
       d.acc = sp.acc;
       d.acc_ops = 0;
       if (jobs && sp.acc) d.acc_ops = (*jobs)[sp.job].accum->ops;
@@ -451,11 +453,14 @@ struct Batch {
       if (flags & F_DUAL) throw Error(DL_EINVAL, "fused reconstruction is not built for clover lattices");
       if ((flags & F_D) && clover_d(ck)) {
         // d is a site matrix on clover slots: apply it to the input first
+        // (plain slots get a bit copy and keep their d in the hop)
         launch_site_factor(p, slots(), nslots, u_rhs, coef(ck), 1 - p_out, in, fd_tmp.p, gate, ctx->st);
         a.in = fd_tmp.p;
       }
-      flags |= F_CLV;
+      launch_dslash(p, flags | F_CLV, a, ctx->st);   // the clover slots
+      if (!has_plain) return;
     }
+    // the slots without a clover term
     if (u_blk > 0 && p == prec && dslash_blk_supports(p, flags)) {
       DslashArgs ab = a;
       ab.total_units = u_blk;
