@@ -932,7 +932,13 @@ void run_batch(dl_ctx* ctx, int tier, const std::vector<SlotPlan>& plan, const s
       }
       b.sync();
     }
-    if (ctx->profile || !ctx->use_graph) {
+    // The graph replays the update kernels every step, gated off for the rhs
+    // not flagged; a gated-off launch still dispatches all its waves (about
+    // 60 us for 50 rhs at 24^3 x 48, nine of them per step) while a host round
+    // trip costs about 0.1 ms, so batches above HP_GRAPH_MAX_UNITS tiles x rhs
+    // run the host-driven loop (the same bits either way).
+    constexpr int HP_GRAPH_MAX_UNITS = 65536;
+    if (ctx->profile || !ctx->use_graph || b.u_rhs > HP_GRAPH_MAX_UNITS) {
       // host-driven: the state goes to the host after every step, each step is
       // either the flagged rhs' reliable updates or one CG iteration
       int guard = 0;
