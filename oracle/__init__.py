@@ -28,5 +28,8 @@ noise   SplitMix64 counter generator and Z2 / Z4 volume sources
 solver  even-odd CGNR (same algorithm as the GPU path) and exact dense solves
 loops   one-end-trick contractions, insertions, momentum projection, TSM
 grad    adjoint-solve gradients of the loops with respect to eta and mu
+hpe     hopping parameter expansion of the loops without tau_3
+dilution  time-diluted sources and their single-slice estimators
+clover  the clover term of the operator (Section 2.4's Wilson-and-clover variant)
 """
 from . import dirac, noise, solver, loops  # noqa: F401
