@@ -231,34 +231,51 @@ template <class S> struct Spinor {
   cx<R> c[12];
 };
 
+// Element i (per lane) of an array of 16-byte values that starts at `row`
+// (wave-uniform): a scalar base plus a 32-bit lane offset, the form the vector
+// memory instructions take directly, so no 64-bit address is formed and held
+// per lane.  Every array here has fewer than 2^28 elements per row.
+template <class T>
+__device__ inline const T& at16(const void* row, long long i) {
+  return *(const T*)((const char*)row + ((uint32_t)i << 4));
+}
+template <class T>
+__device__ inline T& at16(void* row, long long i) {
+  return *(T*)((char*)row + ((uint32_t)i << 4));
+}
+// Row k of a family of rows `stride` elements apart.
+__device__ inline const void* row16(const void* base, long long k, long long stride) {
+  return (const char*)base + k * stride * 16;
+}
+__device__ inline void* row16(void* base, long long k, long long stride) {
+  return (char*)base + k * stride * 16;
+}
+
 template <class S>
 __device__ inline void load_spinor(const void* base, long stride, long s, cx<typename Traits<S>::R> (&v)[12]);
 
 template <>
 __device__ inline void load_spinor<double>(const void* base, long stride, long s, cx<double> (&v)[12]) {
-  const double2* p = (const double2*)base;
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
-    double2 w = p[k * stride + s];
+    const double2 w = at16<double2>(row16(base, k, stride), s);
     v[k] = {w.x, w.y};
   }
 }
 template <>
 __device__ inline void load_spinor<float>(const void* base, long stride, long s, cx<float> (&v)[12]) {
-  const float4* p = (const float4*)base;
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
-    float4 w = p[k * stride + s];
+    const float4 w = at16<float4>(row16(base, k, stride), s);
     v[2 * k] = {w.x, w.y};
     v[2 * k + 1] = {w.z, w.w};
   }
 }
 template <class S16>
 __device__ inline void load_spinor16(const void* base, long stride, long s, cx<float> (&v)[12]) {
-  const uint4* p = (const uint4*)base;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    uint4 w = p[k * stride + s];
+    const uint4 w = at16<uint4>(row16(base, k, stride), s);
     v[4 * k + 0] = unpack2<S16>(w.x);
     v[4 * k + 1] = unpack2<S16>(w.y);
     v[4 * k + 2] = unpack2<S16>(w.z);
@@ -279,20 +296,17 @@ __device__ inline void store_spinor(void* base, long stride, long s, const cx<ty
 
 template <>
 __device__ inline void store_spinor<double>(void* base, long stride, long s, const cx<double> (&v)[12]) {
-  double2* p = (double2*)base;
 #pragma unroll
-  for (int k = 0; k < 12; ++k) p[k * stride + s] = make_double2(v[k].re, v[k].im);
+  for (int k = 0; k < 12; ++k) at16<double2>(row16(base, k, stride), s) = make_double2(v[k].re, v[k].im);
 }
 template <>
 __device__ inline void store_spinor<float>(void* base, long stride, long s, const cx<float> (&v)[12]) {
-  float4* p = (float4*)base;
 #pragma unroll
   for (int k = 0; k < 6; ++k)
-    p[k * stride + s] = make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im);
+    at16<float4>(row16(base, k, stride), s) = make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im);
 }
 template <class S16>
 __device__ inline void store_spinor16(void* base, long stride, long s, const cx<float> (&v)[12]) {
-  uint4* p = (uint4*)base;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     uint4 w;
@@ -300,7 +314,7 @@ __device__ inline void store_spinor16(void* base, long stride, long s, const cx<
     w.y = pack2<S16>(v[4 * k + 1]);
     w.z = pack2<S16>(v[4 * k + 2]);
     w.w = pack2<S16>(v[4 * k + 3]);
-    p[k * stride + s] = w;
+    at16<uint4>(row16(base, k, stride), s) = w;
   }
 }
 template <>
@@ -361,29 +375,28 @@ __device__ inline void load_link(const void* g, long vh, int mu, int par, long s
 
 template <>
 __device__ inline void load_link<double>(const void* g, long vh, int mu, int par, long s, cx<double> (&u)[9]) {
-  const double2* p = (const double2*)g + (long)(mu * 2 + par) * 9 * vh + s;
 #pragma unroll
   for (int e = 0; e < 9; ++e) {
-    double2 w = p[e * vh];
+    const double2 w = at16<double2>(row16(g, (mu * 2 + par) * 9 + e, vh), s);
     u[e] = {w.x, w.y};
   }
 }
 template <>
 __device__ inline void load_link<float>(const void* g, long vh, int mu, int par, long s, cx<float> (&u)[9]) {
-  const float4* p = (const float4*)g + (long)(mu * 2 + par) * 5 * vh + s;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    float4 w = p[k * vh];
+    const float4 w = at16<float4>(row16(g, (mu * 2 + par) * 5 + k, vh), s);
     u[2 * k] = {w.x, w.y};
     u[2 * k + 1] = {w.z, w.w};
   }
-  float4 w = p[4 * vh];
+  const float4 w = at16<float4>(row16(g, (mu * 2 + par) * 5 + 4, vh), s);
   u[8] = {w.x, w.y};
 }
 template <class S16>
 __device__ inline void load_link16(const void* g, long vh, int mu, int par, long s, cx<float> (&u)[9]) {
-  const uint4* p = (const uint4*)g + (long)(mu * 2 + par) * 3 * vh + s;
-  const uint4 a = p[0], b = p[vh], c = p[2 * vh];
+  const long long r0 = (mu * 2 + par) * 3;
+  const uint4 a = at16<uint4>(row16(g, r0, vh), s), b = at16<uint4>(row16(g, r0 + 1, vh), s),
+              c = at16<uint4>(row16(g, r0 + 2, vh), s);
   u[0] = unpack2<S16>(a.x); u[1] = unpack2<S16>(a.y); u[2] = unpack2<S16>(a.z); u[3] = unpack2<S16>(a.w);
   u[4] = unpack2<S16>(b.x); u[5] = unpack2<S16>(b.y); u[6] = unpack2<S16>(b.z); u[7] = unpack2<S16>(b.w);
   u[8] = unpack2<S16>(c.x);
@@ -488,6 +501,9 @@ __host__ __device__ inline int src_vector(const SlotDesc& sd, int r) {
 //   res = e (.) H(d (.) in) + f (.) y,  out = g (.) res   (per-spin complex factors)
 struct Coef {
   double d[4][2], e[4][2], f[4][2], g[4][2];
+  // the same factors rounded to FP32 on the host (the FP32 and 16-bit kernels
+  // read these, so the values stay in scalar registers)
+  float d32[4][2], e32[4][2], f32[4][2], g32[4][2];
   // clover lattices: site matrix (CloverKind) that each factor applies before
   // its per-spin constant, -1 for none: d, e, f, g
   int m[4];

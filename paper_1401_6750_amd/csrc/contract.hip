@@ -125,8 +125,16 @@ __device__ inline XsComps xs_comps(const SlotDesc& sd, int t, int nu) {
 // first, as the field it came from was.
 // ---------------------------------------------------------------------------
 __device__ inline void load_words16(const void* f, long vp, int s, uint32_t (&w)[12]) {
-  const uint4* q = (const uint4*)f;
-  const uint4 q0 = q[s], q1 = q[vp + s], q2 = q[2 * vp + s];
+  // wave-uniform row addresses plus one 32-bit lane offset: the loads take the
+  // scalar-base + vector-offset form and no 64-bit address is held per lane
+  // (the empty asm keeps the offset opaque, so the rhs loop cannot turn each
+  // per-lane address into an induction variable of its own)
+  const char* b = (const char*)f;
+  uint32_t o = (uint32_t)s << 4;
+  asm volatile("" : "+v"(o));
+  const uint4 q0 = *(const uint4*)(b + o);
+  const uint4 q1 = *(const uint4*)(b + vp * 16 + o);
+  const uint4 q2 = *(const uint4*)(b + vp * 32 + o);
   w[0] = q0.x; w[1] = q0.y; w[2] = q0.z; w[3] = q0.w;
   w[4] = q1.x; w[5] = q1.y; w[6] = q1.z; w[7] = q1.w;
   w[8] = q2.x; w[9] = q2.y; w[10] = q2.z; w[11] = q2.w;
@@ -207,12 +215,18 @@ __global__ __launch_bounds__(256) void k_contract_local(const SlotDesc* slots, i
 #pragma unroll
   for (int q = 0; q < 48; ++q) a[q] = (A)0;
   int inblk = 0;
+  // the slot's fields the loop needs, read once: the accumulator flushes are
+  // stores the compiler cannot tell apart from the slot table, so fields read
+  // through `sd` inside the loop would be fetched again (and waited for) on
+  // every right-hand side
+  const long long fo = sd.fo;
+  const int nrhs = sd.nrhs, tdil = sd.tdil, tentry = sd.tentry, tclen = sd.tclen;
 #pragma unroll 1
-  for (int r = 0; r < sd.nrhs; ++r) {
-    const long long off = sd.fo + (long long)r * vp;
+  for (int r = 0; r < nrhs; ++r) {
+    const long long off = fo + (long long)r * vp;
     bool xs = true;
     if constexpr (DIL) {
-      const int comp = tdil_comp(sd, r);
+      const int comp = tdil > 1 ? (tentry + r) / tclen : 0;   // tdil_comp
       xs = xc.c0 == comp || xc.c1 == comp;
     }
     any_xs = any_xs || xs;
@@ -302,23 +316,45 @@ __device__ inline void pack_transport(const uint32_t (&cr)[9], const uint32_t (&
   }
 }
 
+// The rows one rhs of the link-centred derivative contraction reads, as
+// 16-bit words: s and xi at the site and at its +nu neighbour, and phi at both
+// (HPE).  Fetching them is separate from the arithmetic so that the loop can
+// load the next rhs while it contracts the current one.
+template <bool HPE>
+struct DerivRows16 {
+  uint32_t sh[12], so[12], xh[12], xo[12];
+  uint32_t fh[HPE ? 12 : 1], fo[HPE ? 12 : 1];
+};
+
+template <class S, bool HPE>
+__device__ inline void deriv_fetch16(DerivRows16<HPE>& d, const void* s_here, const void* s_other,
+                                     const void* x_here, const void* x_other, const void* f_here,
+                                     const void* f_other, long long off, long vp, int s, int sp, bool xs) {
+  load_words16(field_at<S>(s_here, off), vp, s, d.sh);
+  load_words16(field_at<S>(s_other, off), vp, sp, d.so);
+  if (!xs) return;
+  load_words16(field_at<S>(x_here, off), vp, s, d.xh);
+  load_words16(field_at<S>(x_other, off), vp, sp, d.xo);
+  if constexpr (HPE) {
+    load_words16(field_at<S>(f_here, off), vp, s, d.fh);
+    load_words16(field_at<S>(f_other, off), vp, sp, d.fo);
+  }
+}
+
 // One rhs of the link-centred derivative contraction on 16-bit fields (the
 // same sums as the generic body below; constant factors at the flush).
 template <class S, bool HPE>
-__device__ inline void deriv_rhs16(const void* s_here, const void* s_other, const void* x_here, const void* x_other,
-                                   const void* f_here, const void* f_other, long long off, long vp, int s, int sp,
-                                   const uint32_t (&cr)[9], const uint32_t (&ci)[9], bool xs, float (&a)[48]) {
-  uint32_t sw[12], w[12], tp[12], tq[12];
-  load_words16(field_at<S>(s_here, off), vp, s, sw);
-  load_words16(field_at<S>(s_other, off), vp, sp, w);
-  pack_transport<S>(cr, ci, w, tp, tq);                     // T_s
+__device__ inline void deriv_compute16(const DerivRows16<HPE>& d, const uint32_t (&cr)[9], const uint32_t (&ci)[9],
+                                       bool xs, float (&a)[48]) {
+  uint32_t tp[12], tq[12];
+  pack_transport<S>(cr, ci, d.so, tp, tq);                  // T_s
   // s-s block: F_aa = (i/2) Im sum_c conj(s_a) T_a; off the diagonal
   // conj(s_a) T_b - conj(T_a) s_b
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     float v = a[i];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) v = dot2<S>(sw[3 * i + c], tq[3 * i + c], v);
+    for (int c = 0; c < 3; ++c) v = dot2<S>(d.sh[3 * i + c], tq[3 * i + c], v);
     a[i] = v;
   }
 #pragma unroll
@@ -327,22 +363,17 @@ __device__ inline void deriv_rhs16(const void* s_here, const void* s_other, cons
     float re = a[4 + 2 * k6], im = a[5 + 2 * k6];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      re = dot2<S>(sw[3 * ia + c], tp[3 * ib + c], re);
-      re = dot2<S>(neg16(sw[3 * ib + c]), tp[3 * ia + c], re);
-      im = dot2<S>(sw[3 * ia + c], tq[3 * ib + c], im);
-      im = dot2<S>(sw[3 * ib + c], tq[3 * ia + c], im);
+      re = dot2<S>(d.sh[3 * ia + c], tp[3 * ib + c], re);
+      re = dot2<S>(neg16(d.sh[3 * ib + c]), tp[3 * ia + c], re);
+      im = dot2<S>(d.sh[3 * ia + c], tq[3 * ib + c], im);
+      im = dot2<S>(d.sh[3 * ib + c], tq[3 * ia + c], im);
     }
     a[4 + 2 * k6] = re;
     a[5 + 2 * k6] = im;
   }
   if (!xs) return;
   // xi-s block, first half: conj(xi_a) T_phi,b (phi = s unless HPE)
-  uint32_t xw[12];
-  load_words16(field_at<S>(x_here, off), vp, s, xw);
-  if constexpr (HPE) {
-    load_words16(field_at<S>(f_other, off), vp, sp, w);
-    pack_transport<S>(cr, ci, w, tp, tq);                   // T_phi
-  }
+  if constexpr (HPE) pack_transport<S>(cr, ci, d.fo, tp, tq);   // T_phi
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -350,18 +381,19 @@ __device__ inline void deriv_rhs16(const void* s_here, const void* s_other, cons
       float re = a[16 + 2 * (4 * i + j)], im = a[17 + 2 * (4 * i + j)];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        re = dot2<S>(xw[3 * i + c], tp[3 * j + c], re);
-        im = dot2<S>(xw[3 * i + c], tq[3 * j + c], im);
+        re = dot2<S>(d.xh[3 * i + c], tp[3 * j + c], re);
+        im = dot2<S>(d.xh[3 * i + c], tq[3 * j + c], im);
       }
       a[16 + 2 * (4 * i + j)] = re;
       a[17 + 2 * (4 * i + j)] = im;
     }
   // second half: - conj(T_xi,a) phi_b, with (-re, -im) and (-re, im) of T_xi
-  if constexpr (HPE) load_words16(field_at<S>(f_here, off), vp, s, sw);   // phi
-  load_words16(field_at<S>(x_other, off), vp, sp, w);
+  const uint32_t* ph;
+  if constexpr (HPE) ph = d.fh;
+  else ph = d.sh;
   {
     cx<float> t[12];
-    colour_mul16<S>(cr, ci, w, t);                          // T_xi
+    colour_mul16<S>(cr, ci, d.xo, t);                       // T_xi
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
       tp[k] = pack2<S>(mk<float>(-t[k].re, -t[k].im));
@@ -375,8 +407,8 @@ __device__ inline void deriv_rhs16(const void* s_here, const void* s_other, cons
       float re = a[16 + 2 * (4 * i + j)], im = a[17 + 2 * (4 * i + j)];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        re = dot2<S>(tp[3 * i + c], sw[3 * j + c], re);
-        im = dot2<S>(tq[3 * i + c], swap16(sw[3 * j + c]), im);
+        re = dot2<S>(tp[3 * i + c], ph[3 * j + c], re);
+        im = dot2<S>(tq[3 * i + c], swap16(ph[3 * j + c]), im);
       }
       a[16 + 2 * (4 * i + j)] = re;
       a[17 + 2 * (4 * i + j)] = im;
@@ -393,8 +425,15 @@ __device__ inline void deriv_rhs16(const void* s_here, const void* s_other, cons
 // adds F(x - nu) (a momentum phase for spatial nu, the previous time slice
 // for nu = t).  The s-s block (xi -> s) stays anti-Hermitian.  HPE: the
 // xi-s block pairs xi = eta with phi instead of s, one more transport (T_phi).
+// Waves per SIMD the derivative kernel is compiled for: four for the plain
+// 16-bit instance (it fits 128 registers without spills, and its loads are
+// latency-bound), the compiler's choice for the others (they would spill).
 template <class S, bool HPE, bool DIL>
-__global__ __launch_bounds__(256) void k_contract_deriv(const SlotDesc* slots, int nslots, int total_units,
+constexpr int deriv_min_waves() { return Traits<S>::NC == 3 && !HPE && !DIL ? 4 : 1; }
+
+template <class S, bool HPE, bool DIL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(deriv_min_waves<S, HPE, DIL>(), 8))) void
+k_contract_deriv(const SlotDesc* slots, int nslots, int total_units,
                                                         const void* s_e, const void* s_o, const void* xi_e,
                                                         const void* xi_o, const void* phi_e, const void* phi_o) {
   using R = typename Traits<S>::R;
@@ -444,18 +483,42 @@ __global__ __launch_bounds__(256) void k_contract_deriv(const SlotDesc* slots, i
 #pragma unroll
   for (int q = 0; q < 48; ++q) a[q] = (A)0;
   int inblk = 0;
-#pragma unroll 1
-  for (int r = 0; r < sd.nrhs; ++r) {
-    const long long off = sd.fo + (long long)r * vp;
-    bool xs = true;
+  // the slot's fields the loop needs, read once: the accumulator flushes are
+  // stores the compiler cannot tell apart from the slot table, so fields read
+  // through `sd` inside the loop would be fetched again (and waited for) on
+  // every right-hand side
+  const long long fo = sd.fo;
+  const int nrhs = sd.nrhs, tdil = sd.tdil, tentry = sd.tentry, tclen = sd.tclen;
+  auto xs_of = [&](int r) -> bool {   // the xi-s terms of rhs r reach this site
     if constexpr (DIL) {
-      const int comp = tdil_comp(sd, r);
-      xs = xc.c0 == comp || xc.c1 == comp;
+      const int comp = tdil > 1 ? (tentry + r) / tclen : 0;   // tdil_comp
+      return xc.c0 == comp || xc.c1 == comp;
     }
+    return true;
+  };
+  if constexpr (Traits<S>::NC == 3) {
+    // 16-bit fields (fetching the next rhs's rows during the current one's
+    // arithmetic needs a second buffer, 244 VGPRs, and measured slower)
+    DerivRows16<HPE> d;
+#pragma unroll 1
+    for (int r = 0; r < nrhs; ++r) {
+      const bool xs = xs_of(r);
+      deriv_fetch16<S, HPE>(d, s_here, s_other, x_here, x_other, f_here, f_other, fo + (long long)r * vp, vp, s,
+                            sp, xs);
+      any_xs = any_xs || xs;
+      deriv_compute16<S, HPE>(d, cr, ci, xs, a);
+      if (++inblk == AccT<S>::KB) {
+        flush<true, HPE>(acc, V, lane_off, a, any_xs);
+        inblk = 0;
+        any_xs = false;
+      }
+    }
+  } else {
+#pragma unroll 1
+  for (int r = 0; r < nrhs; ++r) {
+    const long long off = fo + (long long)r * vp;
+    const bool xs = xs_of(r);
     any_xs = any_xs || xs;
-    if constexpr (Traits<S>::NC == 3) {
-      deriv_rhs16<S, HPE>(s_here, s_other, x_here, x_other, f_here, f_other, off, vp, s, sp, cr, ci, xs, a);
-    } else {
     cx<R> sv[12], t[12];
     load_spinor<S>(field_at<S>(s_here, off), vp, s, sv);
     transport_fwd<S>(field_at<S>(s_other, off), vp, sp, up, cr, ci, t);   // t = T_s
@@ -511,12 +574,12 @@ __global__ __launch_bounds__(256) void k_contract_deriv(const SlotDesc* slots, i
           a[17 + 2 * (4 * i + j)] -= (A)w.im;
         }
     }
-    }
     if (++inblk == AccT<S>::KB) {
       flush<true, HPE>(acc, V, lane_off, a, any_xs);
       inblk = 0;
       any_xs = false;
     }
+  }
   }
   if (inblk) flush<true, HPE>(acc, V, lane_off, a, any_xs);
 }

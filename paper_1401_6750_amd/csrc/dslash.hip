@@ -1,8 +1,8 @@
 // Even-odd twisted-mass Wilson hopping kernel with fused site-local epilogues.
 //
 // One wavefront handles one unit = 64 consecutive even-odd sites of G right-
-// hand sides of one batch slot (G = rhs_per_wave: two for 16-bit storage,
-// one for FP32 / FP64): the site coordinates, the eight neighbour indices
+// hand sides of one batch slot (G = rhs_per_wave, two for every storage
+// precision by default): the site coordinates, the eight neighbour indices
 // and every gauge link are computed / loaded once and used for all G
 // right-hand sides.  Units of one tile are consecutive for all right-hand-side
 // groups of the slot, tiles are visited in time-blocked order (tile_of), and
@@ -218,16 +218,16 @@ struct HopWords {
 template <int MU, bool NINE, int G>
 __device__ inline void hop_load16(HopWords<G>& h, const void* gauge, long vp, int link_par, int link_site, int nb,
                                   const void* const (&inb)[G], uint32_t nine) {
-  const uint4* lp = (const uint4*)gauge + (long)(MU * 2 + link_par) * 3 * vp + link_site;
-  const uint4 l0 = lp[0], l1 = lp[vp];
+  const long long lr = (MU * 2 + link_par) * 3;
+  const uint4 l0 = at16<uint4>(row16(gauge, lr, vp), link_site), l1 = at16<uint4>(row16(gauge, lr + 1, vp), link_site);
   h.e[0] = l0.x; h.e[1] = l0.y; h.e[2] = l0.z; h.e[3] = l0.w;
   h.e[4] = l1.x; h.e[5] = l1.y; h.e[6] = l1.z; h.e[7] = l1.w;
   if constexpr (NINE) h.e[8] = nine;
-  else h.e[8] = lp[2 * vp].x;
+  else h.e[8] = at16<uint4>(row16(gauge, lr + 2, vp), link_site).x;
 #pragma unroll
   for (int i = 0; i < G; ++i) {
-    const uint4* q = (const uint4*)inb[i];
-    const uint4 q0 = q[nb], q1 = q[vp + nb], q2 = q[2 * vp + nb];
+    const uint4 q0 = at16<uint4>(inb[i], nb), q1 = at16<uint4>(row16(inb[i], 1, vp), nb),
+                q2 = at16<uint4>(row16(inb[i], 2, vp), nb);
     h.v[i][0] = q0.x; h.v[i][1] = q0.y; h.v[i][2] = q0.z; h.v[i][3] = q0.w;
     h.v[i][4] = q1.x; h.v[i][5] = q1.y; h.v[i][6] = q1.z; h.v[i][7] = q1.w;
     h.v[i][8] = q2.x; h.v[i][9] = q2.y; h.v[i][10] = q2.z; h.v[i][11] = q2.w;
@@ -298,10 +298,15 @@ __device__ inline void hop_compute16(const HopWords<G>& h, float sign, const boo
   }
 }
 
-template <class R>
-__device__ inline void load_coef(const double (&c)[4][2], cx<R> (&out)[4]) {
+// A per-spin factor in the compute precision (FP32 kernels take the host's
+// FP32 rounding of the factor, the same value as converting it here).
+__device__ inline void load_coef(const double (&c)[4][2], const float (&)[4][2], cx<double> (&out)[4]) {
 #pragma unroll
-  for (int k = 0; k < 4; ++k) out[k] = mk<R>((R)c[k][0], (R)c[k][1]);
+  for (int k = 0; k < 4; ++k) out[k] = mk<double>(c[k][0], c[k][1]);
+}
+__device__ inline void load_coef(const double (&)[4][2], const float (&c)[4][2], cx<float> (&out)[4]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) out[k] = mk<float>(c[k][0], c[k][1]);
 }
 
 // Site-local epilogue of a hop (see the file header): res = e (.) acc + f (.) y,
@@ -430,10 +435,10 @@ __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
   if (valid) {
     const Coef& cf = a.coef[si];
     cx<R> d[4], e[4], f[4], g[4];
-    load_coef(cf.d, d);
-    load_coef(cf.e, e);
-    load_coef(cf.f, f);
-    load_coef(cf.g, g);
+    load_coef(cf.d, cf.d32, d);
+    load_coef(cf.e, cf.e32, e);
+    load_coef(cf.f, cf.f32, f);
+    load_coef(cf.g, cf.g32, g);
     const int p_out = a.p_out;
     // clover slots: the site matrices of e, f, g (kind per factor, -1 none);
     // d was applied to the input beforehand (launch_site_factor)
@@ -486,8 +491,8 @@ __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
       for (int i = 0; i < G; ++i) ld[i] = act[i] ? inb[i] : fa;
       // ninth entries of the four links leaving this site and of the four
       // reaching it, one load each
-      const uint4 nf = ((const uint4*)gauge)[(long)(LINK_ROW_NINTH + p_out) * vp + s];
-      const uint4 nb = ((const uint4*)gauge)[(long)(LINK_ROW_NINTH_BWD + p_out) * vp + s];
+      const uint4 nf = at16<uint4>(row16(gauge, LINK_ROW_NINTH + p_out, vp), s);
+      const uint4 nb = at16<uint4>(row16(gauge, LINK_ROW_NINTH_BWD + p_out, vp), s);
       HopWords<G> h0, h1;
       hop_load16<0, true>(h0, gauge, vp, p_out, s, nxp, ld, nf.x);
       hop_load16<0, true>(h1, gauge, vp, q, nxm, nxm, ld, nb.x);
@@ -607,9 +612,9 @@ __global__ __launch_bounds__(256) void k_dslash_blk(DslashArgs a) {
   }
   const Coef& cf = a.coef[si];
   cx<R> e[4], f[4], g[4];
-  load_coef(cf.e, e);
-  load_coef(cf.f, f);
-  load_coef(cf.g, g);
+  load_coef(cf.e, cf.e32, e);
+  load_coef(cf.f, cf.f32, f);
+  load_coef(cf.g, cf.g32, g);
   const void* gauge = sd.gauge[Traits<S>::prec];
   const long ntile = sd.ntile;
   if ((F & F_NORM) && blk == 0 && seg == 0) {

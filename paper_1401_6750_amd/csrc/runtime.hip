@@ -157,10 +157,12 @@ enum CoefKind : int {
 
 using Cd = std::complex<double>;
 
-static void put(double (&dst)[4][2], const Cd (&v)[4]) {
+static void put(double (&dst)[4][2], float (&dst32)[4][2], const Cd (&v)[4]) {
   for (int s = 0; s < 4; ++s) {
     dst[s][0] = v[s].real();
     dst[s][1] = v[s].imag();
+    dst32[s][0] = (float)v[s].real();
+    dst32[s][1] = (float)v[s].imag();
   }
 }
 
@@ -199,10 +201,10 @@ static Coef make_coef_clover(int kind, double kappa) {
     }
   }
   Coef c;
-  put(c.d, d);
-  put(c.e, e);
-  put(c.f, f);
-  put(c.g, g);
+  put(c.d, c.d32, d);
+  put(c.e, c.e32, e);
+  put(c.f, c.f32, f);
+  put(c.g, c.g32, g);
   for (int k = 0; k < 4; ++k) c.m[k] = m[k];
   return c;
 }
@@ -249,10 +251,10 @@ static Coef make_coef(int kind, double kappa, double mu) {
     }
   }
   Coef c;
-  put(c.d, d);
-  put(c.e, e);
-  put(c.f, f);
-  put(c.g, g);
+  put(c.d, c.d32, d);
+  put(c.e, c.e32, e);
+  put(c.f, c.f32, f);
+  put(c.g, c.g32, g);
   for (int k = 0; k < 4; ++k) c.m[k] = -1;
   return c;
 }
