@@ -179,7 +179,10 @@ const char* dl_version(void);
 /* ---- lattice and gauge field ------------------------------------------- */
 
 /* Create a lattice {X, Y, Z, T} (all even, >= 2) with time boundary factor
- * t_bc (-1 antiperiodic, +1 periodic).  The library owns its device fields. */
+ * t_bc (-1 antiperiodic, +1 periodic).  The library owns its device fields.
+ * DL_EINVAL for an odd or too small extent, a bad t_bc, or more than 2^28
+ * sites per parity (the kernels' 32-bit row offsets); DL_ENOMEM when the
+ * link arrays do not fit. */
 int dl_lattice_create(dl_ctx* ctx, const int dims[4], int t_bc, dl_lattice** out);
 int dl_lattice_destroy(dl_lattice* lat);
 

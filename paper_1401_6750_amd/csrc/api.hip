@@ -116,7 +116,9 @@ int dl_lattice_create(dl_ctx* ctx, const int dims[4], int t_bc, dl_lattice** out
       require(dims[k] >= 2 && dims[k] % 2 == 0, "dl_lattice_create: every extent must be even and >= 2");
     require(t_bc == 1 || t_bc == -1, "dl_lattice_create: t_bc must be +1 or -1");
     const long long V = (long long)dims[0] * dims[1] * dims[2] * dims[3];
-    require(V / 2 < (1ll << 30), "dl_lattice_create: lattice too large");
+    // kernels address a row of per-parity 16-byte entries with a 32-bit byte
+    // offset: at most 2^28 entries per row
+    require(pad_half(V / 2) < (1ll << 28), "dl_lattice_create: lattice too large (more than 2^28 sites per parity)");
     HIPCHECK(hipSetDevice(ctx->device));
     auto* L = new dl_lattice();
     L->ctx = ctx;

@@ -784,6 +784,11 @@ def test_edge_cases(ctx):
     with pytest.raises(dl.DiscloopError) as e:
         dl.dl_lattice_create(ctx, (4, 4, 3, 4))
     assert e.value.code == dl.DL_EINVAL
+    # more than 2^28 sites per parity (the kernels' 32-bit row offsets): refused
+    # before anything is allocated
+    with pytest.raises(dl.DiscloopError) as e:
+        dl.dl_lattice_create(ctx, (512, 512, 512, 4))
+    assert e.value.code == dl.DL_EINVAL
     with pytest.raises(dl.DiscloopError):
         dl.dl_set_params(lat.h, 0.16, float("nan"))
     with pytest.raises(dl.DiscloopError):
