@@ -437,6 +437,8 @@ def main() -> int:
     ap.add_argument("--workload", default="batched_24x24x24x48", choices=sorted(WORKLOADS))
     ap.add_argument("--rhs-block", type=int, default=0)
     ap.add_argument("--inflight-mb", type=float, default=65536.0)
+    ap.add_argument("--inflight-rhs", type=int, default=0,
+                    help="most right-hand sides per solve batch (0: the library's default)")
     ap.add_argument("--hpe", type=int, default=0,
                     help="hopping parameter expansion order (1..4) for the loops without tau_3; 0: off")
     ap.add_argument("--tdil", type=int, default=0,
@@ -507,6 +509,8 @@ def main() -> int:
     stream = torch.cuda.current_stream()
     ctx = dl.dl_create(0, stream.cuda_stream)
     dl.dl_set_option(ctx, "inflight_mb", a.inflight_mb)
+    if a.inflight_rhs:
+        dl.dl_set_option(ctx, "inflight_rhs", a.inflight_rhs)
     if a.block_hop:
         dl.dl_set_option(ctx, "block_hop", 1)
     lat = dl.dl_lattice_create(ctx, dims, -1)
