@@ -317,13 +317,13 @@ __device__ inline void pack_transport(const uint32_t (&cr)[9], const uint32_t (&
 }
 
 // The rows one rhs of the link-centred derivative contraction reads, as
-// 16-bit words: s and xi at the site and at its +nu neighbour, and phi at both
-// (HPE).  Fetching them is separate from the arithmetic so that the loop can
-// load the next rhs while it contracts the current one.
+// 16-bit words: s and xi at the site (sh, xh) and at its +nu neighbour (so,
+// xo), and phi at both (ph, po; HPE).  All of an rhs's rows are requested
+// before its first product.
 template <bool HPE>
 struct DerivRows16 {
   uint32_t sh[12], so[12], xh[12], xo[12];
-  uint32_t fh[HPE ? 12 : 1], fo[HPE ? 12 : 1];
+  uint32_t ph[HPE ? 12 : 1], po[HPE ? 12 : 1];
 };
 
 template <class S, bool HPE>
@@ -336,8 +336,8 @@ __device__ inline void deriv_fetch16(DerivRows16<HPE>& d, const void* s_here, co
   load_words16(field_at<S>(x_here, off), vp, s, d.xh);
   load_words16(field_at<S>(x_other, off), vp, sp, d.xo);
   if constexpr (HPE) {
-    load_words16(field_at<S>(f_here, off), vp, s, d.fh);
-    load_words16(field_at<S>(f_other, off), vp, sp, d.fo);
+    load_words16(field_at<S>(f_here, off), vp, s, d.ph);
+    load_words16(field_at<S>(f_other, off), vp, sp, d.po);
   }
 }
 
@@ -373,7 +373,7 @@ __device__ inline void deriv_compute16(const DerivRows16<HPE>& d, const uint32_t
   }
   if (!xs) return;
   // xi-s block, first half: conj(xi_a) T_phi,b (phi = s unless HPE)
-  if constexpr (HPE) pack_transport<S>(cr, ci, d.fo, tp, tq);   // T_phi
+  if constexpr (HPE) pack_transport<S>(cr, ci, d.po, tp, tq);   // T_phi
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -389,7 +389,7 @@ __device__ inline void deriv_compute16(const DerivRows16<HPE>& d, const uint32_t
     }
   // second half: - conj(T_xi,a) phi_b, with (-re, -im) and (-re, im) of T_xi
   const uint32_t* ph;
-  if constexpr (HPE) ph = d.fh;
+  if constexpr (HPE) ph = d.ph;
   else ph = d.sh;
   {
     cx<float> t[12];
