@@ -437,6 +437,8 @@ def main() -> int:
     ap.add_argument("--workload", default="batched_24x24x24x48", choices=sorted(WORKLOADS))
     ap.add_argument("--rhs-block", type=int, default=0)
     ap.add_argument("--inflight-mb", type=float, default=65536.0)
+    ap.add_argument("--contract-tblk", type=int, default=0,
+                    help="time slices per block of the derivative contraction's tile order (0: the library's)")
     ap.add_argument("--inflight-rhs", type=int, default=0,
                     help="most right-hand sides per solve batch (0: the library's default)")
     ap.add_argument("--hpe", type=int, default=0,
@@ -511,6 +513,8 @@ def main() -> int:
     dl.dl_set_option(ctx, "inflight_mb", a.inflight_mb)
     if a.inflight_rhs:
         dl.dl_set_option(ctx, "inflight_rhs", a.inflight_rhs)
+    if a.contract_tblk:
+        dl.dl_set_option(ctx, "contract_tblk", a.contract_tblk)
     if a.block_hop:
         dl.dl_set_option(ctx, "block_hop", 1)
     lat = dl.dl_lattice_create(ctx, dims, -1)

@@ -336,6 +336,11 @@ int dl_loops_backward(dl_ctx* ctx, const dl_job* job, int p2max, const double* g
  *                   slice) on lattices whose shape allows it; 0 (default): the
  *                   tile kernel.  Changes the norms' summation order, so the
  *                   low-precision iterates, not their accuracy.
+ *   "contract_tblk" time slices per block of the derivative contraction's
+ *                   tile order (1..64, default 8): the tiles at one place of
+ *                   successive slices run together, so a tile's +t neighbour
+ *                   rows are read while they are still cached.  Results do
+ *                   not depend on it.
  *   "profile"       1: time every hopping-kernel launch of the CG (the
  *                   u_e = A^-1 H_eo p_o step) with HIP events on the context
  *                   stream and count its compulsory bytes; 0: off

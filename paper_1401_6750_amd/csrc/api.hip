@@ -744,6 +744,9 @@ int dl_set_option(dl_ctx* ctx, const char* name, double value) {
     } else if (n == "use_graph") {
       require(value == 0 || value == 1, "dl_set_option: use_graph must be 0 or 1");
       ctx->use_graph = value != 0;
+    } else if (n == "contract_tblk") {
+      require(value >= 1 && value <= 64, "dl_set_option: contract_tblk must be in 1..64");
+      ctx->contract_tblk = (int)value;
     } else if (n == "block_hop") {
       require(value == 0 || value == 1, "dl_set_option: block_hop must be 0 or 1");
       ctx->block_hop = value != 0;

@@ -443,7 +443,10 @@ k_contract_deriv(const SlotDesc* slots, int nslots, int total_units,
   const int si = find_slot(slots, nslots, UK_DERIV, u);
   const SlotDesc& sd = slots[si];
   const int ul = u - sd.ubeg[UK_DERIV];
-  const int nu = ul & 3, par = (ul >> 2) & 1, tile = ul >> 3;
+  // tiles in time blocks of sd.tblk slices (the pass sets the context's
+  // contract_tblk): the tile holding a tile's +t neighbour rows runs at
+  // nearly the same time, so those rows are still cached
+  const int nu = ul & 3, par = (ul >> 2) & 1, tile = tile_of(sd, ul >> 3);
   const int s = tile * TILE + (threadIdx.x & 63);
   if (s >= sd.Vh || !sd.acc || !(sd.acc_ops & 2)) return;
   const long vp = sd.Vp;

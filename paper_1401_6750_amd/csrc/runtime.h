@@ -47,6 +47,7 @@ struct dl_ctx {
   double inflight_mb = 32768.0;
   bool use_graph = true;
   bool block_hop = false;        // LDS-staged hop for 16-bit storage where the lattice shape allows
+  int contract_tblk = 8;         // time slices per block of the derivative contraction's tile order
   bool profile = false;
   // hopping-kernel profile per storage precision: launches, ms, bytes, rhs
   double prof[4][4] = {};

@@ -591,6 +591,7 @@ static void contract_passes(Batch& b, int P, const void* s_e, const void* s_o, c
     int us = 0, ud = 0;
     for (SlotDesc& d : pass) {
       dil = dil || d.tdil > 1;
+      d.tblk = b.ctx->contract_tblk;
       d.ubeg[UK_SITE] = us;
       d.ubeg[UK_DERIV] = ud;
       us += 2 * d.ntile;

@@ -479,6 +479,39 @@ def test_tile_order_and_tuned_shape_do_not_change_results(tmp_path):
         assert np.array_equal(got[0], ref[0]) and got[1] == ref[1], (blk, tb)
 
 
+def test_contraction_tile_order_does_not_change_loops():
+    """The derivative contraction's time-blocked tile order (option contract_tblk) only reorders
+    work over sites whose accumulators are independent: the loops are bit-identical for 1, 2, 3
+    and 8 slices per block (8^4 has whole tiles per time slice, so the blocked order is used;
+    3 leaves a partial block at the end)."""
+    t = torch()
+    ref = None
+    for tb in (1, 2, 3, 8):
+        c = dl.dl_create(0, t.cuda.current_stream().cuda_stream)
+        dl.dl_set_option(c, "contract_tblk", tb)
+        lat = make_lattice(c, (8, 8, 8, 8), 43, 0.2, 0.1615, 0.004)
+        acc = dl.dl_accum_create(lat.h, dl.DL_OPS_LOCAL | dl.DL_OPS_DERIV)
+        rc, _ = dl.dl_solve_batch(c, dl.make_job(lat.h, noise=dl.DL_NOISE_Z4, tier=dl.DL_TIER_LP_BF16, seed=7,
+                                                 nsrc=12, tol=1e-2, maxiter=200, rhs_block=4, accum=acc,
+                                                 accum_set=dl.DL_SET_HP))
+        assert rc == dl.DL_OK
+        out = np.zeros((2, 5, 16, 8, 7), dtype=np.complex128)
+        assert dl.dl_loops(c, acc, 1, out, 0) == 7
+        dl.dl_accum_destroy(acc)
+        lat.close()
+        dl.dl_destroy(c)
+        if ref is None:
+            ref = out
+        assert np.array_equal(out, ref), tb
+    assert np.abs(ref).max() > 0
+    c = dl.dl_create(0, t.cuda.current_stream().cuda_stream)
+    try:
+        with pytest.raises(dl.DiscloopError):
+            dl.dl_set_option(c, "contract_tblk", 0)
+    finally:
+        dl.dl_destroy(c)
+
+
 def test_graph_replay_equals_plain_launches(ctx):
     """CG iterations replayed from a HIP graph give the same bits as plain launches,
     and repeated graph runs with host work in between stay identical."""
