@@ -231,18 +231,32 @@ template <class S> struct Spinor {
   cx<R> c[12];
 };
 
-// Element i (per lane) of an array of 16-byte values that starts at `row`
-// (wave-uniform): a scalar base plus a 32-bit lane offset, the form the vector
-// memory instructions take directly, so no 64-bit address is formed and held
-// per lane.  Every array here has fewer than 2^28 elements per row.
+// Element i (per lane) of an array of 16-byte values in device memory that
+// starts at `row` (wave-uniform): a scalar base plus a 32-bit lane offset, the
+// form the vector memory instructions take directly, so no 64-bit address is
+// formed and held per lane.  Every array here has fewer than 2^28 elements per
+// row.  The access goes through a global-address-space pointer: a pointer read
+// from a descriptor (the links of a slot) is otherwise generic, and generic
+// (flat) loads make every later wait for any load also wait for all of them.
+// (The access is made on a native vector type: copying the HIP vector struct
+// would go through a generic reference again.)
+template <class T> struct Vec16;
+template <> struct Vec16<uint4> { typedef unsigned int type __attribute__((ext_vector_type(4))); };
+template <> struct Vec16<float4> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct Vec16<double2> { typedef double type __attribute__((ext_vector_type(2))); };
+#define DL_GLOBAL __attribute__((address_space(1)))
 template <class T>
-__device__ inline const T& at16(const void* row, long long i) {
-  return *(const T*)((const char*)row + ((uint32_t)i << 4));
+__device__ inline T at16(const void* row, long long i) {
+  using V = typename Vec16<T>::type;
+  const V v = *(const V DL_GLOBAL*)((const char*)row + ((uint32_t)i << 4));
+  return __builtin_bit_cast(T, v);
 }
 template <class T>
-__device__ inline T& at16(void* row, long long i) {
-  return *(T*)((char*)row + ((uint32_t)i << 4));
+__device__ inline void st16(void* row, long long i, const T& x) {
+  using V = typename Vec16<T>::type;
+  *(V DL_GLOBAL*)((char*)row + ((uint32_t)i << 4)) = __builtin_bit_cast(V, x);
 }
+#undef DL_GLOBAL
 // Row k of a family of rows `stride` elements apart.
 __device__ inline const void* row16(const void* base, long long k, long long stride) {
   return (const char*)base + k * stride * 16;
@@ -297,13 +311,13 @@ __device__ inline void store_spinor(void* base, long stride, long s, const cx<ty
 template <>
 __device__ inline void store_spinor<double>(void* base, long stride, long s, const cx<double> (&v)[12]) {
 #pragma unroll
-  for (int k = 0; k < 12; ++k) at16<double2>(row16(base, k, stride), s) = make_double2(v[k].re, v[k].im);
+  for (int k = 0; k < 12; ++k) st16<double2>(row16(base, k, stride), s, make_double2(v[k].re, v[k].im));
 }
 template <>
 __device__ inline void store_spinor<float>(void* base, long stride, long s, const cx<float> (&v)[12]) {
 #pragma unroll
   for (int k = 0; k < 6; ++k)
-    at16<float4>(row16(base, k, stride), s) = make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im);
+    st16<float4>(row16(base, k, stride), s, make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im));
 }
 template <class S16>
 __device__ inline void store_spinor16(void* base, long stride, long s, const cx<float> (&v)[12]) {
@@ -314,7 +328,7 @@ __device__ inline void store_spinor16(void* base, long stride, long s, const cx<
     w.y = pack2<S16>(v[4 * k + 1]);
     w.z = pack2<S16>(v[4 * k + 2]);
     w.w = pack2<S16>(v[4 * k + 3]);
-    at16<uint4>(row16(base, k, stride), s) = w;
+    st16<uint4>(row16(base, k, stride), s, w);
   }
 }
 template <>
