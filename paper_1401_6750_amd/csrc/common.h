@@ -547,7 +547,7 @@ inline int clover_rows(int prec) { return prec == P64 ? 72 : 36; }
 template <int G>
 __device__ inline void site_matvec(const void* m, int kind, int par, long vp, long s, const cx<double> (&in)[G][12],
                                    cx<double> (&out)[G][12], const bool (&act)[G]) {
-  const double2* p = (const double2*)m + (long)(kind * 2 + par) * 72 * vp + s;
+  const long long r0 = (long long)(kind * 2 + par) * 72;
 #pragma unroll
   for (int b = 0; b < 2; ++b)
 #pragma unroll
@@ -555,7 +555,7 @@ __device__ inline void site_matvec(const void* m, int kind, int par, long vp, lo
       cx<double> row[6];
 #pragma unroll
       for (int j = 0; j < 6; ++j) {
-        const double2 w = p[(long)(36 * b + 6 * i + j) * vp];
+        const double2 w = at16<double2>(row16(m, r0 + 36 * b + 6 * i + j, vp), s);
         row[j] = mk<double>(w.x, w.y);
       }
 #pragma unroll
@@ -572,7 +572,7 @@ __device__ inline void site_matvec(const void* m, int kind, int par, long vp, lo
 template <int G>
 __device__ inline void site_matvec(const void* m, int kind, int par, long vp, long s, const cx<float> (&in)[G][12],
                                    cx<float> (&out)[G][12], const bool (&act)[G]) {
-  const float4* p = (const float4*)m + (long)(kind * 2 + par) * 36 * vp + s;
+  const long long r0 = (long long)(kind * 2 + par) * 36;
 #pragma unroll
   for (int b = 0; b < 2; ++b)
 #pragma unroll
@@ -580,7 +580,7 @@ __device__ inline void site_matvec(const void* m, int kind, int par, long vp, lo
       cx<float> row[6];
 #pragma unroll
       for (int j = 0; j < 6; j += 2) {
-        const float4 w = p[(long)((36 * b + 6 * i + j) / 2) * vp];
+        const float4 w = at16<float4>(row16(m, r0 + (36 * b + 6 * i + j) / 2, vp), s);
         row[j] = mk<float>(w.x, w.y);
         row[j + 1] = mk<float>(w.z, w.w);
       }

@@ -85,9 +85,13 @@ __device__ inline void flush(double* acc, long long V, int lane, A (&a)[48], boo
         }
       }
   }
+  // the accumulator pointer comes from the slot descriptor: accessed through a
+  // global-address-space pointer, not as generic (flat) memory
+  using GD = __attribute__((address_space(1))) double;
+  GD* const g = (GD*)acc;
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
-    double* p = acc + q * V;
+    GD* p = g + q * V;
     const double f = DERIV ? (q < 4 ? 0.5 : 0.25) : 1.0;
     p[lane] += f * (double)a[q];
     a[q] = (A)0;
@@ -95,7 +99,7 @@ __device__ inline void flush(double* acc, long long V, int lane, A (&a)[48], boo
   if (xs) {   // else the xi-s block was not contracted at this site in this block
 #pragma unroll
     for (int q = 16; q < 48; ++q) {
-      double* p = acc + q * V;
+      GD* p = g + q * V;
       p[lane] += (DERIV ? 0.25 : 1.0) * (double)a[q];
       a[q] = (A)0;
     }
@@ -461,8 +465,9 @@ k_contract_deriv(const SlotDesc* slots, int nslots, int total_units,
   cx<R> up[9];
   uint32_t cr[9], ci[9];
   if constexpr (Traits<S>::NC == 3) {
-    const uint4* lp = (const uint4*)gauge + (long)(nu * 2 + par) * 3 * vp + s;
-    const uint4 l0 = lp[0], l1 = lp[vp], l2 = lp[2 * vp];
+    const long long lr = (nu * 2 + par) * 3;
+    const uint4 l0 = at16<uint4>(row16(gauge, lr, vp), s), l1 = at16<uint4>(row16(gauge, lr + 1, vp), s),
+                l2 = at16<uint4>(row16(gauge, lr + 2, vp), s);
     const uint32_t e[9] = {l0.x, l0.y, l0.z, l0.w, l1.x, l1.y, l1.z, l1.w, l2.x};
     link_coef16<true>(e, b < (R)0, cr, ci);
   } else {

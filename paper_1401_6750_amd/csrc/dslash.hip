@@ -549,12 +549,12 @@ __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
 template <int MU, bool NINE, int G>
 __device__ inline void hop_fill16(HopWords<G>& h, const void* gauge, long vp, int link_par, int link_site,
                                   const uint4* const (&src)[G], int cstride, uint32_t nine) {
-  const uint4* lp = (const uint4*)gauge + (long)(MU * 2 + link_par) * 3 * vp + link_site;
-  const uint4 l0 = lp[0], l1 = lp[vp];
+  const long long lr = (MU * 2 + link_par) * 3;
+  const uint4 l0 = at16<uint4>(row16(gauge, lr, vp), link_site), l1 = at16<uint4>(row16(gauge, lr + 1, vp), link_site);
   h.e[0] = l0.x; h.e[1] = l0.y; h.e[2] = l0.z; h.e[3] = l0.w;
   h.e[4] = l1.x; h.e[5] = l1.y; h.e[6] = l1.z; h.e[7] = l1.w;
   if constexpr (NINE) h.e[8] = nine;
-  else h.e[8] = lp[2 * vp].x;
+  else h.e[8] = at16<uint4>(row16(gauge, lr + 2, vp), link_site).x;
 #pragma unroll
   for (int i = 0; i < G; ++i) {
     const uint4 q0 = src[i][0], q1 = src[i][cstride], q2 = src[i][2 * cstride];
@@ -736,8 +736,8 @@ __global__ __launch_bounds__(256) void k_dslash_blk(DslashArgs a) {
 #pragma unroll
         for (int i = 0; i < G; ++i) ld[i] = act[i] ? (const void*)inb[i] : fa;
       }
-      const uint4 nf = ((const uint4*)gauge)[(long)(LINK_ROW_NINTH + p_out) * vp + s];
-      const uint4 nbw = ((const uint4*)gauge)[(long)(LINK_ROW_NINTH_BWD + p_out) * vp + s];
+      const uint4 nf = at16<uint4>(row16(gauge, LINK_ROW_NINTH + p_out, vp), s);
+      const uint4 nbw = at16<uint4>(row16(gauge, LINK_ROW_NINTH_BWD + p_out, vp), s);
       cx<float> acc[G][12];
       HopWords<G> h0, h1;
       // the hops in the tile kernel's order (x, y, z, t; per-site results are the same bits)
