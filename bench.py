@@ -433,7 +433,7 @@ def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="batched_24x24x24x48", choices=sorted(WORKLOADS))
     ap.add_argument("--rhs-block", type=int, default=0)
     ap.add_argument("--inflight-mb", type=float, default=65536.0)
@@ -571,12 +571,15 @@ def main() -> int:
         rc, st = step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    marks = []
     for i in range(a.steps):
-        rc, st = step()
+        rc, st = step()          # the solves synchronise; only the projection may still run
+        marks.append(time.perf_counter())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms = (t1 - t0) * 1e3 / a.steps
-    log(f"timed {a.steps} steps: {ms:.1f} ms/step")
+    per = [round((b - a_) * 1e3, 1) for a_, b in zip([t0] + marks[:-1], marks)]
+    log(f"timed {a.steps} steps: {ms:.1f} ms/step (each: {per})")
     assert rc == dl.DL_OK, f"solve status {rc}"
     # projection + Gamma rebuild + TSM combination alone (part of every step above)
     torch.cuda.synchronize()
