@@ -25,8 +25,10 @@
 namespace dl {
 
 // out += sign * M u for a 4x4 spin matrix (complex128 entries, or their
-// adjoint when DAG) acting on a colour-spinor.
-template <bool DAG>
+// adjoint when DAG) acting on a colour-spinor; G5: on gamma_5 u instead (the
+// sign of spins 2, 3 flipped, exactly as a negated copy of u would give, with
+// no copy held in registers).
+template <bool DAG, bool G5 = false>
 __device__ inline void spin_mat_acc(const double2 (&m)[16], const cx<double> (&u)[12], double sign,
                                     cx<double> (&out)[12]) {
 #pragma unroll
@@ -35,8 +37,9 @@ __device__ inline void spin_mat_acc(const double2 (&m)[16], const cx<double> (&u
     for (int b = 0; b < 4; ++b) {
       const double2 e = DAG ? m[4 * b + a] : m[4 * a + b];
       const cx<double> w = DAG ? mk<double>(e.x, -e.y) : mk<double>(e.x, e.y);
+      const double sb = (G5 && b >= 2) ? -sign : sign;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) out[3 * a + c] = out[3 * a + c] + sign * (w * u[3 * b + c]);
+      for (int c = 0; c < 3; ++c) out[3 * a + c] = out[3 * a + c] + sb * (w * u[3 * b + c]);
     }
 }
 
@@ -104,12 +107,9 @@ __global__ __launch_bounds__(256) void k_insert_apply(const SlotDesc* slots, int
     const void* s_oth = field_at<double>(par ? s_e : s_o, off);
     const void* m_here = field_at<double>(par ? m_o : m_e, off);
     const void* m_oth = field_at<double>(par ? m_e : m_o, off);
-    cx<double> sv[12], mv[12], s5[12];
+    cx<double> sv[12], mv[12];
     load_spinor<double>(s_here, vp, s, sv);
     load_spinor<double>(m_here, vp, s, mv);
-#pragma unroll
-    for (int k = 0; k < 12; ++k) s5[k] = sv[k];
-    g5(s5);
     cx<double> qt3[12], A[12], C[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) qt3[k] = A[k] = C[k] = mk<double>(0, 0);
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(256) void k_insert_apply(const SlotDesc* slots, int
     // local parts
     load_omega(om_t3, V, site, w);
     spin_mat_acc<false>(w, sv, 1.0, qt3);
-    spin_mat_acc<true>(w, s5, 1.0, C);
+    spin_mat_acc<true, true>(w, sv, 1.0, C);
     load_omega(om_1, V, site, w);
     spin_mat_acc<false>(w, sv, 1.0, A);
     spin_mat_acc<true>(w, mv, 1.0, C);
@@ -148,19 +148,13 @@ __global__ __launch_bounds__(256) void k_insert_apply(const SlotDesc* slots, int
         const double2* o3 = om_t3 + (long long)(1 + nu) * 16 * V;
         load_omega(o3, V, site, w);
         spin_mat_acc<false>(w, dt, 0.25, qt3);
-        cx<double> d5[12], tp5[12], tm5[12];
-#pragma unroll
-        for (int k = 0; k < 12; ++k) { d5[k] = dt[k]; tp5[k] = tp[k]; tm5[k] = tm[k]; }
-        g5(d5);
-        g5(tp5);
-        g5(tm5);
-        spin_mat_acc<true>(w, d5, -0.25, C);
+        spin_mat_acc<true, true>(w, dt, -0.25, C);
         load_omega(o3, V, site_p, w);
         spin_mat_acc<false>(w, tp, 0.25, qt3);
-        spin_mat_acc<true>(w, tp5, -0.25, C);
+        spin_mat_acc<true, true>(w, tp, -0.25, C);
         load_omega(o3, V, site_m, w);
         spin_mat_acc<false>(w, tm, -0.25, qt3);
-        spin_mat_acc<true>(w, tm5, 0.25, C);
+        spin_mat_acc<true, true>(w, tm, 0.25, C);
         // no-tau_3 flavour: Q_1 s into A, Q_1^dag (M_0 s) into C
         const double2* o1 = om_1 + (long long)(1 + nu) * 16 * V;
         load_omega(o1, V, site, w);
