@@ -188,7 +188,12 @@ int dl_lattice_destroy(dl_lattice* lat);
 
 /* Copy a gauge field in (layout above) and pack it into the FP64, FP32, bf16
  * and fp16 even-odd layouts.  on_device: 0 host pointer, 1 device pointer.
- * The caller keeps ownership of `links`. */
+ * The caller keeps ownership of `links`.  Any complex 3x3 links are accepted;
+ * when every link's row 2 equals the complex conjugate of the cross product
+ * of rows 0 and 1 to 1e-6 (true of SU(3) matrices, the links of lattice
+ * QCD), the bf16 / fp16 hopping kernels read rows 0 and 1 only and
+ * rebuild row 2, otherwise they read all nine entries (checked here, on the
+ * GPU, once per call). */
 int dl_gauge_set(dl_lattice* lat, const double* links, int on_device);
 
 /* Synthetic gauge field, the stand-in for the paper's twisted-mass ensembles

@@ -520,7 +520,7 @@ void launch_diff_norms(const SlotDesc* slots, int nslots, int total_units, const
 // gauge packing
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_pack_gauge(const double* src, int X, int Y, int Z, int T, void* g64,
-                                                    void* g32, void* gb16, void* gh16) {
+                                                    void* g32, void* gb16, void* gh16, int* not_su3) {
   const long long V = (long long)X * Y * Z * T;
   const long long vp = pad_half(V / 2);   // row stride of the link chunk rows
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -536,12 +536,31 @@ __global__ __launch_bounds__(256) void k_pack_gauge(const double* src, int X, in
   const int par = (x + y + z + t) & 1;
   const long long s = lex >> 1;
   const double2* u = (const double2*)src + (lex * 4 + mu) * 9;
+  // a special unitary matrix has orthonormal rows and unit determinant, so
+  // its row 2 is the complex conjugate of the cross product of rows 0 and 1:
+  // the identity the 16-bit hop uses; flag any link that misses it by > 1e-6
+  {
+    double dev = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      const int i = (k + 1) % 3, j = (k + 2) % 3;
+      const double2 ai = u[i], aj = u[j], bi = u[3 + i], bj = u[3 + j];
+      const double re = ai.x * bj.x - ai.y * bj.y - (aj.x * bi.x - aj.y * bi.y);
+      const double im = ai.x * bj.y + ai.y * bj.x - (aj.x * bi.y + aj.y * bi.x);
+      dev = fmax(dev, fmax(fabs(u[6 + k].x - re), fabs(u[6 + k].y + im)));
+    }
+    if (!(dev <= 1e-6)) atomicOr(not_su3, 1);
+  }
   // chunk rows [mu][parity][chunk][site] of vp sites (common.h)
   const long long row = (long long)(mu * 2 + par);
   double2* r64 = (double2*)g64;
   float2* r32 = (float2*)g32;        // 5 chunks of 2 complex
   uint32_t* rb = (uint32_t*)gb16;    // 3 chunks of 4 complex
   uint32_t* rh = (uint32_t*)gh16;
+  // the site x + mu, which this link reaches from behind
+  int xn[4] = {x, y, z, t};
+  const int ext[4] = {X, Y, Z, T};
+  xn[mu] = xn[mu] + 1 == ext[mu] ? 0 : xn[mu] + 1;
+  const long long sn = (xn[0] + (long long)X * (xn[1] + (long long)Y * (xn[2] + (long long)Z * xn[3]))) >> 1;
   for (int e = 0; e < 12; ++e) {
     const double2 q = e < 9 ? u[e] : make_double2(0.0, 0.0);  // zero padding
     if (e < 9) r64[(row * 9 + e) * vp + s] = q;
@@ -555,22 +574,27 @@ __global__ __launch_bounds__(256) void k_pack_gauge(const double* src, int X, in
       rb[n16] = pack2<bf16s>(qf);
       rh[n16] = pack2<f16s>(qf);
       // and at x + mu, among the links reaching that site from behind
-      int xn[4] = {x, y, z, t};
-      const int ext[4] = {X, Y, Z, T};
-      xn[mu] = xn[mu] + 1 == ext[mu] ? 0 : xn[mu] + 1;
-      const long long lexn = xn[0] + (long long)X * (xn[1] + (long long)Y * (xn[2] + (long long)Z * xn[3]));
-      const long long b16 = ((long long)(LINK_ROW_NINTH_BWD + 1 - par) * vp + (lexn >> 1)) * 4 + mu;
+      const long long b16 = ((long long)(LINK_ROW_NINTH_BWD + 1 - par) * vp + sn) * 4 + mu;
       rb[b16] = pack2<bf16s>(qf);
       rh[b16] = pack2<f16s>(qf);
+    }
+    if (e < 6) {    // rows 0 and 1 again, site-centred, at x and at x + mu
+      const int j = 6 * (mu & 1) + e;
+      const long long cf = (long long)LINK_ROW_R12 + 12 * par + 3 * (mu >> 1) + j / 4;
+      const long long cb = (long long)LINK_ROW_R12 + 12 * (1 - par) + 6 + 3 * (mu >> 1) + j / 4;
+      rb[(cf * vp + s) * 4 + j % 4] = pack2<bf16s>(qf);
+      rh[(cf * vp + s) * 4 + j % 4] = pack2<f16s>(qf);
+      rb[(cb * vp + sn) * 4 + j % 4] = pack2<bf16s>(qf);
+      rh[(cb * vp + sn) * 4 + j % 4] = pack2<f16s>(qf);
     }
   }
 }
 
 void launch_pack_gauge(const double* src, int X, int Y, int Z, int T, void* g64, void* g32, void* gb16,
-                       void* gh16, hipStream_t st) {
+                       void* gh16, int* not_su3, hipStream_t st) {
   const long long n = (long long)X * Y * Z * T * 4;
   hipLaunchKernelGGL(k_pack_gauge, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, X, Y, Z, T, g64,
-                     g32, gb16, gh16);
+                     g32, gb16, gh16, not_su3);
 }
 
 }  // namespace dl

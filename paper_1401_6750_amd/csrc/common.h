@@ -382,7 +382,14 @@ inline int link_chunks(int prec) { return prec == P64 ? 9 : (prec == P32 ? 5 : 3
 // eight (copies; the entries also stay in the links' own chunk rows).
 constexpr int LINK_ROW_NINTH = 24;
 constexpr int LINK_ROW_NINTH_BWD = 26;
-inline int link_rows(int prec) { return 8 * link_chunks(prec) + ((prec == PB16 || prec == PH16) ? 4 : 0); }
+// 16-bit links, site-centred copies of rows 0 and 1 only (6 words a link) for
+// the hopping kernel, which rebuilds row 2 (SU(3)): per parity 12 rows from
+// LINK_ROW_R12 + 12 parity, the first 6 for the links leaving the site,
+// U_mu(x), the last 6 for those reaching it, U_mu(x - mu); two directions
+// share three rows, word j = 6 (mu & 1) + entry at row 3 (mu >> 1) + j / 4,
+// component j % 4.
+constexpr int LINK_ROW_R12 = 28;
+inline int link_rows(int prec) { return 8 * link_chunks(prec) + ((prec == PB16 || prec == PH16) ? 28 : 0); }
 
 template <class S>
 __device__ inline void load_link(const void* g, long vh, int mu, int par, long s, cx<typename Traits<S>::R> (&u)[9]);
@@ -479,6 +486,8 @@ struct SlotDesc {
   int rhs_begin;           // global index of this slot's rhs 0
   long long fo;            // site offset of rhs 0 in every batch field
   double bc;               // time-boundary factor
+  int su3;                 // 1: the links are special unitary (row 2 = conj(row 0 x row 1)),
+                           // the 16-bit hop reads the two-row copies
   const void* gauge[4];    // gauge field per precision
   const void* clv64;       // clover site matrices (FP64 class), or null: no clover term
   const void* clv32;       // clover site matrices (FP32 class, all other tiers), or null

@@ -250,6 +250,56 @@ __device__ inline void hop_load16(HopWords<G>& h, const void* gauge, long vp, in
   }
 }
 
+// Two-row links (SU(3)): rows 0 and 1 of two directions from three chunks of
+// the site-centred rows (LINK_ROW_R12), forward (BWD = 0) or backward.
+struct Link12 {
+  uint32_t w[12];
+};
+__device__ inline void load_link12(Link12& L, const void* gauge, long vp, int par, int bwd, int pair, int s) {
+  const long long r = LINK_ROW_R12 + 12 * par + 6 * bwd + 3 * pair;
+  const uint4 a = at16<uint4>(row16(gauge, r, vp), s), b = at16<uint4>(row16(gauge, r + 1, vp), s),
+              c = at16<uint4>(row16(gauge, r + 2, vp), s);
+  L.w[0] = a.x; L.w[1] = a.y; L.w[2] = a.z; L.w[3] = a.w;
+  L.w[4] = b.x; L.w[5] = b.y; L.w[6] = b.z; L.w[7] = b.w;
+  L.w[8] = c.x; L.w[9] = c.y; L.w[10] = c.z; L.w[11] = c.w;
+}
+// The words of one hop from a two-row pair (direction M of the pair) and the
+// neighbour spinor of every group member.
+template <int G>
+__device__ inline void hop_load12(HopWords<G>& h, const Link12& L, int m, long vp, int nb,
+                                  const void* const (&inb)[G]) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) h.e[k] = L.w[6 * m + k];
+#pragma unroll
+  for (int i = 0; i < G; ++i) {
+    const uint4 q0 = at16<uint4>(inb[i], nb), q1 = at16<uint4>(row16(inb[i], 1, vp), nb),
+                q2 = at16<uint4>(row16(inb[i], 2, vp), nb);
+    h.v[i][0] = q0.x; h.v[i][1] = q0.y; h.v[i][2] = q0.z; h.v[i][3] = q0.w;
+    h.v[i][4] = q1.x; h.v[i][5] = q1.y; h.v[i][6] = q1.z; h.v[i][7] = q1.w;
+    h.v[i][8] = q2.x; h.v[i][9] = q2.y; h.v[i][10] = q2.z; h.v[i][11] = q2.w;
+  }
+}
+// Row 2 of an SU(3) link from rows 0 and 1: the rows are orthonormal and the
+// determinant is one, so row 2 is the complex conjugate of the cross product
+// of rows 0 and 1.  FP32 arithmetic on the stored values, rounded to the
+// storage format as a stored entry is.
+template <class S>
+__device__ inline void link_row2(uint32_t (&e)[9]) {
+  cx<float> a[3], b[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    a[k] = unpack2<S>(e[k]);
+    b[k] = unpack2<S>(e[3 + k]);
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int i = (k + 1) % 3, j = (k + 2) % 3;
+    const float re = fmaf(a[i].re, b[j].re, fmaf(-a[i].im, b[j].im, fmaf(-a[j].re, b[i].re, a[j].im * b[i].im)));
+    const float im = fmaf(a[i].re, b[j].im, fmaf(a[i].im, b[j].re, fmaf(-a[j].re, b[i].im, -(a[j].im * b[i].re))));
+    e[6 + k] = pack2<S>(mk<float>(re, -im));
+  }
+}
+
 // Coefficient operand of the packed colour products: the link word w (SW =
 // false) or its half-swapped form (SW = true), with the signs of its low / high
 // half flipped (NLO / NHI) by the dot2 input modifiers, so no instruction is
@@ -311,6 +361,71 @@ __device__ inline void hop_compute16(const HopWords<G>& h, float sign, const boo
                                      chain16<S, Ci, ProjIm<PS::c1, FWD>>(w, sw, v, 1, PS::b1));
       reconstruct_row<MU, FWD, INIT>(acc[i], a, w0, w1, sign);
     }
+  }
+}
+
+// The eight hops of a site on 16-bit fields, in the order x+, x-, y+, ..., t-,
+// each hop's link and neighbour words loaded while the previous hop computes.
+// TWO_ROW (SU(3) links): rows 0 and 1 of the eight links from the site-centred
+// two-row copies, two directions per three loads, and row 2 rebuilt before
+// each hop's arithmetic (12 link loads for the site instead of 18); otherwise
+// all nine entries, the ninth of the four forward and of the four backward
+// links from one load each.  nbr: neighbour sites in that order.
+template <class S, bool TWO_ROW, int G>
+__device__ __forceinline__ void hops16(const void* gauge, long vp, int p_out, int s, const int (&nbr)[8], float sp,
+                                       float sm, const void* const (&ld)[G], const bool (&act)[G],
+                                       cx<float> (&acc)[G][12]) {
+  const int q = 1 - p_out;
+  HopWords<G> h0, h1;
+  if constexpr (TWO_ROW) {
+    Link12 lf, lb;
+    load_link12(lf, gauge, vp, p_out, 0, 0, s);
+    load_link12(lb, gauge, vp, p_out, 1, 0, s);
+    hop_load12(h0, lf, 0, vp, nbr[0], ld);
+    hop_load12(h1, lb, 0, vp, nbr[1], ld);
+    link_row2<S>(h0.e);
+    hop_compute16<S, 0, true, true>(h0, 1.0f, act, acc);
+    hop_load12(h0, lf, 1, vp, nbr[2], ld);
+    link_row2<S>(h1.e);
+    hop_compute16<S, 0, false, false>(h1, 1.0f, act, acc);
+    hop_load12(h1, lb, 1, vp, nbr[3], ld);
+    load_link12(lf, gauge, vp, p_out, 0, 1, s);
+    load_link12(lb, gauge, vp, p_out, 1, 1, s);
+    link_row2<S>(h0.e);
+    hop_compute16<S, 1, true, false>(h0, 1.0f, act, acc);
+    hop_load12(h0, lf, 0, vp, nbr[4], ld);
+    link_row2<S>(h1.e);
+    hop_compute16<S, 1, false, false>(h1, 1.0f, act, acc);
+    hop_load12(h1, lb, 0, vp, nbr[5], ld);
+    link_row2<S>(h0.e);
+    hop_compute16<S, 2, true, false>(h0, 1.0f, act, acc);
+    hop_load12(h0, lf, 1, vp, nbr[6], ld);
+    link_row2<S>(h1.e);
+    hop_compute16<S, 2, false, false>(h1, 1.0f, act, acc);
+    hop_load12(h1, lb, 1, vp, nbr[7], ld);
+    link_row2<S>(h0.e);
+    hop_compute16<S, 3, true, false>(h0, sp, act, acc);
+    link_row2<S>(h1.e);
+    hop_compute16<S, 3, false, false>(h1, sm, act, acc);
+  } else {
+    const uint4 nf = at16<uint4>(row16(gauge, LINK_ROW_NINTH + p_out, vp), s);
+    const uint4 nb = at16<uint4>(row16(gauge, LINK_ROW_NINTH_BWD + p_out, vp), s);
+    hop_load16<0, true>(h0, gauge, vp, p_out, s, nbr[0], ld, nf.x);
+    hop_load16<0, true>(h1, gauge, vp, q, nbr[1], nbr[1], ld, nb.x);
+    hop_compute16<S, 0, true, true>(h0, 1.0f, act, acc);
+    hop_load16<1, true>(h0, gauge, vp, p_out, s, nbr[2], ld, nf.y);
+    hop_compute16<S, 0, false, false>(h1, 1.0f, act, acc);
+    hop_load16<1, true>(h1, gauge, vp, q, nbr[3], nbr[3], ld, nb.y);
+    hop_compute16<S, 1, true, false>(h0, 1.0f, act, acc);
+    hop_load16<2, true>(h0, gauge, vp, p_out, s, nbr[4], ld, nf.z);
+    hop_compute16<S, 1, false, false>(h1, 1.0f, act, acc);
+    hop_load16<2, true>(h1, gauge, vp, q, nbr[5], nbr[5], ld, nb.z);
+    hop_compute16<S, 2, true, false>(h0, 1.0f, act, acc);
+    hop_load16<3, true>(h0, gauge, vp, p_out, s, nbr[6], ld, nf.w);
+    hop_compute16<S, 2, false, false>(h1, 1.0f, act, acc);
+    hop_load16<3, true>(h1, gauge, vp, q, nbr[7], nbr[7], ld, nb.w);
+    hop_compute16<S, 3, true, false>(h0, sp, act, acc);
+    hop_compute16<S, 3, false, false>(h1, sm, act, acc);
   }
 }
 
@@ -505,27 +620,9 @@ __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
 #pragma unroll
     for (int i = 0; i < G; ++i) ld[i] = act[i] ? inb[i] : fa;
     if constexpr (Traits<S>::NC == 3 && !HD) {
-      // ninth entries of the four links leaving this site and of the four
-      // reaching it, one load each
-      const uint4 nf = at16<uint4>(row16(gauge, LINK_ROW_NINTH + p_out, vp), s);
-      const uint4 nb = at16<uint4>(row16(gauge, LINK_ROW_NINTH_BWD + p_out, vp), s);
-      HopWords<G> h0, h1;
-      hop_load16<0, true>(h0, gauge, vp, p_out, s, nxp, ld, nf.x);
-      hop_load16<0, true>(h1, gauge, vp, q, nxm, nxm, ld, nb.x);
-      hop_compute16<S, 0, true, true>(h0, 1.0f, act, acc);
-      hop_load16<1, true>(h0, gauge, vp, p_out, s, nyp, ld, nf.y);
-      hop_compute16<S, 0, false, false>(h1, 1.0f, act, acc);
-      hop_load16<1, true>(h1, gauge, vp, q, nym, nym, ld, nb.y);
-      hop_compute16<S, 1, true, false>(h0, 1.0f, act, acc);
-      hop_load16<2, true>(h0, gauge, vp, p_out, s, nzp, ld, nf.z);
-      hop_compute16<S, 1, false, false>(h1, 1.0f, act, acc);
-      hop_load16<2, true>(h1, gauge, vp, q, nzm, nzm, ld, nb.z);
-      hop_compute16<S, 2, true, false>(h0, 1.0f, act, acc);
-      hop_load16<3, true>(h0, gauge, vp, p_out, s, ntp, ld, nf.w);
-      hop_compute16<S, 2, false, false>(h1, 1.0f, act, acc);
-      hop_load16<3, true>(h1, gauge, vp, q, ntm, ntm, ld, nb.w);
-      hop_compute16<S, 3, true, false>(h0, (float)sp, act, acc);
-      hop_compute16<S, 3, false, false>(h1, (float)sm, act, acc);
+      const int nbr[8] = {nxp, nxm, nyp, nym, nzp, nzm, ntp, ntm};
+      if (sd.su3) hops16<S, true>(gauge, vp, p_out, s, nbr, (float)sp, (float)sm, ld, act, acc);
+      else hops16<S, false>(gauge, vp, p_out, s, nbr, (float)sp, (float)sm, ld, act, acc);
     } else {
     hop<S, 0, true, HD, true>(gauge, vp, p_out, s, nxp, (R)1, ld, nr, act, d, acc);
     hop<S, 0, false, HD, false>(gauge, vp, q, nxm, nxm, (R)1, ld, nr, act, d, acc);
@@ -756,22 +853,33 @@ __global__ __launch_bounds__(256) void k_dslash_blk(DslashArgs a) {
       const uint4 nbw = at16<uint4>(row16(gauge, LINK_ROW_NINTH_BWD + p_out, vp), s);
       cx<float> acc[G][12];
       HopWords<G> h0, h1;
-      // the hops in the tile kernel's order (x, y, z, t; per-site results are the same bits)
+      // the hops in the tile kernel's order (x, y, z, t; per-site results are
+      // the same bits: with SU(3) links row 2 is rebuilt from the stored rows
+      // 0 and 1, the words the tile kernel reads from the two-row copies)
+      const bool two = sd.su3 != 0;
       hop_fill16<0, true>(h0, gauge, vp, p_out, s, pxp, Xh, nf.x);
       hop_fill16<0, true>(h1, gauge, vp, q, nxm, pxm, Xh, nbw.x);
+      if (two) link_row2<S>(h0.e);
       hop_compute16<S, 0, true, true>(h0, 1.0f, act, acc);
       hop_fill16<1, true>(h0, gauge, vp, p_out, s, pyp, Xh, nf.y);
+      if (two) link_row2<S>(h1.e);
       hop_compute16<S, 0, false, false>(h1, 1.0f, act, acc);
       hop_fill16<1, true>(h1, gauge, vp, q, nym, pym, Xh, nbw.y);
+      if (two) link_row2<S>(h0.e);
       hop_compute16<S, 1, true, false>(h0, 1.0f, act, acc);
       hop_fill16<2, true>(h0, gauge, vp, p_out, s, pzp, Xh, nf.z);
+      if (two) link_row2<S>(h1.e);
       hop_compute16<S, 1, false, false>(h1, 1.0f, act, acc);
       hop_fill16<2, true>(h1, gauge, vp, q, nzm, pzm, Xh, nbw.z);
+      if (two) link_row2<S>(h0.e);
       hop_compute16<S, 2, true, false>(h0, 1.0f, act, acc);
       hop_load16<3, true>(h0, gauge, vp, p_out, s, ntp, ld, nf.w);
+      if (two) link_row2<S>(h1.e);
       hop_compute16<S, 2, false, false>(h1, 1.0f, act, acc);
       hop_load16<3, true>(h1, gauge, vp, q, ntm, ntm, ld, nbw.w);
+      if (two) link_row2<S>(h0.e);
       hop_compute16<S, 3, true, false>(h0, sp, act, acc);
+      if (two) link_row2<S>(h1.e);
       hop_compute16<S, 3, false, false>(h1, sm, act, acc);
       dslash_epilogue<S, F, G>(a, sd, cf, nullptr, -1, -1, -1, p_out, vp, s, off, r0, act, e, f, g, acc, nrm);
     }

@@ -135,9 +135,11 @@ void launch_residual_replace(const SlotDesc* slots, int nslots, int total_units,
 void launch_diff_norms(const SlotDesc* slots, int nslots, int total_units, const void* a,
                        const void* b, double* partial_diff, double* partial_b, hipStream_t st);
 
-// gauge packing: FP64 [t][z][y][x][mu][3][3] (device) -> four even-odd layouts
+// gauge packing: FP64 [t][z][y][x][mu][3][3] (device) -> four even-odd layouts;
+// *not_su3 (device, cleared by the caller) is set to 1 if a link's row 2 is not
+// conj(row 0 x row 1) to 1e-6
 void launch_pack_gauge(const double* src, int X, int Y, int Z, int T, void* g64, void* g32,
-                       void* gb16, void* gh16, hipStream_t st);
+                       void* gb16, void* gh16, int* not_su3, hipStream_t st);
 
 // loop contractions of a block of solutions into FP64 accumulators.
 // Without phi (null): the one-end-trick structures, (xi, s) pairs with

@@ -18,7 +18,7 @@ import pytest
 import paper_1401_6750_amd as dl
 import synth
 from oracle import dirac, loops, noise, solver
-from tests.gpu_util import dev, elementwise, elementwise_check, host, make_lattice, rel, torch, zeros_dev
+from tests.gpu_util import Lattice, dev, elementwise, elementwise_check, host, make_lattice, rel, torch, zeros_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -118,6 +118,28 @@ def test_operators_storage_precision(ctx, tier, tol, dims, bc):
         torch().cuda.synchronize()
         e = rel(host(out), oracle_op(lat, op, psi))
         log("  op", op, "rel err", e)
+        assert e < tol, (op, e)
+    lat.close()
+
+
+@pytest.mark.parametrize("tier,tol", [(dl.DL_TIER_LP_FP16, 2e-3), (dl.DL_TIER_LP_BF16, 1.6e-2)])
+def test_operators_16bit_links_not_special_unitary(ctx, tier, tol):
+    """Links in U(3) but not SU(3) (a random phase per link, so row 2 is not
+    conj(row 0 x row 1)): the 16-bit hop must read all nine stored entries
+    instead of rebuilding row 2.  A rebuilt row would be off by the phase,
+    an O(1) error; the bound is that of SU(3) links."""
+    dims = (6, 4, 4, 8)
+    U = synth.random_gauge(dims, 31, 0.3)
+    rng = np.random.default_rng(5)
+    U = U * np.exp(1j * rng.uniform(-np.pi, np.pi, U.shape[:-2]))[..., None, None]
+    lat = Lattice(ctx, dims, U, 0.16, 0.02, -1)
+    psi = synth.random_spinor(dims, 8, nrhs=2)
+    for op in OPS:
+        out = zeros_dev(psi.shape)
+        dl.dl_apply_op(lat.h, op, tier, dev(psi), out, 2)
+        torch().cuda.synchronize()
+        e = rel(host(out), oracle_op(lat, op, psi))
+        log("  U(3) op", op, "rel err", e)
         assert e < tol, (op, e)
     lat.close()
 
