@@ -219,11 +219,11 @@ static void gauge_upload(dl_lattice* lat, const double* links, int on_device) {
   launch_pack_gauge(src, lat->dims[0], lat->dims[1], lat->dims[2], lat->dims[3], lat->gauge[0], lat->gauge[1],
                     lat->gauge[2], lat->gauge[3], flag.as<int>(), c->st);
   HIPCHECK(hipGetLastError());
-  int not_su3 = 1;
+  int not_su3 = TWO_ROW_16 | TWO_ROW_32;
   HIPCHECK(hipMemcpyAsync(&not_su3, flag.p, sizeof(int), hipMemcpyDeviceToHost, c->st));
   HIPCHECK(hipStreamSynchronize(c->st));
   stream_exit(c);
-  lat->su3 = not_su3 == 0;
+  lat->two_row = (TWO_ROW_16 | TWO_ROW_32) & ~not_su3;
   lat->gauge_set = true;
   clover_rebuild(lat);
 }

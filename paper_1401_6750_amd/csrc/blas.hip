@@ -538,7 +538,8 @@ __global__ __launch_bounds__(256) void k_pack_gauge(const double* src, int X, in
   const double2* u = (const double2*)src + (lex * 4 + mu) * 9;
   // a special unitary matrix has orthonormal rows and unit determinant, so
   // its row 2 is the complex conjugate of the cross product of rows 0 and 1:
-  // the identity the 16-bit hop uses; flag any link that misses it by > 1e-6
+  // the identity the two-row hops use; flag the storage classes for which a
+  // link misses it: by > 1e-6 (16-bit and FP32), by > 1e-7 (FP32)
   {
     double dev = 0.0;
     for (int k = 0; k < 3; ++k) {
@@ -548,7 +549,8 @@ __global__ __launch_bounds__(256) void k_pack_gauge(const double* src, int X, in
       const double im = ai.x * bj.y + ai.y * bj.x - (aj.x * bi.y + aj.y * bi.x);
       dev = fmax(dev, fmax(fabs(u[6 + k].x - re), fabs(u[6 + k].y + im)));
     }
-    if (!(dev <= 1e-6)) atomicOr(not_su3, 1);
+    if (!(dev <= 1e-6)) atomicOr(not_su3, TWO_ROW_16 | TWO_ROW_32);
+    else if (!(dev <= 1e-7)) atomicOr(not_su3, TWO_ROW_32);
   }
   // chunk rows [mu][parity][chunk][site] of vp sites (common.h)
   const long long row = (long long)(mu * 2 + par);

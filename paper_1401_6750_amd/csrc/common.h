@@ -167,6 +167,26 @@ template <class S, int L1, int H1, int L2, int H2> struct Chain6;
 #define DL_CHAIN6_ALL(S, INSTR) DL_CHAIN6_H1(S, INSTR, 0) DL_CHAIN6_H1(S, INSTR, 1)
 DL_CHAIN6_ALL(bf16s, "v_dot2_f32_bf16")
 DL_CHAIN6_ALL(f16s, "v_dot2_f32_f16")
+// Two chained products, x = a0 . b0 + a1 . b1, modifiers (L0, H0) on a0 and
+// (L1, H1) on a1, the same wait states at the end.
+template <class S, int L0, int H0, int L1, int H1> struct Chain2;
+#define DL_CHAIN2(S, INSTR, L0, H0, L1, H1)                                                                  \
+  template <> struct Chain2<S, L0, H0, L1, H1> {                                                             \
+    __device__ static inline float run(uint32_t a0, uint32_t a1, uint32_t b0, uint32_t b1) {                 \
+      float x;                                                                                               \
+      asm(INSTR " %0, %1, %3, 0" DL_NEG##L0##H0 "\n\t"                                                        \
+          INSTR " %0, %2, %4, %0" DL_NEG##L1##H1 "\n\t"                                                       \
+          "s_nop 2"                                                                                          \
+          : "=&v"(x)                                                                                         \
+          : "v"(a0), "v"(a1), "v"(b0), "v"(b1));                                                             \
+      return x;                                                                                              \
+    }                                                                                                        \
+  };
+DL_CHAIN2(bf16s, "v_dot2_f32_bf16", 0, 1, 1, 0)
+DL_CHAIN2(bf16s, "v_dot2_f32_bf16", 0, 0, 1, 1)
+DL_CHAIN2(f16s, "v_dot2_f32_f16", 0, 1, 1, 0)
+DL_CHAIN2(f16s, "v_dot2_f32_f16", 0, 0, 1, 1)
+#undef DL_CHAIN2
 #undef DL_CHAIN6_ALL
 #undef DL_CHAIN6_H1
 #undef DL_CHAIN6_L2
@@ -389,6 +409,12 @@ constexpr int LINK_ROW_NINTH_BWD = 26;
 // share three rows, word j = 6 (mu & 1) + entry at row 3 (mu >> 1) + j / 4,
 // component j % 4.
 constexpr int LINK_ROW_R12 = 28;
+// Bits of a lattice's two-row flag, set at upload when every link's row 2
+// equals conj(row 0 x row 1) (a special unitary matrix) to 1e-6 (16-bit
+// hops) or 1e-7 (FP32 hops, which then read the first three of a link's five
+// chunks)
+constexpr int TWO_ROW_16 = 1;
+constexpr int TWO_ROW_32 = 2;
 inline int link_rows(int prec) { return 8 * link_chunks(prec) + ((prec == PB16 || prec == PH16) ? 28 : 0); }
 
 template <class S>
@@ -413,6 +439,36 @@ __device__ inline void load_link<float>(const void* g, long vh, int mu, int par,
   const float4 w = at16<float4>(row16(g, (mu * 2 + par) * 5 + 4, vh), s);
   u[8] = {w.x, w.y};
 }
+// Row 2 of a special unitary matrix from rows 0 and 1: the rows are
+// orthonormal and the determinant is one, so u2_k = conj(u0_i u1_j - u0_j u1_i)
+// for (i, j, k) cyclic.
+template <class R>
+__device__ inline void su3_row2(cx<R> (&u)[9]) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int i = (k + 1) % 3, j = (k + 2) % 3;
+    const cx<R> a = u[i], b = u[3 + j], c = u[j], e = u[3 + i];
+    const R re = fmadd(a.re, b.re, fmadd(-a.im, b.im, fmadd(-c.re, e.re, c.im * e.im)));
+    const R im = fmadd(a.re, b.im, fmadd(a.im, b.re, fmadd(-c.re, e.im, -(c.im * e.re))));
+    u[6 + k] = mk<R>(re, -im);
+  }
+}
+// FP32 link from its first three chunks (entries 0-5: rows 0 and 1), row 2
+// rebuilt (links special unitary, TWO_ROW_32)
+__device__ inline void load_link_2row(const void* g, long vh, int mu, int par, long s, cx<float> (&u)[9]) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float4 w = at16<float4>(row16(g, (mu * 2 + par) * 5 + k, vh), s);
+    u[2 * k] = {w.x, w.y};
+    u[2 * k + 1] = {w.z, w.w};
+  }
+  su3_row2(u);
+}
+template <class R>
+__device__ inline void load_link_2row(const void*, long, int, int, long, cx<R> (&)[9]) {
+  static_assert(sizeof(R) == 0, "two-row links: FP32 unpacked hops only");
+}
+
 template <class S16>
 __device__ inline void load_link16(const void* g, long vh, int mu, int par, long s, cx<float> (&u)[9]) {
   const long long r0 = (mu * 2 + par) * 3;
@@ -486,8 +542,8 @@ struct SlotDesc {
   int rhs_begin;           // global index of this slot's rhs 0
   long long fo;            // site offset of rhs 0 in every batch field
   double bc;               // time-boundary factor
-  int su3;                 // 1: the links are special unitary (row 2 = conj(row 0 x row 1)),
-                           // the 16-bit hop reads the two-row copies
+  int two_row;             // TWO_ROW_* bits: the hops of that storage class read rows 0 and 1 of
+                           // the links and rebuild row 2 (links special unitary to its precision)
   const void* gauge[4];    // gauge field per precision
   const void* clv64;       // clover site matrices (FP64 class), or null: no clover term
   const void* clv32;       // clover site matrices (FP32 class, all other tiers), or null

@@ -174,13 +174,14 @@ template <> struct ProjSpec<3, false> { static constexpr int b0 = 2, c0 = 0, b1 
 // the group, unpacked arithmetic: FP32 / FP64 storage, and 16-bit storage with
 // the input factor d.  The link is loaded once; the spin projection comes
 // first and two colour vectors are multiplied.
-template <class S, int MU, bool FWD, bool HAS_D, bool INIT, int G>
+template <class S, int MU, bool FWD, bool HAS_D, bool INIT, bool TWO, int G>
 __device__ inline void hop(const void* gauge, long vp, int link_par, int link_site, int nb, typename Traits<S>::R sign,
                            const void* const (&ld)[G], int nr, const bool (&act)[G],
                            const cx<typename Traits<S>::R> (&d)[4], cx<typename Traits<S>::R> (&acc)[G][12]) {
   using R = typename Traits<S>::R;
   cx<R> u[9];
-  load_link<S>(gauge, vp, MU, link_par, link_site, u);
+  if constexpr (TWO) load_link_2row(gauge, vp, MU, link_par, link_site, u);
+  else load_link<S>(gauge, vp, MU, link_par, link_site, u);
   // 16-bit fields (this path: hops with an input factor): every member's
   // neighbour row is requested with the link, without a branch (an inactive
   // member reads an active member's row, `ld`), so the hop waits once for all
@@ -217,6 +218,28 @@ __device__ inline void hop(const void* gauge, long vp, int link_par, int link_si
     }
     reconstruct<MU, FWD, INIT>(acc[i], w0, w1, sign);
   }
+}
+
+// The eight hops of a site in the order x+, x-, y+, ..., t- (nbr: neighbour
+// sites in that order), unpacked arithmetic.  TWO (FP32 storage, SU(3)
+// links): rows 0 and 1 of each link (its first three chunks) are loaded and
+// row 2 rebuilt, 3 link loads per hop instead of 5.
+template <class S, bool HD, bool TWO, int G>
+__device__ __forceinline__ void hops_unpacked(const void* gauge, long vp, int p_out, int s, const int (&nbr)[8],
+                                              typename Traits<S>::R sp, typename Traits<S>::R sm,
+                                              const void* const (&ld)[G], int nr, const bool (&act)[G],
+                                              const cx<typename Traits<S>::R> (&d)[4],
+                                              cx<typename Traits<S>::R> (&acc)[G][12]) {
+  using R = typename Traits<S>::R;
+  const int q = 1 - p_out;
+  hop<S, 0, true, HD, true, TWO>(gauge, vp, p_out, s, nbr[0], (R)1, ld, nr, act, d, acc);
+  hop<S, 0, false, HD, false, TWO>(gauge, vp, q, nbr[1], nbr[1], (R)1, ld, nr, act, d, acc);
+  hop<S, 1, true, HD, false, TWO>(gauge, vp, p_out, s, nbr[2], (R)1, ld, nr, act, d, acc);
+  hop<S, 1, false, HD, false, TWO>(gauge, vp, q, nbr[3], nbr[3], (R)1, ld, nr, act, d, acc);
+  hop<S, 2, true, HD, false, TWO>(gauge, vp, p_out, s, nbr[4], (R)1, ld, nr, act, d, acc);
+  hop<S, 2, false, HD, false, TWO>(gauge, vp, q, nbr[5], nbr[5], (R)1, ld, nr, act, d, acc);
+  hop<S, 3, true, HD, false, TWO>(gauge, vp, p_out, s, nbr[6], sp, ld, nr, act, d, acc);
+  hop<S, 3, false, HD, false, TWO>(gauge, vp, q, nbr[7], nbr[7], sm, ld, nr, act, d, acc);
 }
 
 // ---- software-pipelined 16-bit hops ---------------------------------------
@@ -281,22 +304,24 @@ __device__ inline void hop_load12(HopWords<G>& h, const Link12& L, int m, long v
 }
 // Row 2 of an SU(3) link from rows 0 and 1: the rows are orthonormal and the
 // determinant is one, so row 2 is the complex conjugate of the cross product
-// of rows 0 and 1.  FP32 arithmetic on the stored values, rounded to the
-// storage format as a stored entry is.
+// of rows 0 and 1, u2_k = conj(u0_i u1_j - u0_j u1_i), (i, j, k) cyclic.
+// Each part is a chain of two dot2 products on the stored words (exact
+// products, FP32 sums; signs by input modifiers, the imaginary part against
+// the half-swapped words of row 1), rounded to the storage format as a stored
+// entry is:
+//   Re = (Re a_i, -Im a_i) . b_j + (-Re a_j, Im a_j) . b_i
+//   Im = a_j . swap(b_i) - a_i . swap(b_j)      (a = row 0, b = row 1)
 template <class S>
 __device__ inline void link_row2(uint32_t (&e)[9]) {
-  cx<float> a[3], b[3];
+  uint32_t sb[3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    a[k] = unpack2<S>(e[k]);
-    b[k] = unpack2<S>(e[3 + k]);
-  }
+  for (int k = 0; k < 3; ++k) sb[k] = swap16(e[3 + k]);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const int i = (k + 1) % 3, j = (k + 2) % 3;
-    const float re = fmaf(a[i].re, b[j].re, fmaf(-a[i].im, b[j].im, fmaf(-a[j].re, b[i].re, a[j].im * b[i].im)));
-    const float im = fmaf(a[i].re, b[j].im, fmaf(a[i].im, b[j].re, fmaf(-a[j].re, b[i].im, -(a[j].im * b[i].re))));
-    e[6 + k] = pack2<S>(mk<float>(re, -im));
+    const float re = Chain2<S, 0, 1, 1, 0>::run(e[i], e[j], e[3 + j], e[3 + i]);
+    const float im = Chain2<S, 0, 0, 1, 1>::run(e[j], e[i], sb[i], sb[j]);
+    e[6 + k] = pack2<S>(mk<float>(re, im));
   }
 }
 
@@ -621,17 +646,16 @@ __global__ __launch_bounds__(256) void k_dslash(DslashArgs a) {
     for (int i = 0; i < G; ++i) ld[i] = act[i] ? inb[i] : fa;
     if constexpr (Traits<S>::NC == 3 && !HD) {
       const int nbr[8] = {nxp, nxm, nyp, nym, nzp, nzm, ntp, ntm};
-      if (sd.su3) hops16<S, true>(gauge, vp, p_out, s, nbr, (float)sp, (float)sm, ld, act, acc);
+      if (sd.two_row & TWO_ROW_16) hops16<S, true>(gauge, vp, p_out, s, nbr, (float)sp, (float)sm, ld, act, acc);
       else hops16<S, false>(gauge, vp, p_out, s, nbr, (float)sp, (float)sm, ld, act, acc);
     } else {
-    hop<S, 0, true, HD, true>(gauge, vp, p_out, s, nxp, (R)1, ld, nr, act, d, acc);
-    hop<S, 0, false, HD, false>(gauge, vp, q, nxm, nxm, (R)1, ld, nr, act, d, acc);
-    hop<S, 1, true, HD, false>(gauge, vp, p_out, s, nyp, (R)1, ld, nr, act, d, acc);
-    hop<S, 1, false, HD, false>(gauge, vp, q, nym, nym, (R)1, ld, nr, act, d, acc);
-    hop<S, 2, true, HD, false>(gauge, vp, p_out, s, nzp, (R)1, ld, nr, act, d, acc);
-    hop<S, 2, false, HD, false>(gauge, vp, q, nzm, nzm, (R)1, ld, nr, act, d, acc);
-    hop<S, 3, true, HD, false>(gauge, vp, p_out, s, ntp, sp, ld, nr, act, d, acc);
-    hop<S, 3, false, HD, false>(gauge, vp, q, ntm, ntm, sm, ld, nr, act, d, acc);
+    const int nbr[8] = {nxp, nxm, nyp, nym, nzp, nzm, ntp, ntm};
+    if constexpr (Traits<S>::prec == P32) {
+      if (sd.two_row & TWO_ROW_32) hops_unpacked<S, HD, true>(gauge, vp, p_out, s, nbr, sp, sm, ld, nr, act, d, acc);
+      else hops_unpacked<S, HD, false>(gauge, vp, p_out, s, nbr, sp, sm, ld, nr, act, d, acc);
+    } else {
+      hops_unpacked<S, HD, false>(gauge, vp, p_out, s, nbr, sp, sm, ld, nr, act, d, acc);
+    }
     }
     dslash_epilogue<S, F, G>(a, sd, cf, clv, me, mf, mg, p_out, vp, s, off, r0, act, e, f, g, acc, nrm);
   }
@@ -856,7 +880,7 @@ __global__ __launch_bounds__(256) void k_dslash_blk(DslashArgs a) {
       // the hops in the tile kernel's order (x, y, z, t; per-site results are
       // the same bits: with SU(3) links row 2 is rebuilt from the stored rows
       // 0 and 1, the words the tile kernel reads from the two-row copies)
-      const bool two = sd.su3 != 0;
+      const bool two = (sd.two_row & TWO_ROW_16) != 0;
       hop_fill16<0, true>(h0, gauge, vp, p_out, s, pxp, Xh, nf.x);
       hop_fill16<0, true>(h1, gauge, vp, q, nxm, pxm, Xh, nbw.x);
       if (two) link_row2<S>(h0.e);

@@ -136,8 +136,9 @@ void launch_diff_norms(const SlotDesc* slots, int nslots, int total_units, const
                        const void* b, double* partial_diff, double* partial_b, hipStream_t st);
 
 // gauge packing: FP64 [t][z][y][x][mu][3][3] (device) -> four even-odd layouts;
-// *not_su3 (device, cleared by the caller) is set to 1 if a link's row 2 is not
-// conj(row 0 x row 1) to 1e-6
+// *not_su3 (device, cleared by the caller) gets the TWO_ROW_* bits of the
+// storage classes for which a link's row 2 is not conj(row 0 x row 1) to
+// their threshold
 void launch_pack_gauge(const double* src, int X, int Y, int Z, int T, void* g64, void* g32,
                        void* gb16, void* gh16, int* not_su3, hipStream_t st);
 

@@ -60,9 +60,9 @@ struct dl_lattice {
   long long V = 0, Vh = 0;
   void* gauge[4] = {nullptr, nullptr, nullptr, nullptr};
   bool gauge_set = false;
-  // every link special unitary to 1e-6 (checked at upload): the 16-bit hop may
-  // rebuild row 2 from rows 0 and 1
-  bool su3 = false;
+  // TWO_ROW_* bits (checked at upload): the hops of those storage classes
+  // rebuild row 2 of the links from rows 0 and 1
+  int two_row = 0;
   double kappa = 0, mu = 0;
   bool params_set = false;
   // clover term (c_sw = 0: none); its site matrices follow the gauge field,

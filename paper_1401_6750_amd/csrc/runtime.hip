@@ -337,7 +337,7 @@ struct Batch {
       d.rhs_begin = rb;
       d.fo = fo;
       d.bc = (double)L->bc;
-      d.su3 = L->su3 ? 1 : 0;
+      d.two_row = L->two_row;
       for (int p = 0; p < 4; ++p) d.gauge[p] = L->gauge[p];
       d.clv64 = L->csw != 0.0 ? L->clv64 : nullptr;
       d.clv32 = L->csw != 0.0 ? L->clv32 : nullptr;
