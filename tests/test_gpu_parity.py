@@ -122,6 +122,42 @@ def test_operators_storage_precision(ctx, tier, tol, dims, bc):
     lat.close()
 
 
+def test_two_row_links_follow_the_upload_check(ctx):
+    """Which hops rebuild row 2 of the links: the upload check sets it per
+    storage class (1e-6 for the 16-bit hops, 1e-7 for the FP32 ones).  Row 2
+    of every link is moved by d off the SU(3) identity; a hop that rebuilds it
+    never reads it, so its result is bit-identical to the unperturbed field's,
+    and a hop that reads it sees the change."""
+    dims = (6, 4, 4, 8)
+    U = synth.random_gauge(dims, 41, 0.3)
+    psi = synth.random_spinor(dims, 9, nrhs=2)
+
+    def hop(Uf, tier):
+        lat = Lattice(ctx, dims, Uf, 0.16, 0.02, -1)
+        out = zeros_dev(psi.shape)
+        dl.dl_apply_op(lat.h, dl.DL_OP_HOP, tier, dev(psi), out, 2)
+        torch().cuda.synchronize()
+        got = host(out)
+        want = oracle_op(lat, dl.DL_OP_HOP, psi)
+        lat.close()
+        return got, want
+
+    def moved(d):
+        V = U.copy()
+        V[..., 2, :] += d * (1 + 1j)
+        return V
+
+    b16, _ = hop(U, dl.DL_TIER_LP_BF16)
+    b32, _ = hop(U, dl.DL_TIER_HP_FP32)
+    for d, rebuilt16, rebuilt32 in ((3e-8, True, True), (3e-7, True, False), (1e-3, False, False)):
+        g16, w16 = hop(moved(d), dl.DL_TIER_LP_BF16)
+        g32, w32 = hop(moved(d), dl.DL_TIER_HP_FP32)
+        log("row 2 moved by", d, "bf16 rel", rel(g16, w16), "fp32 rel", rel(g32, w32))
+        assert np.array_equal(g16, b16) == rebuilt16, d
+        assert np.array_equal(g32, b32) == rebuilt32, d
+        assert rel(g16, w16) < 1.6e-2 and rel(g32, w32) < (5e-7 if not rebuilt32 else 5e-7 + 4 * d)
+
+
 @pytest.mark.parametrize("tier,tol", [(dl.DL_TIER_LP_FP16, 2e-3), (dl.DL_TIER_LP_BF16, 1.6e-2)])
 def test_operators_16bit_links_not_special_unitary(ctx, tier, tol):
     """Links in U(3) but not SU(3) (a random phase per link, so row 2 is not
