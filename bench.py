@@ -459,7 +459,7 @@ def main() -> int:
                     help="run only the profiled LP pass (for rocprofv3 counter runs)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; the per-GPU share of a multi-GPU run is the "
+        print("bench.py: the library runs on one GPU only; the per-GPU share of a multi-GPU run is the "
               "N=1 workload (sources shard across GPUs with one final reduction of the projected loops)",
               file=sys.stderr)
         return 2
