@@ -113,6 +113,13 @@ def test_link_generator_is_special_unitary():
     # loose check that the eigenphase spread matches eps = 0.3
     ang = np.angle(np.linalg.eigvals(U)).ravel()
     assert 0.1 < ang.std() < 0.5
+    # the identity the library's two-row link reads rely on (row 2 = conj(row 0 x
+    # row 1)) holds far inside its upload thresholds (1e-6 / 1e-7), so the
+    # synthetic workloads run the two-row hops; a U(1) phase per link breaks it
+    row2 = np.cross(U[..., 0, :], U[..., 1, :]).conj()
+    assert np.abs(row2 - U[..., 2, :]).max() < 1e-13
+    Up = U * np.exp(0.5j)
+    assert np.abs(np.cross(Up[..., 0, :], Up[..., 1, :]).conj() - Up[..., 2, :]).max() > 0.1
 
 
 @pytest.mark.parametrize("mu", [0.05, -0.02])
