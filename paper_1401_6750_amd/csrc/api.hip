@@ -205,6 +205,7 @@ static void clover_rebuild(dl_lattice* lat) {
 
 static void gauge_upload(dl_lattice* lat, const double* links, int on_device) {
   dl_ctx* c = lat->ctx;
+  lat->two_row = 0;   // nine-entry reads unless this upload's check passes
   stream_enter(c);
   const size_t bytes = (size_t)lat->V * 4 * 9 * 16;
   DevBuf stage;

@@ -543,8 +543,8 @@ __global__ __launch_bounds__(256) void k_pack_gauge(const double* src, int X, in
   {
     double dev = 0.0;
     for (int k = 0; k < 3; ++k) {
-      const int i = (k + 1) % 3, j = (k + 2) % 3;
-      const double2 ai = u[i], aj = u[j], bi = u[3 + i], bj = u[3 + j];
+      const int ki = (k + 1) % 3, kj = (k + 2) % 3;
+      const double2 ai = u[ki], aj = u[kj], bi = u[3 + ki], bj = u[3 + kj];
       const double re = ai.x * bj.x - ai.y * bj.y - (aj.x * bi.x - aj.y * bi.y);
       const double im = ai.x * bj.y + ai.y * bj.x - (aj.x * bi.y + aj.y * bi.x);
       dev = fmax(dev, fmax(fabs(u[6 + k].x - re), fabs(u[6 + k].y + im)));
